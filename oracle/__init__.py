@@ -1,0 +1,175 @@
+"""CPU oracle for HyperBall (test infrastructure).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The HIP library never loads it, and the
+two share no code: the oracle is a plain single-threaded C implementation of
+Algorithms 1 and 2 of the paper (``hb_oracle.c``), wrapped here with ctypes.
+
+Parity status of every function (pins live in ``tests/test_oracle_*.py``):
+
+* ``hash64``/``rho``/``add``  - pinned: published SplitMix64 outputs, the
+  paper's rho+ example, uniformity of index and rank.
+* ``register_sum``           - pinned: Python's correctly rounded int->float.
+* ``size``                   - pinned: closed forms (constant registers,
+  single register), exact small-set regime, statistical bias/RSD vs Sec. 4.1.
+* ``run``                    - pinned: registers equal the HyperLogLog state of
+  breadth-first balls (computed with scipy), termination count, closed-form
+  accumulators on cycles, paths, stars, complete graphs in the exact regime.
+* ``node``                   - pinned: agrees with ``run`` and with closed forms.
+* ``finalize``               - pinned: closed forms on the same graphs.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hb_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle (gcc, -O2, no FMA contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        vp, i64, u64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int
+        L.hbo_hash.argtypes = [u64, u64]
+        L.hbo_hash.restype = u64
+        L.hbo_rho.argtypes = [u64, ci]
+        L.hbo_rho.restype = ci
+        L.hbo_add.argtypes = [vp, ci, u64, u64]
+        L.hbo_add.restype = None
+        L.hbo_alpha.argtypes = [ci]
+        L.hbo_alpha.restype = ctypes.c_double
+        L.hbo_register_sum.argtypes = [vp, ci]
+        L.hbo_register_sum.restype = ctypes.c_double
+        L.hbo_size.argtypes = [vp, ci]
+        L.hbo_size.restype = ctypes.c_double
+        L.hbo_run.argtypes = [i64, vp, vp, ci, u64, ci, vp, vp, vp, vp, vp]
+        L.hbo_run.restype = ci
+        L.hbo_finalize.argtypes = [i64, vp, ci, vp, vp, vp, vp, vp, vp]
+        L.hbo_finalize.restype = None
+        L.hbo_node.argtypes = [i64, vp, vp, ci, u64, i64, ci, vp, vp, vp, vp, vp]
+        L.hbo_node.restype = ci
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def hash64(x: int, seed: int) -> int:
+    return _load().hbo_hash(x, seed)
+
+
+def rho(h: int, b: int) -> int:
+    return _load().hbo_rho(h, b)
+
+
+def alpha(b: int) -> float:
+    return _load().hbo_alpha(b)
+
+
+def new_counter(b: int) -> np.ndarray:
+    return np.zeros(1 << b, dtype=np.uint8)
+
+
+def add(M: np.ndarray, b: int, item: int, seed: int) -> None:
+    assert M.dtype == np.uint8 and M.flags.c_contiguous and M.shape == (1 << b,)
+    _load().hbo_add(_p(M), b, item, seed)
+
+
+def counter_of(items, b: int, seed: int) -> np.ndarray:
+    M = new_counter(b)
+    for x in items:
+        add(M, b, int(x), seed)
+    return M
+
+
+def register_sum(M: np.ndarray, b: int) -> float:
+    M = np.ascontiguousarray(M, dtype=np.uint8)
+    return _load().hbo_register_sum(_p(M), b)
+
+
+def size(M: np.ndarray, b: int) -> float:
+    M = np.ascontiguousarray(M, dtype=np.uint8)
+    return _load().hbo_size(_p(M), b)
+
+
+def _csr(offsets, indices):
+    o = np.ascontiguousarray(offsets, dtype=np.int64)
+    i = np.ascontiguousarray(indices, dtype=np.int32)
+    if i.size == 0:
+        i = np.zeros(1, dtype=np.int32)
+    return o, i
+
+
+def run(offsets, indices, b: int, seed: int, max_passes: int = 0):
+    """Algorithm 2 to stabilisation (or max_passes passes).
+
+    Returns dict(regs (n, p) uint8, S, H float64, nmod int64 per pass, passes).
+    """
+    o, i = _csr(offsets, indices)
+    n = o.shape[0] - 1
+    p = 1 << b
+    regs = np.zeros((max(n, 1), p), dtype=np.uint8)
+    S = np.zeros(max(n, 1))
+    H = np.zeros(max(n, 1))
+    cap = max_passes if max_passes > 0 else n + 2
+    nmod = np.zeros(cap + 1, dtype=np.int64)
+    passes = ctypes.c_int(0)
+    rc = _load().hbo_run(n, _p(o), _p(i), b, seed, max_passes, _p(regs), _p(S), _p(H), _p(nmod),
+                         ctypes.byref(passes))
+    if rc != 0:
+        raise RuntimeError("oracle run failed")
+    t = passes.value
+    return dict(regs=regs[:n], S=S[:n], H=H[:n], nmod=nmod[:t].copy(), passes=t)
+
+
+def finalize(regs: np.ndarray, b: int, S: np.ndarray, H: np.ndarray):
+    """Closeness, Lin, harmonic and coreachable-set size per node."""
+    n = regs.shape[0]
+    regs = np.ascontiguousarray(regs, dtype=np.uint8)
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    out = [np.zeros(max(n, 1)) for _ in range(4)]
+    _load().hbo_finalize(n, _p(regs), b, _p(S), _p(H), *(_p(a) for a in out))
+    clo, lin, harm, core = (a[:n] for a in out)
+    return dict(closeness=clo, lin=lin, harmonic=harm, coreach=core)
+
+
+def node(offsets, indices, b: int, seed: int, x: int, radius: int = -1):
+    """Per-node evaluation from breadth-first balls.
+
+    Returns dict(regs (registers of B(x, radius), or of the reachable set when
+    radius < 0), S, H, last_change, ecc).
+    """
+    o, i = _csr(offsets, indices)
+    n = o.shape[0] - 1
+    regs = new_counter(b)
+    S = ctypes.c_double(0.0)
+    H = ctypes.c_double(0.0)
+    last = ctypes.c_int(0)
+    ecc = ctypes.c_int(0)
+    rc = _load().hbo_node(n, _p(o), _p(i), b, seed, x, radius, _p(regs), ctypes.byref(S),
+                          ctypes.byref(H), ctypes.byref(last), ctypes.byref(ecc))
+    if rc != 0:
+        raise RuntimeError("oracle node evaluation failed")
+    return dict(regs=regs, S=S.value, H=H.value, last_change=last.value, ecc=ecc.value)

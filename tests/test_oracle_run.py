@@ -1,0 +1,195 @@
+"""Pins for the oracle's HyperBall loop (Sec. 4.2 Algorithm 2, Sec. 5, Sec. 3).
+
+The recurrence is pinned to its definition: after t passes, the counter of x
+is exactly the HyperLogLog state of the ball B(x, t), with balls computed by
+scipy's breadth-first shortest paths (independent of the oracle).  The
+accumulators and centralities are pinned to exact distance sums on graphs in
+the exact-counting regime (p = 2^16, at most ~48 nodes), and to closed forms
+on cycles, paths, stars and complete graphs.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.sparse import csr_matrix
+from scipy.sparse.csgraph import shortest_path
+
+
+def bfs_dist(offsets, indices):
+    n = offsets.shape[0] - 1
+    A = csr_matrix((np.ones(indices.shape[0]), indices, offsets), shape=(n, n))
+    return shortest_path(A, method="D", directed=True, unweighted=True)
+
+
+def ball_counters(orc, D, b, seed, t):
+    n = D.shape[0]
+    out = np.zeros((n, 1 << b), dtype=np.uint8)
+    for x in range(n):
+        out[x] = orc.counter_of(np.flatnonzero(D[x] <= t), b, seed)
+    return out
+
+
+def small_graphs(gg):
+    yield "path", gg.directed_path(9)
+    yield "cycle", gg.directed_cycle(11)
+    yield "star", gg.star(10)
+    yield "grid", gg.grid(4, 5)
+    yield "empty", gg.empty(6)
+    for s in range(6):
+        n = [12, 20, 33, 40, 50, 64][s]
+        m = [10, 30, 60, 120, 80, 400][s]
+        yield f"rand{s}", gg.random_digraph(n, m, seed=100 + s, self_loops=(s % 2 == 1))
+    yield "rmat6", gg.rmat(6, 4, seed=5, transpose=True)
+    yield "rmat6u", gg.rmat(6, 4, seed=6, directed=False)
+
+
+@pytest.mark.parametrize("b", [4, 5, 7])
+def test_counters_are_hll_of_balls(orc, gg, b):
+    seed = 42 + b
+    for name, (o, i) in small_graphs(gg):
+        D = bfs_dist(o, i)
+        full = orc.run(o, i, b, seed)
+        T = full["passes"]
+        for t in range(1, T + 1):
+            r = orc.run(o, i, b, seed, max_passes=t)
+            assert np.array_equal(r["regs"], ball_counters(orc, D, b, seed, t)), (name, t)
+        # radius 0 through the per-node path: {x}
+        for x in range(min(5, D.shape[0])):
+            assert np.array_equal(orc.node(o, i, b, seed, x, radius=0)["regs"],
+                                  orc.counter_of([x], b, seed))
+
+
+@pytest.mark.parametrize("b", [4, 6])
+def test_termination_count(orc, gg, b):
+    # Algorithm 2 stops after the first pass that changes no counter; that
+    # pass is counted.  From balls: passes = 1 + max_x L(x), where L(x) is
+    # the last t with HLL(B(x,t)) != HLL(B(x,t-1)).
+    seed = 9
+    for name, (o, i) in small_graphs(gg):
+        D = bfs_dist(o, i)
+        n = D.shape[0]
+        finite = D[np.isfinite(D)]
+        diam = int(finite.max()) if finite.size else 0
+        prev = ball_counters(orc, D, b, seed, 0)
+        L = np.zeros(n, dtype=int)
+        for t in range(1, diam + 1):
+            cur = ball_counters(orc, D, b, seed, t)
+            L[(cur != prev).any(axis=1)] = t
+            prev = cur
+        r = orc.run(o, i, b, seed)
+        expect = 1 + (int(L.max()) if n else 0)
+        assert r["passes"] == expect, name
+        assert r["passes"] <= diam + 1
+        assert r["nmod"][-1] == 0 and (r["nmod"][:-1] > 0).all()
+        # the per-node evaluation reports the same L(x)
+        for x in range(n):
+            assert orc.node(o, i, b, seed, x)["last_change"] == L[x]
+
+
+def test_node_evaluation_matches_run_bitwise(orc, gg):
+    for b in (4, 6, 8):
+        for name, (o, i) in small_graphs(gg):
+            r = orc.run(o, i, b, 77)
+            n = o.shape[0] - 1
+            for x in range(n):
+                q = orc.node(o, i, b, 77, x)
+                assert q["S"] == r["S"][x] and q["H"] == r["H"][x], (name, x)
+                assert np.array_equal(q["regs"], r["regs"][x])
+
+
+def exact_seed(orc, n, b=16):
+    # a seed for which the n node ids fill n distinct registers
+    for seed in range(1000):
+        if np.count_nonzero(orc.counter_of(range(n), b, seed)) == n:
+            return seed
+    raise AssertionError("no collision-free seed")
+
+
+def test_accumulators_match_exact_distances(orc, gg):
+    # With p = 2^16 and <= 64 nodes, counters count exactly (no collisions),
+    # so S ~ sum of distances, H ~ sum of reciprocal distances, coreach ~
+    # reachable-set size (Sec. 5), up to the linear-counting bias k^2/2p.
+    b = 16
+    for name, (o, i) in small_graphs(gg):
+        n = o.shape[0] - 1
+        seed = exact_seed(orc, n)
+        D = bfs_dist(o, i)
+        r = orc.run(o, i, b, seed)
+        f = orc.finalize(r["regs"], b, r["S"], r["H"])
+        for x in range(n):
+            d = D[x][np.isfinite(D[x]) & (D[x] > 0)]
+            S, H, R = d.sum(), (1.0 / d).sum(), 1 + d.size
+            tol = 2e-3 * max(1.0, S)
+            assert abs(r["S"][x] - S) < tol, (name, x)
+            assert abs(r["H"][x] - H) < 2e-3 * max(1.0, H), (name, x)
+            assert abs(f["coreach"][x] - R) < 2e-3 * R, (name, x)
+            if d.size == 0:
+                assert r["S"][x] == 0.0 and f["closeness"][x] == 0.0 and f["lin"][x] == 1.0
+            else:
+                assert abs(f["closeness"][x] - 1.0 / S) < 3e-3 / S
+                assert abs(f["lin"][x] - R * R / S) < 6e-3 * R * R / S
+            assert f["harmonic"][x] == r["H"][x]
+
+
+def test_closed_forms(orc, gg):
+    b = 16
+    # directed cycle C_n: every node reaches the n-1 others at distances 1..n-1
+    n = 24
+    o, i = gg.directed_cycle(n)
+    r = orc.run(o, i, b, exact_seed(orc, n))
+    f = orc.finalize(r["regs"], b, r["S"], r["H"])
+    Hn = sum(1.0 / k for k in range(1, n))
+    assert np.allclose(r["S"], n * (n - 1) / 2, rtol=3e-3)
+    assert np.allclose(r["H"], Hn, rtol=3e-3)
+    assert np.allclose(f["coreach"], n, rtol=3e-3)
+    assert r["passes"] == n  # distances up to n-1, plus the unchanged pass
+    # complete digraph K_n: S = H = n-1, two passes
+    n = 30
+    o, i = gg.complete(n)
+    r = orc.run(o, i, b, exact_seed(orc, n))
+    assert np.allclose(r["S"], n - 1, rtol=3e-3) and np.allclose(r["H"], n - 1, rtol=3e-3)
+    assert r["passes"] == 2
+    # undirected star: centre S = H = n-1; leaf S = 2n-3, H = 1 + (n-2)/2
+    n = 20
+    o, i = gg.star(n)
+    r = orc.run(o, i, b, exact_seed(orc, n))
+    assert abs(r["S"][0] - (n - 1)) < 3e-3 * n and abs(r["H"][0] - (n - 1)) < 3e-3 * n
+    assert np.allclose(r["S"][1:], 2 * n - 3, rtol=3e-3)
+    assert np.allclose(r["H"][1:], 1 + (n - 2) / 2, rtol=3e-3)
+    # directed path 0->1->...->n-1: node 0 has S = n(n-1)/2, the sink S = 0
+    n = 16
+    o, i = gg.directed_path(n)
+    r = orc.run(o, i, b, exact_seed(orc, n))
+    f = orc.finalize(r["regs"], b, r["S"], r["H"])
+    assert abs(r["S"][0] - n * (n - 1) / 2) < 3e-3 * n * n
+    assert r["S"][-1] == 0.0 and f["closeness"][-1] == 0.0 and f["lin"][-1] == 1.0
+
+
+def test_graph_without_arcs(orc, gg):
+    for b in (4, 8):
+        o, i = gg.empty(7)
+        r = orc.run(o, i, b, 1)
+        assert r["passes"] == 1 and (r["S"] == 0).all() and (r["H"] == 0).all()
+        f = orc.finalize(r["regs"], b, r["S"], r["H"])
+        p = 1 << b
+        assert np.all(f["coreach"] == p * math.log(p / (p - 1)))
+    o, i = gg.empty(0)
+    assert orc.run(o, i, 4, 1)["passes"] == 1
+
+
+def test_invariants_on_rmat(orc, gg):
+    # Registers never decrease; a pass that reports a change changed some
+    # register; once a pass changes nothing, further passes change nothing.
+    o, i = gg.rmat(9, 8, seed=11, transpose=True)
+    b = 5
+    full = orc.run(o, i, b, 3)
+    prev = orc.run(o, i, b, 3, max_passes=1)["regs"]
+    for t in range(2, full["passes"] + 3):
+        cur = orc.run(o, i, b, 3, max_passes=t)["regs"]
+        assert (cur >= prev).all()
+        nchg = int((cur != prev).any(axis=1).sum())
+        if t <= full["passes"]:
+            assert nchg == full["nmod"][t - 1]
+        else:
+            assert nchg == 0
+        prev = cur
