@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""HyperBall benchmark on one MI355X.
+
+Workload (default): directed R-MAT, scale 24 (16,777,216 nodes), edge factor
+16, (a,b,c,d) = (.57,.19,.19,.05), generator seed 3, nodes relabelled by a
+seeded permutation, self-loops and duplicates removed, run on the transposed
+CSR (int64 offsets, int32 indices), log2m = 7 (128 registers), hash seed 42,
+modified-node frontier on.
+
+One step = one whole HyperBall computation on that graph: reset (counters of
+radius 0), passes until a pass changes no counter, and the centralities
+written to device memory.  The graph is resident in HBM before timing starts.
+
+Printed (one JSON line): edge visits per second per iteration (arcs scanned
+per pass, summed over the passes of a step, divided by the step time), the
+roofline of the dominant kernel (the expand kernel: algorithmic bytes per
+launch / mean launch time from HIP events, against 8 TB/s), and the CPU
+oracle timed on one pass of the same graph.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "edge visits/s per iteration + % HBM peak (R-MAT s24); batched graphs/s vs plain"
+
+WORKLOADS = {
+    "rmat-s24": dict(scale=24, ef=16, gen_seed=3, log2m=7, offsets=64),
+    "rmat-s20": dict(scale=20, ef=16, gen_seed=2, log2m=6, offsets=32),
+    "rmat-s10u": dict(scale=10, ef=8, gen_seed=1, log2m=4, offsets=32, undirected=True),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_graph(w):
+    import graphgen
+
+    t = time.time()
+    if w.get("undirected"):
+        off, idx = graphgen.rmat(w["scale"], w["ef"], seed=w["gen_seed"], directed=False)
+    else:
+        off, idx = graphgen.rmat(w["scale"], w["ef"], seed=w["gen_seed"], transpose=True, relabel=True)
+    log(f"graph: n={len(off) - 1} m={len(idx)} generated in {time.time() - t:.1f}s")
+    return off, idx
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ("hb_kernels.hip", "hb_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1308_2144_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def pass_bytes(ps, n, m, p, n_hrows):
+    """Algorithmic HBM bytes of one pass's expand kernel.
+
+    offsets 8 B/row, successor ids 4 B/arc, one p-byte counter per gathered
+    successor, own counter of every loaded row, every written counter, S/H/E
+    read+write for changed rows (48 B), both frontier bitmaps once (n/8 B
+    each).  The heavy rows' own loads are done by the merge kernel and are
+    left out."""
+    return (8 * n + 4 * m + p * ps["counters_gathered"] + p * max(ps["rows_loaded"] - n_hrows, 0)
+            + p * ps["rows_written"] + 48 * ps["rows_changed"] + 2 * (n // 8))
+
+
+def cpu_baseline(w, seed):
+    """The oracle on a bounded sample of the workload: pass 0 (every arc
+    gathered) of the same generator at scale-2 (a quarter of the nodes and
+    arcs), single-threaded.  Edge visits per second are comparable because a
+    pass costs the same per arc; the full scale-24 pass takes ~100 s."""
+    import graphgen
+    import oracle
+
+    scale = max(w["scale"] - 2, 8)
+    sw = dict(w, scale=scale)
+    off, idx = make_graph(sw)
+    t = time.time()
+    r = oracle.run(off, idx, w["log2m"], seed, max_passes=1)
+    dt = time.time() - t
+    m = len(idx)
+    return {"value": m / dt, "unit": "edge visits/s", "cores": 1, "kind": "oracle",
+            "sample": f"pass 0 of R-MAT scale {scale} (same generator and options, n={len(off) - 1}, "
+                      f"m={m}, log2m={w['log2m']}), single-threaded C oracle: {dt:.1f}s",
+            "seconds": round(dt, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat-s24", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--light-max", type=int, default=0)
+    ap.add_argument("--heavy-min", type=int, default=0)
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--frontier", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_1308_2144_amd as hb
+
+    w = WORKLOADS[args.workload]
+    off, idx = make_graph(w)
+    n, m = len(off) - 1, len(idx)
+    p = 1 << w["log2m"]
+    seed = 42
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    o_d = torch.from_numpy(off.astype(np.int64 if w["offsets"] == 64 else np.int32)).to(dev)
+    i_d = torch.from_numpy(idx).to(dev)
+    outs = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(4)]
+    stream = torch.cuda.current_stream().cuda_stream
+    g = hb.HyperBall(o_d, i_d, w["log2m"], seed, stream=stream, timing=1, frontier=args.frontier,
+                     light_max=args.light_max, heavy_min=args.heavy_min, chunk=args.chunk)
+    st0 = g.stats()
+    log(f"rows: medium={st0['medium_rows']} heavy={st0['heavy_rows']} chunks={st0['heavy_chunks']}")
+
+    def step():
+        g.reset(seed)
+        passes = g.run()
+        hb.hb_centralities(g._ctx, *outs, True)
+        return passes
+
+    for i in range(args.warmup):
+        passes = step()
+        log(f"warmup {i}: {passes} passes")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step_passes = []
+    exp_ms, exp_bytes, launches = 0.0, 0, 0
+    first = None
+    for k in range(args.steps):
+        passes = step()
+        step_passes.append(passes)
+        infos = [g.pass_stats(t) for t in range(passes)]
+        for ps in infos:
+            exp_ms += ps["expand_ms"]
+            exp_bytes += pass_bytes(ps, n, m, p, st0["heavy_rows"])
+            launches += 1
+        if first is None:
+            first = infos
+        log(f"step {k}: {passes} passes")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = 1e3 * dt / args.steps
+    visits = m * sum(step_passes)
+    value = visits / dt
+
+    for t, ps in enumerate(first):
+        log(f"  pass {t:2d}: gathered={ps['counters_gathered']:>11d} loaded={ps['rows_loaded']:>9d} "
+            f"written={ps['rows_written']:>9d} changed={ps['rows_changed']:>9d} "
+            f"expand={ps['expand_ms']:.3f}ms merge={ps['merge_ms']:.3f}ms "
+            f"{pass_bytes(ps, n, m, p, st0['heavy_rows']) / (ps['expand_ms'] * 1e6):.0f} GB/s")
+
+    mean_ms = exp_ms / launches
+    achieved = exp_bytes / launches / (mean_ms * 1e-3) / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "expand_traffic_rmat_s24.json")
+    if os.path.exists(tfile) and args.workload == "rmat-s24":
+        tj = json.load(open(tfile))
+        if tj.get("kernel_hash") == kernel_hash():
+            traffic = tj.get("bytes_per_launch")
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "k_expand", "launches": launches, "mean_launch_ms": round(mean_ms, 4),
+            "algorithmic_bytes_per_launch": exp_bytes // launches}
+    p0 = first[0]
+    out = {
+        "metric": METRIC, "value": value, "unit": "edge visits/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "m": m, "log2m": w["log2m"], "p": p,
+                   "passes": step_passes[0], "frontier": bool(args.frontier), "hash_seed": seed,
+                   "generator": "rmat a=.57 b=.19 c=.19 d=.05, gen seed %d" % w["gen_seed"],
+                   "offsets": f"int{w['offsets']}"},
+        "first_pass": {"ms": p0["expand_ms"] + p0["merge_ms"],
+                       "edge_visits_per_s": m / ((p0["expand_ms"] + p0["merge_ms"]) * 1e-3),
+                       "GBps": pass_bytes(p0, n, m, p, st0["heavy_rows"]) / (p0["expand_ms"] * 1e6)},
+        "roofline": roof,
+    }
+    g.close()
+    del o_d, i_d, outs
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle pass 0 ...")
+        del off, idx
+        out["cpu_baseline"] = cpu_baseline(w, seed)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

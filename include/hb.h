@@ -1,0 +1,182 @@
+/*
+ * hb.h - C ABI of the MI355X HyperBall library (libhb.so).
+ *
+ * HyperBall (Boldi & Vigna, "In-Core Computation of Geometric Centralities
+ * with HyperBall") keeps one HyperLogLog counter per node (Sec. 4.1,
+ * Algorithm 1) and repeatedly replaces every counter by the register-wise
+ * maximum of itself and the counters of its successors (the ball recurrence
+ * of Sec. 4.2, Algorithm 2) until no counter changes.  While it runs it
+ * accumulates, per node, sum_t t*(|B_t|-|B_{t-1}|) and
+ * sum_t (|B_t|-|B_{t-1}|)/t (Sec. 5), from which closeness, Lin's and
+ * harmonic centrality follow (Sec. 3).
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns an hb_status; nothing throws across the ABI.
+ *     On a non-OK status hb_last_error() describes the failure (per thread).
+ *   - Balls grow along the arcs of the CSR that is passed in: row v lists the
+ *     arcs v->w.  Centralities on incoming distances (Sec. 3, Sec. 5) need the
+ *     transposed graph; undirected graphs pass a symmetric CSR.
+ *   - Counters are p = 2^log2m byte-wide registers, node-major (register j of
+ *     node v at byte v*p + j), 4 <= log2m <= 16.
+ *   - Hash of node v: SplitMix64 finalizer of v + (seed+1)*0x9E3779B97F4A7C15;
+ *     register index = leftmost log2m bits; value = rho+ of the remaining
+ *     bits (65-log2m if they are all zero); empty registers hold 0.
+ *   - Estimator: alpha_p p^2 / sum_j 2^-M[j] with the register sum exact and
+ *     rounded once; linear counting p*ln(p/V) when that estimate is <= 5p/2
+ *     and V > 0 registers are zero.  alpha_p = 0.673, 0.697, 0.709 for
+ *     p = 16, 32, 64, else 0.7213/(1+1.079/p).
+ *   - Pass t (from 0) turns counters of radius t into radius t+1 and adds
+ *     (t+1)*delta to S[v] and delta/(t+1) to H[v], delta = E(new) - E(old).
+ *   - All device work runs on the stream given at init (NULL: the default
+ *     stream).  Calls that return host data synchronise that stream.
+ *   - One context must not be used by two threads at once.
+ */
+#ifndef HB_H
+#define HB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HB_OK = 0,
+  HB_EINVAL = -1,  /* bad argument: log2m range, malformed CSR, NULL pointer */
+  HB_ENOMEM = -2,  /* device or host allocation failed, or over a memory budget */
+  HB_EDEVICE = -3, /* a HIP call failed; the message names it */
+  HB_ESTATE = -4   /* call not valid in the context's state (failed / freed / busy) */
+} hb_status;
+
+typedef struct hb_ctx hb_ctx;
+
+/* A graph in compressed sparse rows.
+ *   offsets: n+1 entries, offsets[0] = 0, nondecreasing, offsets[n] = m;
+ *            int32 or int64 as offsets_bits says (32 or 64).
+ *   indices: m int32 entries in [0, n); row v is indices[offsets[v]..offsets[v+1]).
+ *   on_device = 0: host pointers, copied at hb_init and not retained.
+ *   on_device = 1: device pointers, BORROWED: they must stay valid and
+ *            unchanged until hb_free.  int32 offsets are widened into a
+ *            library-owned copy; int64 offsets and indices are used in place. */
+typedef struct {
+  int64_t n;
+  int64_t m;
+  const void* offsets;
+  int32_t offsets_bits;
+  const int32_t* indices;
+  int32_t on_device;
+} hb_csr;
+
+/* Tuning and behaviour switches; hb_default_options fills the defaults.
+ *   frontier   1: gather only successors whose counter changed in the
+ *              previous pass (exact: an unchanged successor's counter is
+ *              already contained in the node's own); 0: gather every arc.
+ *   light_max  rows with at most this many arcs are handled by one lane group.
+ *   heavy_min  rows with at least this many arcs are split into chunks of
+ *              `chunk` arcs reduced by separate workgroups; rows in between
+ *              are handled by a whole wavefront.  (<= 0: library default.)
+ *   validate   1: check the CSR (offsets monotone and bounded, indices in
+ *              range) at init and fail with HB_EINVAL if it is malformed.
+ *   timing     1: time every pass's kernels with HIP events (hb_pass_info). */
+typedef struct {
+  int32_t frontier;
+  int32_t light_max;
+  int32_t heavy_min;
+  int32_t chunk;
+  int32_t validate;
+  int32_t timing;
+} hb_options;
+
+void hb_default_options(hb_options* opt);
+
+/* Sec. 4.2 / Algorithm 2 set-up: allocates device state for g, feeds every
+ * counter its own node (counter of radius 0), zeroes the accumulators.
+ * log2m in [4, 16]; seed selects the hash.  opt may be NULL (defaults).
+ * stream: a hipStream_t (e.g. torch.cuda.current_stream().cuda_stream) or NULL.
+ * On success *out owns the context; release it with hb_free. */
+hb_status hb_init(hb_ctx** out, const hb_csr* g, int32_t log2m, uint64_t seed,
+                  const hb_options* opt, void* stream);
+
+/* Restart the computation on the same graph with another hash seed, without
+ * reallocating: counters back to radius 0, accumulators to zero, pass 0. */
+hb_status hb_reset(hb_ctx* c, uint64_t seed);
+
+/* One synchronous pass of Algorithm 2 (all new counters computed from the
+ * old ones, then applied together), with the Sec. 5 accumulation fused in.
+ * *n_modified (nullable) receives the number of counters that changed.  The
+ * pass that changes nothing marks the context converged; later calls are
+ * no-ops that report 0.  Synchronises the stream (one 8 KB readback). */
+hb_status hb_iterate(hb_ctx* c, int64_t* n_modified);
+
+/* Iterate until a pass changes no counter (that pass included) or until
+ * max_passes passes have run in total (max_passes <= 0: no cap).
+ * *passes (nullable) receives the number of passes run so far. */
+hb_status hb_run(hb_ctx* c, int32_t max_passes, int32_t* passes);
+
+/* Sec. 3 / Sec. 5 finalisation, per node v:
+ *   coreach[v]   = size estimate of v's counter (coreachable set on G^T),
+ *   closeness[v] = S == 0 ? 0 : 1/S,
+ *   lin[v]       = S == 0 ? 1 : coreach^2 / S,
+ *   harmonic[v]  = H,
+ * where S = sum of distance-weighted increments and H = sum of reciprocal
+ * ones.  Each output holds n doubles; any of them may be NULL.  dst_on_device
+ * says whether the pointers are device (1) or host (0) memory.  Valid before
+ * convergence too (partial sums); hb_stats tells whether it converged. */
+hb_status hb_centralities(hb_ctx* c, double* closeness, double* lin, double* harmonic,
+                          double* coreach, int32_t dst_on_device);
+
+/* The current counters, n*p bytes, node-major. */
+hb_status hb_get_registers(hb_ctx* c, uint8_t* dst, int32_t dst_on_device);
+
+/* The raw accumulators S (sum of t*delta) and H (sum of delta/t), n doubles
+ * each; either may be NULL. */
+hb_status hb_get_accumulators(hb_ctx* c, double* S, double* H, int32_t dst_on_device);
+
+typedef struct {
+  int64_t n, m;
+  int32_t log2m;
+  int32_t passes;          /* passes run since init/reset */
+  int32_t converged;       /* 1 once a pass changed no counter */
+  int64_t last_modified;   /* counters changed by the last pass */
+  int64_t heavy_rows;      /* rows split across workgroups */
+  int64_t heavy_chunks;
+  int64_t medium_rows;     /* rows handled by a whole wavefront */
+  double total_kernel_ms;  /* sum of timed pass kernels (timing = 1) */
+} hb_stats_t;
+
+hb_status hb_stats(hb_ctx* c, hb_stats_t* s);
+
+/* Per-pass record (pass in [0, passes)).  Work counters are exact:
+ *   arcs_scanned       arcs whose successor id was read (every arc, every pass)
+ *   counters_gathered  successor counters read (p bytes each)
+ *   rows_loaded        own counters read (rows with a gathered successor or
+ *                      a counter changed in the previous pass)
+ *   rows_written       counters written into the next buffer
+ *   rows_changed       counters that changed (= n_modified)
+ *   expand_ms / merge_ms: kernel times from HIP events (timing = 1, else 0). */
+typedef struct {
+  int64_t arcs_scanned;
+  int64_t counters_gathered;
+  int64_t rows_loaded;
+  int64_t rows_written;
+  int64_t rows_changed;
+  double expand_ms;
+  double merge_ms;
+} hb_pass_info;
+
+hb_status hb_pass_stats(hb_ctx* c, int32_t pass, hb_pass_info* info);
+
+/* Releases everything the context owns (never borrowed memory).  NULL-safe. */
+void hb_free(hb_ctx* c);
+
+/* Message for the last non-OK status returned on this thread. */
+const char* hb_last_error(void);
+
+/* Library ABI version (this header: 1). */
+int32_t hb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HB_H */

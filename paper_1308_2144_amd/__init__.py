@@ -1,0 +1,289 @@
+"""Python binding of libhb, the MI355X HyperBall library.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libhb.so``.  The module-level ``hb_*`` functions mirror the C ABI
+declared in ``include/hb.h`` one to one; :class:`HyperBall` is a small
+convenience wrapper over them.
+
+Arrays: host inputs are numpy arrays (copied by the library); device inputs
+are torch CUDA tensors, whose memory the library borrows until ``hb_free``
+(the wrapper keeps references so they stay alive).  PyTorch is used only for
+device memory and streams.
+
+Importing this module raises if ``libhb.so`` has not been built: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhb.so")
+
+HB_OK, HB_EINVAL, HB_ENOMEM, HB_EDEVICE, HB_ESTATE = 0, -1, -2, -3, -4
+_STATUS = {HB_EINVAL: "HB_EINVAL", HB_ENOMEM: "HB_ENOMEM", HB_EDEVICE: "HB_EDEVICE",
+           HB_ESTATE: "HB_ESTATE"}
+
+
+class HBError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class hb_csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("offsets", ctypes.c_void_p),
+                ("offsets_bits", ctypes.c_int32), ("indices", ctypes.c_void_p),
+                ("on_device", ctypes.c_int32)]
+
+
+class hb_options(ctypes.Structure):
+    _fields_ = [("frontier", ctypes.c_int32), ("light_max", ctypes.c_int32),
+                ("heavy_min", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("validate", ctypes.c_int32), ("timing", ctypes.c_int32)]
+
+
+class hb_stats_t(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("log2m", ctypes.c_int32),
+                ("passes", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("last_modified", ctypes.c_int64), ("heavy_rows", ctypes.c_int64),
+                ("heavy_chunks", ctypes.c_int64), ("medium_rows", ctypes.c_int64),
+                ("total_kernel_ms", ctypes.c_double)]
+
+
+class hb_pass_info(ctypes.Structure):
+    _fields_ = [("arcs_scanned", ctypes.c_int64), ("counters_gathered", ctypes.c_int64),
+                ("rows_loaded", ctypes.c_int64), ("rows_written", ctypes.c_int64),
+                ("rows_changed", ctypes.c_int64), ("expand_ms", ctypes.c_double),
+                ("merge_ms", ctypes.c_double)]
+
+
+def _declare(L):
+    vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    P = ctypes.POINTER
+    sig = {
+        "hb_default_options": (None, [P(hb_options)]),
+        "hb_init": (ctypes.c_int, [P(vp), P(hb_csr), i32, u64, P(hb_options), vp]),
+        "hb_reset": (ctypes.c_int, [vp, u64]),
+        "hb_iterate": (ctypes.c_int, [vp, P(i64)]),
+        "hb_run": (ctypes.c_int, [vp, i32, P(i32)]),
+        "hb_centralities": (ctypes.c_int, [vp, vp, vp, vp, vp, i32]),
+        "hb_get_registers": (ctypes.c_int, [vp, vp, i32]),
+        "hb_get_accumulators": (ctypes.c_int, [vp, vp, vp, i32]),
+        "hb_stats": (ctypes.c_int, [vp, P(hb_stats_t)]),
+        "hb_pass_stats": (ctypes.c_int, [vp, i32, P(hb_pass_info)]),
+        "hb_free": (None, [vp]),
+        "hb_last_error": (ctypes.c_char_p, []),
+        "hb_version": (i32, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libhb.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        # One HIP runtime per process: PyTorch ships its own libamdhip64 and
+        # libhsa-runtime64 (same sonames as the system ROCm ones).  Loading
+        # torch first makes libhb bind to that runtime instead of pulling in a
+        # second copy, which would leave torch without a visible GPU.
+        import torch  # noqa: F401
+
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(python -c 'import __graft_entry__ as g; g.build()')")
+        _lib = _declare(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+lib()
+
+
+def _check(st: int):
+    if st != HB_OK:
+        raise HBError(st, lib().hb_last_error().decode(errors="replace"))
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def default_options(**kw) -> hb_options:
+    o = hb_options()
+    lib().hb_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, int(v))
+    return o
+
+
+# --- one-to-one wrappers of the C ABI ------------------------------------------
+
+def hb_init(offsets, indices, log2m: int, seed: int, options: hb_options | None = None,
+            stream=None):
+    """Returns (ctx handle, keepalive tuple).  offsets: int32/int64; indices int32.
+
+    numpy inputs are host memory (copied); torch CUDA tensors are borrowed."""
+    dev = _is_torch(offsets)
+    if dev != _is_torch(indices):
+        raise TypeError("offsets and indices must both be numpy arrays or both torch tensors")
+    if dev:
+        import torch
+
+        if offsets.dtype not in (torch.int32, torch.int64) or indices.dtype != torch.int32:
+            raise TypeError("offsets must be int32/int64 and indices int32")
+        if not (offsets.is_cuda and indices.is_cuda and offsets.is_contiguous() and indices.is_contiguous()):
+            raise TypeError("device inputs must be contiguous CUDA tensors")
+        n = offsets.numel() - 1
+        bits = 64 if offsets.dtype == torch.int64 else 32
+        g = hb_csr(n, indices.numel(), offsets.data_ptr(), bits,
+                   indices.data_ptr() if indices.numel() else None, 1)
+    else:
+        offsets = np.ascontiguousarray(offsets)
+        indices = np.ascontiguousarray(indices, dtype=np.int32)
+        if offsets.dtype not in (np.int32, np.int64):
+            offsets = offsets.astype(np.int64)
+        n = offsets.shape[0] - 1
+        bits = 64 if offsets.dtype == np.int64 else 32
+        g = hb_csr(n, indices.shape[0], offsets.ctypes.data, bits,
+                   indices.ctypes.data if indices.size else None, 0)
+    ctx = ctypes.c_void_p()
+    opt = ctypes.byref(options) if options is not None else None
+    _check(lib().hb_init(ctypes.byref(ctx), ctypes.byref(g), int(log2m), int(seed), opt,
+                         ctypes.c_void_p(stream) if stream else None))
+    return ctx, (offsets, indices)
+
+
+def hb_reset(ctx, seed: int):
+    _check(lib().hb_reset(ctx, int(seed)))
+
+
+def hb_iterate(ctx) -> int:
+    nmod = ctypes.c_int64(0)
+    _check(lib().hb_iterate(ctx, ctypes.byref(nmod)))
+    return nmod.value
+
+
+def hb_run(ctx, max_passes: int = 0) -> int:
+    passes = ctypes.c_int32(0)
+    _check(lib().hb_run(ctx, int(max_passes), ctypes.byref(passes)))
+    return passes.value
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    return a.data_ptr() if _is_torch(a) else a.ctypes.data
+
+
+def hb_centralities(ctx, closeness, lin, harmonic, coreach, dst_on_device: bool):
+    _check(lib().hb_centralities(ctx, _ptr(closeness), _ptr(lin), _ptr(harmonic), _ptr(coreach),
+                                 int(dst_on_device)))
+
+
+def hb_get_registers(ctx, dst, dst_on_device: bool):
+    _check(lib().hb_get_registers(ctx, _ptr(dst), int(dst_on_device)))
+
+
+def hb_get_accumulators(ctx, S, H, dst_on_device: bool):
+    _check(lib().hb_get_accumulators(ctx, _ptr(S), _ptr(H), int(dst_on_device)))
+
+
+def hb_stats(ctx) -> dict:
+    s = hb_stats_t()
+    _check(lib().hb_stats(ctx, ctypes.byref(s)))
+    return {k: getattr(s, k) for k, _ in hb_stats_t._fields_}
+
+
+def hb_pass_stats(ctx, t: int) -> dict:
+    s = hb_pass_info()
+    _check(lib().hb_pass_stats(ctx, int(t), ctypes.byref(s)))
+    return {k: getattr(s, k) for k, _ in hb_pass_info._fields_}
+
+
+def hb_free(ctx):
+    lib().hb_free(ctx)
+
+
+def hb_version() -> int:
+    return lib().hb_version()
+
+
+# --- convenience wrapper --------------------------------------------------------
+
+class HyperBall:
+    """One HyperBall computation on one graph (see include/hb.h)."""
+
+    def __init__(self, offsets, indices, log2m: int, seed: int, *, stream=None, **options):
+        self.log2m = int(log2m)
+        self.p = 1 << self.log2m
+        opt = default_options(**options)
+        self._ctx, self._keep = hb_init(offsets, indices, log2m, seed, opt, stream)
+        self.n = (offsets.numel() if _is_torch(offsets) else len(offsets)) - 1
+
+    def close(self):
+        if self._ctx is not None:
+            hb_free(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def reset(self, seed: int):
+        hb_reset(self._ctx, seed)
+
+    def iterate(self) -> int:
+        return hb_iterate(self._ctx)
+
+    def run(self, max_passes: int = 0) -> int:
+        return hb_run(self._ctx, max_passes)
+
+    def registers(self) -> np.ndarray:
+        out = np.empty((max(self.n, 1), self.p), dtype=np.uint8)
+        hb_get_registers(self._ctx, out, False)
+        return out[: self.n]
+
+    def accumulators(self):
+        S = np.empty(max(self.n, 1))
+        H = np.empty(max(self.n, 1))
+        hb_get_accumulators(self._ctx, S, H, False)
+        return S[: self.n], H[: self.n]
+
+    def centralities(self, device: bool = False):
+        if device:
+            import torch
+
+            outs = [torch.empty(max(self.n, 1), dtype=torch.float64, device="cuda") for _ in range(4)]
+            hb_centralities(self._ctx, *outs, True)
+            outs = [o[: self.n] for o in outs]
+        else:
+            outs = [np.empty(max(self.n, 1)) for _ in range(4)]
+            hb_centralities(self._ctx, *outs, False)
+            outs = [o[: self.n] for o in outs]
+        return dict(zip(("closeness", "lin", "harmonic", "coreach"), outs))
+
+    def stats(self) -> dict:
+        return hb_stats(self._ctx)
+
+    def pass_stats(self, t: int) -> dict:
+        return hb_pass_stats(self._ctx, t)

@@ -1,0 +1,500 @@
+// Host side of libhb: context management, validation, allocation and the
+// per-pass driver loop.  See include/hb.h for the contract of every entry
+// point.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/hb.h"
+#include "hb_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+hb_status fail(hb_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HB_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) return fail(HB_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int DEFAULT_LIGHT_MAX = 32;
+constexpr int DEFAULT_HEAVY_MIN = 8192;
+constexpr int DEFAULT_CHUNK = 4096;
+
+// alpha_p of Flajolet-Fusy-Gandouet-Meunier 2007 (Algorithm 1 defers to it).
+double alpha_for(int p) {
+  if (p == 16) return 0.673;
+  if (p == 32) return 0.697;
+  if (p == 64) return 0.709;
+  return 0.7213 / (1.0 + 1.079 / (double)p);
+}
+
+template <class T>
+hipError_t dmalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+}
+
+}  // namespace
+
+struct hb_ctx {
+  int64_t n = 0, m = 0;
+  int b = 0, p = 0;
+  uint64_t seed = 0;
+  hb_options opt{};
+  hipStream_t stream = nullptr;
+  int64_t* off = nullptr;
+  bool own_off = false;
+  const int32_t* idx = nullptr;
+  int32_t* idx_owned = nullptr;
+  uint8_t* cnt[2] = {nullptr, nullptr};
+  uint64_t* mod[2] = {nullptr, nullptr};
+  int64_t n_blocks = 0;
+  double* S = nullptr;
+  double* H = nullptr;
+  double* E = nullptr;
+  double* lc = nullptr;
+  double alpha_pp = 0.0;
+  hb::HeavyItem* items = nullptr;
+  int64_t n_items = 0;
+  hb::HeavyRow* hrows = nullptr;
+  int64_t n_hrows = 0;
+  int64_t n_medium = 0;
+  uint8_t* partial = nullptr;
+  unsigned long long* stats = nullptr;       // 2 halves of STAT_SLOTS * STAT_K
+  unsigned long long* stats_host = nullptr;  // pinned
+  double* out_tmp = nullptr;                 // 4n doubles for host-destination finalize
+  int* bad = nullptr;
+  int cur = 0;
+  int32_t t = 0;
+  bool converged = false;
+  int64_t last_nmod = -1;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  std::vector<hb_pass_info> hist;
+  double total_ms = 0.0;
+  bool failed = false;
+};
+
+namespace {
+
+void release(hb_ctx* c) {
+  if (!c) return;
+  if (c->own_off) (void)hipFree(c->off);
+  (void)hipFree(c->idx_owned);
+  for (int i = 0; i < 2; ++i) {
+    (void)hipFree(c->cnt[i]);
+    (void)hipFree(c->mod[i]);
+  }
+  (void)hipFree(c->S);
+  (void)hipFree(c->H);
+  (void)hipFree(c->E);
+  (void)hipFree(c->lc);
+  (void)hipFree(c->items);
+  (void)hipFree(c->hrows);
+  (void)hipFree(c->partial);
+  (void)hipFree(c->stats);
+  (void)hipFree(c->out_tmp);
+  (void)hipFree(c->bad);
+  if (c->stats_host) (void)hipHostFree(c->stats_host);
+  for (int i = 0; i < 3; ++i)
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  delete c;
+}
+
+hb_status check_ctx(hb_ctx* c) {
+  if (!c) return fail(HB_EINVAL, "NULL context");
+  if (c->failed) return fail(HB_ESTATE, "context is in a failed state");
+  return HB_OK;
+}
+
+// Classify rows by degree and cut heavy rows into chunks.
+void plan_rows(hb_ctx* c, const int64_t* off_host, std::vector<hb::HeavyItem>& items,
+               std::vector<hb::HeavyRow>& hrows) {
+  const int64_t lmax = c->opt.light_max, hmin = c->opt.heavy_min, chunk = c->opt.chunk;
+  c->n_medium = 0;
+  for (int64_t v = 0; v < c->n; ++v) {
+    const int64_t s = off_host[v], e = off_host[v + 1], deg = e - s;
+    if (deg <= lmax) continue;
+    if (deg < hmin) {
+      ++c->n_medium;
+      continue;
+    }
+    hb::HeavyRow hr;
+    hr.row = v;
+    hr.item0 = (int64_t)items.size();
+    for (int64_t k = s; k < e; k += chunk) {
+      hb::HeavyItem it;
+      it.row = v;
+      it.e0 = k;
+      it.e1 = k + chunk < e ? k + chunk : e;
+      items.push_back(it);
+    }
+    hr.nitems = (int64_t)items.size() - hr.item0;
+    hrows.push_back(hr);
+  }
+}
+
+hb_status do_reset(hb_ctx* c, uint64_t seed) {
+  c->seed = seed;
+  c->t = 0;
+  c->cur = 0;
+  c->converged = false;
+  c->last_nmod = -1;
+  c->hist.clear();
+  c->total_ms = 0.0;
+  const size_t cbytes = (size_t)c->n * (size_t)c->p;
+  HB_HIP(hb::launch_fill_zero(c->cnt[0], cbytes, c->stream));
+  HB_HIP(hb::launch_fill_zero(c->cnt[1], cbytes, c->stream));
+  HB_HIP(hb::launch_fill_zero(c->mod[0], (size_t)c->n_blocks * 8, c->stream));
+  HB_HIP(hb::launch_fill_zero(c->mod[1], (size_t)c->n_blocks * 8, c->stream));
+  HB_HIP(hb::launch_fill_zero(c->stats, sizeof(unsigned long long) * 2 * hb::STAT_SLOTS * hb::STAT_K,
+                              c->stream));
+  HB_HIP(hb::launch_init_nodes(c->b, c->n, seed, c->cnt[0], c->cnt[1], c->S, c->H, c->E, c->lc,
+                               c->alpha_pp, c->stream));
+  return HB_OK;
+}
+
+hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, const hb_options* opt,
+                    void* stream) {
+  c->n = g->n;
+  c->m = g->m;
+  c->b = log2m;
+  c->p = 1 << log2m;
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  if (opt)
+    c->opt = *opt;
+  else
+    hb_default_options(&c->opt);
+  if (c->opt.light_max <= 0) c->opt.light_max = DEFAULT_LIGHT_MAX;
+  if (c->opt.heavy_min <= 0) c->opt.heavy_min = DEFAULT_HEAVY_MIN;
+  if (c->opt.chunk <= 0) c->opt.chunk = DEFAULT_CHUNK;
+  if (c->opt.heavy_min <= c->opt.light_max) c->opt.heavy_min = c->opt.light_max + 1;
+  const int64_t n = c->n, m = c->m;
+  c->n_blocks = (n + 63) / 64;
+
+  // Graph arrays.
+  std::vector<int64_t> off_host;
+  if (!g->on_device) {
+    off_host.resize((size_t)n + 1);
+    if (g->offsets_bits == 64) {
+      std::memcpy(off_host.data(), g->offsets, sizeof(int64_t) * ((size_t)n + 1));
+    } else {
+      const int32_t* o32 = static_cast<const int32_t*>(g->offsets);
+      for (int64_t i = 0; i <= n; ++i) off_host[(size_t)i] = o32[i];
+    }
+    HB_HIP(dmalloc(&c->off, (size_t)n + 1));
+    c->own_off = true;
+    HB_HIP(hipMemcpyAsync(c->off, off_host.data(), sizeof(int64_t) * ((size_t)n + 1),
+                          hipMemcpyHostToDevice, c->stream));
+    HB_HIP(dmalloc(&c->idx_owned, (size_t)m));
+    if (m > 0)
+      HB_HIP(hipMemcpyAsync(c->idx_owned, g->indices, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice,
+                            c->stream));
+    c->idx = c->idx_owned;
+  } else {
+    if (g->offsets_bits == 64) {
+      c->off = const_cast<int64_t*>(static_cast<const int64_t*>(g->offsets));
+    } else {
+      HB_HIP(dmalloc(&c->off, (size_t)n + 1));
+      c->own_off = true;
+      HB_HIP(hb::launch_widen_offsets(static_cast<const int32_t*>(g->offsets), c->off, n + 1, c->stream));
+    }
+    c->idx = g->indices;
+  }
+
+  if (c->opt.validate) {
+    HB_HIP(dmalloc(&c->bad, 1));
+    HB_HIP(hipMemsetAsync(c->bad, 0, sizeof(int), c->stream));
+    HB_HIP(hb::launch_validate(c->off, c->idx, n, m, c->bad, c->stream));
+    int bad = 0;
+    HB_HIP(hipMemcpyAsync(&bad, c->bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HB_HIP(hipStreamSynchronize(c->stream));
+    if (bad & 1) return fail(HB_EINVAL, "malformed CSR offsets (need offsets[0]=0, nondecreasing, offsets[n]=m)");
+    if (bad & 2) return fail(HB_EINVAL, "CSR index outside [0, n)");
+  }
+  if (g->on_device) {
+    off_host.resize((size_t)n + 1);
+    HB_HIP(hipMemcpyAsync(off_host.data(), c->off, sizeof(int64_t) * ((size_t)n + 1), hipMemcpyDeviceToHost,
+                          c->stream));
+    HB_HIP(hipStreamSynchronize(c->stream));
+  }
+
+  std::vector<hb::HeavyItem> items;
+  std::vector<hb::HeavyRow> hrows;
+  plan_rows(c, off_host.data(), items, hrows);
+  c->n_items = (int64_t)items.size();
+  c->n_hrows = (int64_t)hrows.size();
+  HB_HIP(dmalloc(&c->items, items.size()));
+  HB_HIP(dmalloc(&c->hrows, hrows.size()));
+  if (!items.empty())
+    HB_HIP(hipMemcpyAsync(c->items, items.data(), sizeof(hb::HeavyItem) * items.size(), hipMemcpyHostToDevice,
+                          c->stream));
+  if (!hrows.empty())
+    HB_HIP(hipMemcpyAsync(c->hrows, hrows.data(), sizeof(hb::HeavyRow) * hrows.size(), hipMemcpyHostToDevice,
+                          c->stream));
+
+  // Counters, bitmaps, accumulators.
+  const size_t cbytes = (size_t)n * (size_t)c->p;
+  for (int i = 0; i < 2; ++i) {
+    if (dmalloc(&c->cnt[i], cbytes) != hipSuccess)
+      return fail(HB_ENOMEM, "cannot allocate counter buffers (" + std::to_string(cbytes) + " bytes each)");
+    if (dmalloc(&c->mod[i], (size_t)c->n_blocks) != hipSuccess) return fail(HB_ENOMEM, "cannot allocate bitmaps");
+  }
+  if (dmalloc(&c->S, (size_t)n) != hipSuccess || dmalloc(&c->H, (size_t)n) != hipSuccess ||
+      dmalloc(&c->E, (size_t)n) != hipSuccess)
+    return fail(HB_ENOMEM, "cannot allocate accumulators");
+  HB_HIP(dmalloc(&c->lc, (size_t)c->p + 1));
+  HB_HIP(dmalloc(&c->partial, (size_t)c->n_items * (size_t)c->p));
+  HB_HIP(dmalloc(&c->stats, (size_t)2 * hb::STAT_SLOTS * hb::STAT_K));
+  HB_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->stats_host),
+                       sizeof(unsigned long long) * hb::STAT_SLOTS * hb::STAT_K, hipHostMallocDefault));
+  for (int i = 0; i < 3; ++i) HB_HIP(hipEventCreate(&c->ev[i]));
+
+  // Estimator constants: alpha_p p^2 and the linear-counting table p ln(p/V).
+  c->alpha_pp = (alpha_for(c->p) * (double)c->p) * (double)c->p;
+  std::vector<double> lc((size_t)c->p + 1, 0.0);
+  for (int V = 1; V <= c->p; ++V) lc[(size_t)V] = (double)c->p * std::log((double)c->p / (double)V);
+  HB_HIP(hipMemcpyAsync(c->lc, lc.data(), sizeof(double) * lc.size(), hipMemcpyHostToDevice, c->stream));
+  hb_status st = do_reset(c, seed);
+  if (st != HB_OK) return st;
+  HB_HIP(hipStreamSynchronize(c->stream));  // host staging vectors die here
+  return HB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void hb_default_options(hb_options* opt) {
+  if (!opt) return;
+  opt->frontier = 1;
+  opt->light_max = DEFAULT_LIGHT_MAX;
+  opt->heavy_min = DEFAULT_HEAVY_MIN;
+  opt->chunk = DEFAULT_CHUNK;
+  opt->validate = 1;
+  opt->timing = 0;
+}
+
+hb_status hb_init(hb_ctx** out, const hb_csr* g, int32_t log2m, uint64_t seed, const hb_options* opt,
+                  void* stream) {
+  if (!out) return fail(HB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!g) return fail(HB_EINVAL, "graph is NULL");
+  if (log2m < 4 || log2m > 16) return fail(HB_EINVAL, "log2m must be in [4, 16]");
+  if (g->n < 0 || g->m < 0) return fail(HB_EINVAL, "negative n or m");
+  if (g->n > 0x7fffffffLL) return fail(HB_EINVAL, "n must fit int32 node ids");
+  if (g->offsets_bits != 32 && g->offsets_bits != 64) return fail(HB_EINVAL, "offsets_bits must be 32 or 64");
+  if (g->offsets_bits == 32 && g->m > 0x7fffffffLL) return fail(HB_EINVAL, "m too large for int32 offsets");
+  if (!g->offsets) return fail(HB_EINVAL, "offsets is NULL");
+  if (g->m > 0 && !g->indices) return fail(HB_EINVAL, "indices is NULL");
+  if (opt && opt->chunk < 0) return fail(HB_EINVAL, "chunk must be >= 0");
+  if (!g->on_device) {
+    // Host arrays: check the CSR shape cheaply before copying.
+    const bool o64 = g->offsets_bits == 64;
+    const int64_t first = o64 ? static_cast<const int64_t*>(g->offsets)[0]
+                              : static_cast<const int32_t*>(g->offsets)[0];
+    const int64_t last = o64 ? static_cast<const int64_t*>(g->offsets)[g->n]
+                             : static_cast<const int32_t*>(g->offsets)[g->n];
+    if (first != 0 || last != g->m) return fail(HB_EINVAL, "offsets must start at 0 and end at m");
+  }
+  hb_ctx* c = new (std::nothrow) hb_ctx();
+  if (!c) return fail(HB_ENOMEM, "cannot allocate context");
+  const hb_status st = init_impl(c, g, log2m, seed, opt, stream);
+  if (st != HB_OK) {
+    const std::string msg = g_err;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    release(c);
+    g_err = msg;
+    return st;
+  }
+  *out = c;
+  return HB_OK;
+}
+
+hb_status hb_reset(hb_ctx* c, uint64_t seed) {
+  hb_status st = check_ctx(c);
+  if (st != HB_OK) return st;
+  st = do_reset(c, seed);
+  if (st != HB_OK) c->failed = true;
+  return st;
+}
+
+hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
+  hb_status st = check_ctx(c);
+  if (st != HB_OK) return st;
+  if (n_modified) *n_modified = 0;
+  if (c->converged) return HB_OK;
+  hb_pass_info info{};
+  if (c->n == 0) {
+    c->hist.push_back(info);
+    c->t += 1;
+    c->converged = true;
+    c->last_nmod = 0;
+    return HB_OK;
+  }
+  hb::PassArgs a{};
+  a.off = c->off;
+  a.idx = c->idx;
+  a.cur = c->cnt[c->cur];
+  a.nxt = c->cnt[c->cur ^ 1];
+  a.mod_prev = c->mod[c->cur];
+  a.mod_cur = c->mod[c->cur ^ 1];
+  a.S = c->S;
+  a.H = c->H;
+  a.E = c->E;
+  a.lc = c->lc;
+  a.items = c->items;
+  a.hrows = c->hrows;
+  a.partial = c->partial;
+  const size_t half = (size_t)hb::STAT_SLOTS * hb::STAT_K;
+  a.stats = c->stats + (size_t)(c->t & 1) * half;
+  a.stats_next = c->stats + (size_t)((c->t + 1) & 1) * half;
+  a.alpha_pp = c->alpha_pp;
+  a.d = (double)(c->t + 1);
+  a.n = c->n;
+  a.n_blocks = c->n_blocks;
+  a.n_items = c->n_items;
+  a.n_hrows = c->n_hrows;
+  a.light_max = c->opt.light_max;
+  a.heavy_min = c->opt.heavy_min;
+  a.first = c->t == 0 ? 1 : 0;
+  a.gather_all = (c->t == 0 || !c->opt.frontier) ? 1 : 0;
+  const bool timing = c->opt.timing != 0;
+  hipError_t e = hipSuccess;
+  if (timing) e = hipEventRecord(c->ev[0], c->stream);
+  if (e == hipSuccess) e = hb::launch_pass(c->b, a, c->stream, timing ? c->ev[1] : nullptr);
+  if (e == hipSuccess && timing) e = hipEventRecord(c->ev[2], c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->stats_host, a.stats, sizeof(unsigned long long) * half, hipMemcpyDeviceToHost,
+                       c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    c->failed = true;
+    return fail(HB_EDEVICE, std::string("pass ") + std::to_string(c->t) + ": " + hipGetErrorString(e));
+  }
+  unsigned long long sum[hb::STAT_K] = {0, 0, 0, 0};
+  for (int s = 0; s < hb::STAT_SLOTS; ++s)
+    for (int k = 0; k < hb::STAT_K; ++k) sum[k] += c->stats_host[s * hb::STAT_K + k];
+  info.arcs_scanned = c->m;
+  info.counters_gathered = (int64_t)sum[0];
+  info.rows_loaded = (int64_t)sum[1];
+  info.rows_written = (int64_t)sum[2];
+  info.rows_changed = (int64_t)sum[3];
+  if (timing) {
+    float ms1 = 0.f, ms2 = 0.f;
+    (void)hipEventElapsedTime(&ms1, c->ev[0], c->ev[1]);
+    (void)hipEventElapsedTime(&ms2, c->ev[1], c->ev[2]);
+    info.expand_ms = ms1;
+    info.merge_ms = ms2;
+    c->total_ms += (double)ms1 + (double)ms2;
+  }
+  c->hist.push_back(info);
+  c->cur ^= 1;
+  c->t += 1;
+  c->last_nmod = info.rows_changed;
+  if (info.rows_changed == 0) c->converged = true;
+  if (n_modified) *n_modified = info.rows_changed;
+  return HB_OK;
+}
+
+hb_status hb_run(hb_ctx* c, int32_t max_passes, int32_t* passes) {
+  hb_status st = check_ctx(c);
+  if (st != HB_OK) return st;
+  while (!c->converged && (max_passes <= 0 || c->t < max_passes)) {
+    st = hb_iterate(c, nullptr);
+    if (st != HB_OK) return st;
+  }
+  if (passes) *passes = c->t;
+  return HB_OK;
+}
+
+hb_status hb_centralities(hb_ctx* c, double* closeness, double* lin, double* harmonic, double* coreach,
+                          int32_t dst_on_device) {
+  hb_status st = check_ctx(c);
+  if (st != HB_OK) return st;
+  if (c->n == 0) return HB_OK;
+  if (dst_on_device) {
+    HB_HIP(hb::launch_finalize(c->n, c->S, c->H, c->E, closeness, lin, harmonic, coreach, c->stream));
+    HB_HIP(hipStreamSynchronize(c->stream));
+    return HB_OK;
+  }
+  const size_t n = (size_t)c->n;
+  if (!c->out_tmp) {
+    if (dmalloc(&c->out_tmp, 4 * n) != hipSuccess) return fail(HB_ENOMEM, "cannot allocate output staging");
+  }
+  double* d[4] = {c->out_tmp, c->out_tmp + n, c->out_tmp + 2 * n, c->out_tmp + 3 * n};
+  double* h[4] = {closeness, lin, harmonic, coreach};
+  HB_HIP(hb::launch_finalize(c->n, c->S, c->H, c->E, h[0] ? d[0] : nullptr, h[1] ? d[1] : nullptr,
+                             h[2] ? d[2] : nullptr, h[3] ? d[3] : nullptr, c->stream));
+  for (int i = 0; i < 4; ++i)
+    if (h[i]) HB_HIP(hipMemcpyAsync(h[i], d[i], sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  HB_HIP(hipStreamSynchronize(c->stream));
+  return HB_OK;
+}
+
+hb_status hb_get_registers(hb_ctx* c, uint8_t* dst, int32_t dst_on_device) {
+  hb_status st = check_ctx(c);
+  if (st != HB_OK) return st;
+  if (!dst) return fail(HB_EINVAL, "dst is NULL");
+  const size_t bytes = (size_t)c->n * (size_t)c->p;
+  if (bytes == 0) return HB_OK;
+  HB_HIP(hipMemcpyAsync(dst, c->cnt[c->cur], bytes,
+                        dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+  HB_HIP(hipStreamSynchronize(c->stream));
+  return HB_OK;
+}
+
+hb_status hb_get_accumulators(hb_ctx* c, double* S, double* H, int32_t dst_on_device) {
+  hb_status st = check_ctx(c);
+  if (st != HB_OK) return st;
+  const size_t bytes = sizeof(double) * (size_t)c->n;
+  if (bytes == 0) return HB_OK;
+  const hipMemcpyKind k = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (S) HB_HIP(hipMemcpyAsync(S, c->S, bytes, k, c->stream));
+  if (H) HB_HIP(hipMemcpyAsync(H, c->H, bytes, k, c->stream));
+  HB_HIP(hipStreamSynchronize(c->stream));
+  return HB_OK;
+}
+
+hb_status hb_stats(hb_ctx* c, hb_stats_t* s) {
+  if (!c || !s) return fail(HB_EINVAL, "NULL argument");
+  s->n = c->n;
+  s->m = c->m;
+  s->log2m = c->b;
+  s->passes = c->t;
+  s->converged = c->converged ? 1 : 0;
+  s->last_modified = c->last_nmod;
+  s->heavy_rows = c->n_hrows;
+  s->heavy_chunks = c->n_items;
+  s->medium_rows = c->n_medium;
+  s->total_kernel_ms = c->total_ms;
+  return HB_OK;
+}
+
+hb_status hb_pass_stats(hb_ctx* c, int32_t pass, hb_pass_info* info) {
+  if (!c || !info) return fail(HB_EINVAL, "NULL argument");
+  if (pass < 0 || pass >= (int32_t)c->hist.size()) return fail(HB_EINVAL, "no such pass");
+  *info = c->hist[(size_t)pass];
+  return HB_OK;
+}
+
+void hb_free(hb_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  release(c);
+}
+
+const char* hb_last_error(void) { return g_err.c_str(); }
+
+int32_t hb_version(void) { return 1; }
+
+}  // extern "C"

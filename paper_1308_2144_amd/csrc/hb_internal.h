@@ -1,0 +1,75 @@
+// Internal interface between the host side of libhb (hb_api.cpp) and its HIP
+// kernels (hb_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hb {
+
+// A row whose arcs are reduced by several workgroups: `nitems` consecutive
+// chunk items starting at `item0` each write a partial counter that the merge
+// kernel folds into the row.
+struct HeavyRow {
+  int64_t row;
+  int64_t item0;
+  int64_t nitems;
+};
+
+// One chunk of a heavy row: arcs [e0, e1).
+struct HeavyItem {
+  int64_t row;
+  int64_t e0;
+  int64_t e1;
+};
+
+// Number of slots the per-pass work counters are spread over (atomics to a
+// single address would serialise); STAT_K counters per slot.
+constexpr int STAT_SLOTS = 256;
+constexpr int STAT_K = 4;  // gathered, loaded, written, changed
+
+// Everything one pass needs.  `cur` holds counters of radius t, `nxt`
+// receives radius t+1.  mod_prev has bit v set if counter v changed in the
+// previous pass; mod_cur receives this pass's bits (every word is written).
+struct PassArgs {
+  const int64_t* off;
+  const int32_t* idx;
+  const uint8_t* cur;
+  uint8_t* nxt;
+  const uint64_t* mod_prev;
+  uint64_t* mod_cur;
+  double* S;
+  double* H;
+  double* E;
+  const double* lc;  // linear-counting table, entries 0..p
+  const HeavyItem* items;
+  const HeavyRow* hrows;
+  uint8_t* partial;                  // n_items * p bytes
+  unsigned long long* stats;         // this pass: STAT_SLOTS * STAT_K
+  unsigned long long* stats_next;    // zeroed by this pass for the next one
+  double alpha_pp;                   // (alpha_p * p) * p
+  double d;                          // t + 1
+  int64_t n;
+  int64_t n_blocks;                  // ceil(n / 64)
+  int64_t n_items;
+  int64_t n_hrows;
+  int32_t light_max;
+  int32_t heavy_min;
+  int32_t gather_all;                // pass 0 or frontier off
+  int32_t first;                     // pass 0: no previous-pass bits exist
+};
+
+// Launchers (hb_kernels.hip).  All return the launch status.
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_init_nodes(int log2m, int64_t n, uint64_t seed, uint8_t* cur, uint8_t* nxt,
+                             double* S, double* H, double* E, const double* lc, double alpha_pp,
+                             hipStream_t s);
+hipError_t launch_pass(int log2m, const PassArgs& a, hipStream_t s, hipEvent_t ev_mid);
+hipError_t launch_finalize(int64_t n, const double* S, const double* H, const double* E,
+                           double* clo, double* lin, double* harm, double* core, hipStream_t s);
+hipError_t launch_widen_offsets(const int32_t* in, int64_t* out, int64_t count, hipStream_t s);
+// Writes 1 to *bad if the CSR is malformed (bad must be zeroed first).
+hipError_t launch_validate(const int64_t* off, const int32_t* idx, int64_t n, int64_t m,
+                           int* bad, hipStream_t s);
+
+}  // namespace hb

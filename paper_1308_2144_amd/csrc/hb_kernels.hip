@@ -1,0 +1,662 @@
+// HIP kernels of the HyperBall pass for gfx950 (MI355X).
+//
+// Data layout in HBM:
+//   counters  two buffers of n * p bytes, node-major (register j of node v at
+//             v*p + j); pass t reads `cur` and writes `nxt`, then they swap.
+//   bitmaps   two arrays of ceil(n/64) words; bit v of mod_prev says the
+//             counter of v changed in the previous pass.
+//   S, H, E   doubles per node: the two accumulators of Sec. 5 and the size
+//             estimate of the current counter (cached so that a pass only
+//             evaluates the estimator once per changed node).
+//
+// One pass (Algorithm 2, one iteration of the do-loop):
+//   a = c[v] U (U over arcs v->w of c[w])       (register-wise max, Sec. 4.2)
+// with two exact shortcuts:
+//   * edge skipping: a successor whose counter did not change in the previous
+//     pass is already contained in c[v] (c_t(v) contains c_{t-1}(w) for every
+//     arc v->w), so only changed successors are gathered;
+//   * write skipping: the next buffer still holds c_{t-1}(v), which equals
+//     c_t(v) unless v changed in the previous pass; so a counter is written
+//     only if it changes now or changed in the previous pass.
+// A changed counter's estimate E(a) is computed in the same kernel and the
+// increments delta*(t+1) and delta/(t+1) are added to S and H (Sec. 5).
+//
+// Work decomposition (degree-aware): a 64-row block per wavefront.  Each
+// counter is handled by a group of G = p/16 lanes, every lane owning 16
+// bytes; a wavefront holds W = 64/G groups.  Rows with <= light_max arcs are
+// dealt to the groups round-robin; rows up to heavy_min arcs are processed by
+// the whole wavefront (groups stride over the arcs, then reduce by shuffles);
+// heavier rows are cut into chunks reduced by separate workgroups into
+// partial counters that a second kernel merges.  Counters wider than 256
+// bytes use a one-workgroup-per-block kernel.
+//
+// There is no dense contraction here: the pass is a gather of p-byte rows and
+// byte-wise maxima, bound by HBM bandwidth, so no MFMA is involved.
+#include "hb_internal.h"
+
+namespace hb {
+namespace {
+
+constexpr int U = 8;  // successor counters in flight per lane group
+
+// Node hash: SplitMix64 finalizer (Steele, Lea, Flood 2014) of
+// v + (seed+1) * golden-ratio increment.  The paper asks only for a fixed
+// hash (Sec. 4.1); this is the library's convention.
+__device__ __forceinline__ uint64_t node_hash(uint64_t v, uint64_t seed) {
+  uint64_t z = v + (seed + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Byte-wise maximum of four packed registers.  Even and odd bytes are
+// maximised separately in 16-bit lanes (packed u16 max), where no byte can
+// carry into its neighbour, then recombined.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t bmax4(uint32_t a, uint32_t b) {
+  const u16x2 ae = __builtin_bit_cast(u16x2, a & 0x00FF00FFu);
+  const u16x2 be = __builtin_bit_cast(u16x2, b & 0x00FF00FFu);
+  const u16x2 ao = __builtin_bit_cast(u16x2, a & 0xFF00FF00u);
+  const u16x2 bo = __builtin_bit_cast(u16x2, b & 0xFF00FF00u);
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(ae, be)) |
+         __builtin_bit_cast(uint32_t, __builtin_elementwise_max(ao, bo));
+}
+
+__device__ __forceinline__ uint4 bmax(uint4 a, uint4 b) {
+  a.x = bmax4(a.x, b.x);
+  a.y = bmax4(a.y, b.y);
+  a.z = bmax4(a.z, b.z);
+  a.w = bmax4(a.w, b.w);
+  return a;
+}
+
+// Gather accumulator kept as even and odd bytes in separate 16-bit lanes, so
+// folding in one dword costs two masks and two packed maxima.
+struct SplitAcc {
+  uint4 e;
+  uint4 o;
+};
+
+__device__ __forceinline__ uint32_t pkmax(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
+                                                                __builtin_bit_cast(u16x2, b)));
+}
+
+__device__ __forceinline__ void fold(SplitAcc& acc, uint4 x) {
+  acc.e.x = pkmax(acc.e.x, x.x & 0x00FF00FFu);
+  acc.o.x = pkmax(acc.o.x, x.x & 0xFF00FF00u);
+  acc.e.y = pkmax(acc.e.y, x.y & 0x00FF00FFu);
+  acc.o.y = pkmax(acc.o.y, x.y & 0xFF00FF00u);
+  acc.e.z = pkmax(acc.e.z, x.z & 0x00FF00FFu);
+  acc.o.z = pkmax(acc.o.z, x.z & 0xFF00FF00u);
+  acc.e.w = pkmax(acc.e.w, x.w & 0x00FF00FFu);
+  acc.o.w = pkmax(acc.o.w, x.w & 0xFF00FF00u);
+}
+
+__device__ __forceinline__ uint4 unsplit(const SplitAcc& acc) {
+  return make_uint4(acc.e.x | acc.o.x, acc.e.y | acc.o.y, acc.e.z | acc.o.z, acc.e.w | acc.o.w);
+}
+
+__device__ __forceinline__ bool differs(uint4 a, uint4 b) {
+  return ((a.x ^ b.x) | (a.y ^ b.y) | (a.z ^ b.z) | (a.w ^ b.w)) != 0u;
+}
+
+__device__ __forceinline__ uint4 shfl_xor4(uint4 v, int m) {
+  v.x = __shfl_xor(v.x, m);
+  v.y = __shfl_xor(v.y, m);
+  v.z = __shfl_xor(v.z, m);
+  v.w = __shfl_xor(v.w, m);
+  return v;
+}
+
+__device__ __forceinline__ uint4 zero4() { return make_uint4(0u, 0u, 0u, 0u); }
+
+// 2^-r as a double, built from its exponent field (r <= 61 here).
+__device__ __forceinline__ double pow2neg(uint32_t r) {
+  return __hiloint2double((int)(0x3FF00000u - (r << 20)), 0);
+}
+
+// Exact pieces of sum_j 2^-M[j] over the 16 registers in v.  Terms with
+// M[j] <= 26 go to `big`, the others to `small`: any sum of up to 2^16 terms
+// of either kind is a multiple of a fixed power of two below 2^53 ulps, so
+// both partial sums (and sums of them across lanes) are exact in double, and
+// big + small rounds the exact total once.  `zeros` counts empty registers.
+struct Parts {
+  double big;
+  double small;
+  int zeros;
+};
+
+__device__ __forceinline__ Parts reg_parts(uint4 v) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+  uint32_t high = 0;
+  int zeros = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    high |= (w[i] + 0x65656565u) & 0x80808080u;  // some byte >= 27 (bytes are <= 61)
+    const uint32_t t = ((w[i] & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | w[i];
+    zeros += __popc(~t & 0x80808080u);          // bytes equal to 0
+  }
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, sm = 0.0;
+  if (high == 0u) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a0 += pow2neg(w[i] & 0xFFu);
+      a1 += pow2neg((w[i] >> 8) & 0xFFu);
+      a2 += pow2neg((w[i] >> 16) & 0xFFu);
+      a3 += pow2neg(w[i] >> 24);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t r = (w[i] >> (8 * k)) & 0xFFu;
+        const double t = pow2neg(r);
+        const bool lo = r <= 26u;
+        a0 += lo ? t : 0.0;
+        sm += lo ? 0.0 : t;
+      }
+  }
+  Parts out;
+  out.big = (a0 + a1) + (a2 + a3);
+  out.small = sm;
+  out.zeros = zeros;
+  return out;
+}
+
+// Algorithm 1 `size` with the small-range (linear counting) estimator:
+// alpha_p p^2 / Z, or p ln(p/V) (tabulated in lc) when that is <= 5p/2 and
+// V > 0 registers are empty.
+__device__ __forceinline__ double estimate(double big, double small, int V, double alpha_pp,
+                                           double p, const double* lc) {
+  const double z = big + small;
+  double E = alpha_pp / z;
+  if (E <= 2.5 * p && V > 0) E = lc[V];
+  return E;
+}
+
+// Gather-max over the arcs k, k+st, k+2st, ... < e of a row: every lane of
+// the group loads its 16-byte slice of each selected successor counter.
+// `got` is set if at least one counter was gathered; `ngath` counts them.
+template <int B>
+__device__ __forceinline__ uint4 gather(const PassArgs& A, int64_t k, int64_t e, int64_t st, int gl,
+                                        bool& got, uint32_t& ngath) {
+  constexpr int P = 1 << B;
+  SplitAcc acc{zero4(), zero4()};
+  const uint8_t* base = A.cur + gl * 16;
+  for (; k < e; k += st * U) {
+    int32_t w[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t kk = k + u * st;
+      w[u] = kk < e ? A.idx[kk] : -1;
+    }
+    bool m[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t ws = w[u] < 0 ? 0 : w[u];
+      const bool bit = A.gather_all ? true : (((A.mod_prev[ws >> 6] >> (ws & 63)) & 1ull) != 0ull);
+      m[u] = (w[u] >= 0) && bit;
+    }
+    uint4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v[u] = zero4();
+      if (m[u]) v[u] = *reinterpret_cast<const uint4*>(base + (size_t)w[u] * P);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      fold(acc, v[u]);
+      got |= m[u];
+      ngath += m[u] ? 1u : 0u;
+    }
+  }
+  return unsplit(acc);
+}
+
+// Completes row `row` for a group of G lanes: a = own U gathered, write-back
+// rule, change detection and the fused estimator/accumulator.  Returns
+// whether the counter changed (uniform over the group).
+template <int B>
+__device__ __forceinline__ bool finish_row(const PassArgs& A, int64_t row, uint4 acc, bool got,
+                                           bool own_mod, int gl, int grp, uint32_t& nload,
+                                           uint32_t& nwrite) {
+  constexpr int P = 1 << B;
+  constexpr int G = P / 16;
+  const size_t off = (size_t)row * P + (size_t)gl * 16;
+  uint4 own = zero4();
+  if (got || own_mod) own = *reinterpret_cast<const uint4*>(A.cur + off);
+  const uint4 a = got ? bmax(acc, own) : own;
+  const bool diff = got && differs(a, own);
+  const uint64_t bal = __ballot(diff);
+  const uint64_t gmask = (G >= 64) ? ~0ull : (((1ull << G) - 1ull) << (grp * G));
+  const bool changed = (bal & gmask) != 0ull;
+  if (changed || own_mod) *reinterpret_cast<uint4*>(A.nxt + off) = a;
+  if (gl == 0) {
+    nload += (got || own_mod) ? 1u : 0u;
+    nwrite += (changed || own_mod) ? 1u : 0u;
+  }
+  if (changed) {
+    const Parts pr = reg_parts(a);
+    double big = pr.big, small = pr.small;
+    int V = pr.zeros;
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+      big += __shfl_xor(big, o);
+      small += __shfl_xor(small, o);
+      V += __shfl_xor(V, o);
+    }
+    if (gl == 0) {
+      const double En = estimate(big, small, V, A.alpha_pp, (double)P, A.lc);
+      const double delta = En - A.E[row];
+      A.S[row] = A.S[row] + A.d * delta;
+      A.H[row] = A.H[row] + delta / A.d;
+      A.E[row] = En;
+    }
+  }
+  return changed;
+}
+
+__device__ __forceinline__ void add_stats(unsigned long long* st, uint32_t g, uint32_t l, uint32_t w,
+                                          uint32_t c) {
+  if (g) atomicAdd(st + 0, (unsigned long long)g);
+  if (l) atomicAdd(st + 1, (unsigned long long)l);
+  if (w) atomicAdd(st + 2, (unsigned long long)w);
+  if (c) atomicAdd(st + 3, (unsigned long long)c);
+}
+
+template <int B>
+__device__ __forceinline__ void light_block(const PassArgs& A, int64_t blk, int lane) {
+  constexpr int P = 1 << B;
+  constexpr int G = P / 16;
+  constexpr int W = 64 / G;
+  const int gl = lane % G;
+  const int grp = lane / G;
+  const int64_t r0 = blk * 64;
+  const int64_t row = r0 + lane;
+  const bool valid = row < A.n;
+  int64_t s = 0, deg = 0;
+  if (valid) {
+    s = A.off[row];
+    deg = A.off[row + 1] - s;
+  }
+  const uint64_t own_word = A.first ? 0ull : A.mod_prev[blk];
+  uint64_t bits = 0;
+  uint32_t ngath = 0, nload = 0, nwrite = 0;
+
+  // Light rows: row q*W + grp goes to group grp in round q.
+  for (int q = 0; q < G; ++q) {
+    const int rl = q * W + grp;
+    const int64_t rs = __shfl(s, rl);
+    const int64_t rd = __shfl(deg, rl);
+    const int64_t rrow = r0 + rl;
+    if (rrow < A.n && rd <= A.light_max) {
+      const bool own_mod = ((own_word >> rl) & 1ull) != 0ull;
+      bool got = false;
+      uint32_t g = 0;
+      const uint4 acc = gather<B>(A, rs, rs + rd, 1, gl, got, g);
+      if (gl == 0) ngath += g;
+      if (finish_row<B>(A, rrow, acc, got, own_mod, gl, grp, nload, nwrite) && gl == 0)
+        bits |= 1ull << rl;
+    }
+  }
+
+  // Medium rows: the whole wavefront, groups striding over the arcs.
+  uint64_t mm = __ballot(valid && deg > A.light_max && deg < A.heavy_min);
+  while (mm) {
+    const int rl = __builtin_ctzll(mm);
+    mm &= mm - 1ull;
+    const int64_t rs = __shfl(s, rl);
+    const int64_t rd = __shfl(deg, rl);
+    bool got = false;
+    uint32_t g = 0;
+    uint4 acc = gather<B>(A, rs + grp, rs + rd, W, gl, got, g);
+    if (gl == 0) ngath += g;
+#pragma unroll
+    for (int o = G; o < 64; o <<= 1) acc = bmax(acc, shfl_xor4(acc, o));
+    got = __ballot(got) != 0ull;
+    if (grp == 0) {
+      const bool own_mod = ((own_word >> rl) & 1ull) != 0ull;
+      if (finish_row<B>(A, r0 + rl, acc, got, own_mod, gl, 0, nload, nwrite) && gl == 0)
+        bits |= 1ull << rl;
+    }
+  }
+
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    bits |= __shfl_xor(bits, o);
+    ngath += __shfl_xor(ngath, o);
+    nload += __shfl_xor(nload, o);
+    nwrite += __shfl_xor(nwrite, o);
+  }
+  if (lane == 0) {
+    A.mod_cur[blk] = bits;
+    add_stats(A.stats + (blk & (STAT_SLOTS - 1)) * STAT_K, ngath, nload, nwrite,
+              (uint32_t)__popcll(bits));
+  }
+}
+
+template <int B>
+__device__ __forceinline__ void heavy_chunk(const PassArgs& A, int64_t item, int lane, int wave) {
+  constexpr int P = 1 << B;
+  constexpr int G = P / 16;
+  constexpr int W = 64 / G;
+  __shared__ uint4 red[4][16];
+  const int gl = lane % G;
+  const int grp = lane / G;
+  const HeavyItem it = A.items[item];
+  bool got = false;
+  uint32_t g = 0;
+  uint4 acc = gather<B>(A, it.e0 + wave * W + grp, it.e1, 4 * W, gl, got, g);
+#pragma unroll
+  for (int o = G; o < 64; o <<= 1) acc = bmax(acc, shfl_xor4(acc, o));
+  if (grp == 0) red[wave][gl] = acc;
+  uint32_t ng = (gl == 0) ? g : 0u;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) ng += __shfl_xor(ng, o);
+  if (lane == 0) add_stats(A.stats + (item & (STAT_SLOTS - 1)) * STAT_K, ng, 0, 0, 0);
+  __syncthreads();
+  if (wave == 0 && grp == 0) {
+    uint4 a = red[0][gl];
+    a = bmax(a, red[1][gl]);
+    a = bmax(a, red[2][gl]);
+    a = bmax(a, red[3][gl]);
+    *reinterpret_cast<uint4*>(A.partial + (size_t)item * P + (size_t)gl * 16) = a;
+  }
+}
+
+template <int B>
+__global__ __launch_bounds__(256) void k_expand(PassArgs A) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < STAT_SLOTS * STAT_K; i += blockDim.x) A.stats_next[i] = 0ull;
+  if ((int64_t)blockIdx.x < A.n_items) {
+    heavy_chunk<B>(A, blockIdx.x, lane, wave);
+    return;
+  }
+  const int64_t blk = ((int64_t)blockIdx.x - A.n_items) * 4 + wave;
+  if (blk < A.n_blocks) light_block<B>(A, blk, lane);
+}
+
+// Folds the partial counters of every heavy row into the row (one wavefront
+// per heavy row) and finishes it like any other row.
+template <int B>
+__global__ __launch_bounds__(256) void k_merge(PassArgs A) {
+  constexpr int P = 1 << B;
+  constexpr int G = P / 16;
+  constexpr int W = 64 / G;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int gl = lane % G;
+  const int grp = lane / G;
+  const int64_t h = (int64_t)blockIdx.x * 4 + wave;
+  if (h >= A.n_hrows) return;
+  const HeavyRow hr = A.hrows[h];
+  uint4 acc = zero4();
+  for (int64_t j = grp; j < hr.nitems; j += W)
+    acc = bmax(acc, *reinterpret_cast<const uint4*>(A.partial + (size_t)(hr.item0 + j) * P +
+                                                    (size_t)gl * 16));
+#pragma unroll
+  for (int o = G; o < 64; o <<= 1) acc = bmax(acc, shfl_xor4(acc, o));
+  if (grp == 0) {
+    const bool own_mod =
+        A.first ? false : (((A.mod_prev[hr.row >> 6] >> (hr.row & 63)) & 1ull) != 0ull);
+    uint32_t nload = 0, nwrite = 0;
+    const bool changed = finish_row<B>(A, hr.row, acc, true, own_mod, gl, 0, nload, nwrite);
+    if (gl == 0) {
+      if (changed) atomicOr(A.mod_cur + (hr.row >> 6), 1ull << (hr.row & 63));
+      add_stats(A.stats + (h & (STAT_SLOTS - 1)) * STAT_K, 0, nload, nwrite, changed ? 1u : 0u);
+    }
+  }
+}
+
+// Counters wider than 256 bytes: one workgroup per 64-row block, rows in
+// sequence, each thread owning 16-byte chunks tid, tid+256, ...; the new
+// counter is staged in LDS (p bytes) until the change decision is known.
+__global__ __launch_bounds__(256) void k_expand_wide(PassArgs A, int log2m) {
+  extern __shared__ uint4 stage[];
+  __shared__ double red_big[256];
+  __shared__ double red_small[256];
+  __shared__ int red_v[256];
+  const int P = 1 << log2m;
+  const int C = P / 16;
+  const int tid = threadIdx.x;
+  if (blockIdx.x == 0)
+    for (int i = tid; i < STAT_SLOTS * STAT_K; i += blockDim.x) A.stats_next[i] = 0ull;
+  const int64_t blk = blockIdx.x;
+  const int64_t r0 = blk * 64;
+  const uint64_t own_word = A.first ? 0ull : A.mod_prev[blk];
+  uint64_t bits = 0;
+  uint32_t ngath = 0, nload = 0, nwrite = 0;
+  for (int rl = 0; rl < 64; ++rl) {
+    const int64_t row = r0 + rl;
+    if (row >= A.n) break;
+    const int64_t s = A.off[row], e = A.off[row + 1];
+    const bool own_mod = ((own_word >> rl) & 1ull) != 0ull;
+    int mine = 0;
+    for (int64_t k = s + tid; k < e; k += 256) {
+      const int32_t w = A.idx[k];
+      if (A.gather_all || ((A.mod_prev[w >> 6] >> (w & 63)) & 1ull)) ++mine;
+    }
+    const int ngot = __syncthreads_count(mine);
+    const bool got = ngot > 0;
+    ngath += (uint32_t)ngot;
+    if (!got && !own_mod) continue;
+    ++nload;
+    int diff = 0;
+    for (int c = tid; c < C; c += 256) {
+      const uint4 own = *reinterpret_cast<const uint4*>(A.cur + (size_t)row * P + (size_t)c * 16);
+      uint4 a = own;
+      if (got)
+        for (int64_t k = s; k < e; ++k) {
+          const int32_t w = A.idx[k];
+          if (A.gather_all || ((A.mod_prev[w >> 6] >> (w & 63)) & 1ull))
+            a = bmax(a, *reinterpret_cast<const uint4*>(A.cur + (size_t)w * P + (size_t)c * 16));
+        }
+      diff |= differs(a, own) ? 1 : 0;
+      stage[c] = a;
+    }
+    const bool changed = __syncthreads_or(diff) != 0;
+    if (changed || own_mod) {
+      ++nwrite;
+      for (int c = tid; c < C; c += 256)
+        *reinterpret_cast<uint4*>(A.nxt + (size_t)row * P + (size_t)c * 16) = stage[c];
+    }
+    if (changed) {
+      double big = 0.0, small = 0.0;
+      int V = 0;
+      for (int c = tid; c < C; c += 256) {
+        const Parts pr = reg_parts(stage[c]);
+        big += pr.big;
+        small += pr.small;
+        V += pr.zeros;
+      }
+      red_big[tid] = big;
+      red_small[tid] = small;
+      red_v[tid] = V;
+      __syncthreads();
+      for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) {
+          red_big[tid] += red_big[tid + o];
+          red_small[tid] += red_small[tid + o];
+          red_v[tid] += red_v[tid + o];
+        }
+        __syncthreads();
+      }
+      if (tid == 0) {
+        const double En = estimate(red_big[0], red_small[0], red_v[0], A.alpha_pp, (double)P, A.lc);
+        const double delta = En - A.E[row];
+        A.S[row] = A.S[row] + A.d * delta;
+        A.H[row] = A.H[row] + delta / A.d;
+        A.E[row] = En;
+      }
+      bits |= 1ull << rl;
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    A.mod_cur[blk] = bits;
+    add_stats(A.stats + (blk & (STAT_SLOTS - 1)) * STAT_K, ngath, nload, nwrite,
+              (uint32_t)__popcll(bits));
+  }
+}
+
+__global__ void k_fill_zero(uint4* p, size_t n16, uint8_t* tail, size_t ntail) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) p[i] = zero4();
+  if (blockIdx.x == 0)
+    for (size_t i = threadIdx.x; i < ntail; i += blockDim.x) tail[i] = 0;
+}
+
+// Algorithm 2 initialisation: add(c[v], v) into both buffers, zero S and H,
+// and cache E(c[v]) for the singleton counter (p-1 empty registers).
+__global__ void k_init_nodes(int log2m, int64_t n, uint64_t seed, uint8_t* cur, uint8_t* nxt,
+                             double* S, double* H, double* E, const double* lc, double alpha_pp) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int P = 1 << log2m;
+  const uint64_t h = node_hash((uint64_t)v, seed);
+  const uint32_t j = (uint32_t)(h >> (64 - log2m));
+  const uint64_t rest = h << log2m;
+  const uint32_t r = rest == 0ull ? (uint32_t)(65 - log2m) : (uint32_t)__clzll((long long)rest) + 1u;
+  cur[(size_t)v * P + j] = (uint8_t)r;
+  nxt[(size_t)v * P + j] = (uint8_t)r;
+  S[v] = 0.0;
+  H[v] = 0.0;
+  double big = (double)(P - 1), small = 0.0;
+  if (r <= 26u)
+    big += pow2neg(r);
+  else
+    small += pow2neg(r);
+  E[v] = estimate(big, small, P - 1, alpha_pp, (double)P, lc);
+}
+
+// Sec. 3 / Sec. 5 finalisation.
+__global__ void k_finalize(int64_t n, const double* S, const double* H, const double* E, double* clo,
+                           double* lin, double* harm, double* core) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const double s = S[v];
+  const double size = E[v];
+  if (core) core[v] = size;
+  if (clo) clo[v] = (s == 0.0) ? 0.0 : 1.0 / s;
+  if (lin) lin[v] = (s == 0.0) ? 1.0 : (size * size) / s;
+  if (harm) harm[v] = H[v];
+}
+
+__global__ void k_widen(const int32_t* in, int64_t* out, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = (int64_t)in[i];
+}
+
+__global__ void k_validate(const int64_t* off, const int32_t* idx, int64_t n, int64_t m, int* bad) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = t0; i <= n; i += stride) {
+    const int64_t o = off[i];
+    bool ok = o >= 0 && o <= m;
+    if (i == 0) ok = ok && o == 0;
+    if (i == n) ok = ok && o == m;
+    if (i < n) ok = ok && off[i + 1] >= o;
+    if (!ok) atomicOr(bad, 1);
+  }
+  for (int64_t k = t0; k < m; k += stride) {
+    const int32_t w = idx[k];
+    if (w < 0 || (int64_t)w >= n) atomicOr(bad, 2);
+  }
+}
+
+int grid_for(int64_t work, int per_block, int cap) {
+  int64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  const size_t n16 = bytes / 16;
+  const size_t tail = bytes - n16 * 16;
+  hipLaunchKernelGGL(k_fill_zero, dim3(grid_for((int64_t)n16, 256 * 8, 65536)), dim3(256), 0, s,
+                     reinterpret_cast<uint4*>(p), n16, reinterpret_cast<uint8_t*>(p) + n16 * 16, tail);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_nodes(int log2m, int64_t n, uint64_t seed, uint8_t* cur, uint8_t* nxt,
+                             double* S, double* H, double* E, const double* lc, double alpha_pp,
+                             hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init_nodes, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, log2m, n, seed,
+                     cur, nxt, S, H, E, lc, alpha_pp);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass(int log2m, const PassArgs& a, hipStream_t s, hipEvent_t ev_mid) {
+  if (a.n_blocks == 0) return hipSuccess;
+  if (log2m <= 8) {
+    const int64_t grid = a.n_items + (a.n_blocks + 3) / 4;
+    switch (log2m) {
+      case 4: hipLaunchKernelGGL(k_expand<4>, dim3((unsigned)grid), dim3(256), 0, s, a); break;
+      case 5: hipLaunchKernelGGL(k_expand<5>, dim3((unsigned)grid), dim3(256), 0, s, a); break;
+      case 6: hipLaunchKernelGGL(k_expand<6>, dim3((unsigned)grid), dim3(256), 0, s, a); break;
+      case 7: hipLaunchKernelGGL(k_expand<7>, dim3((unsigned)grid), dim3(256), 0, s, a); break;
+      default: hipLaunchKernelGGL(k_expand<8>, dim3((unsigned)grid), dim3(256), 0, s, a); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (ev_mid) {
+      e = hipEventRecord(ev_mid, s);
+      if (e != hipSuccess) return e;
+    }
+    if (a.n_hrows > 0) {
+      const unsigned mg = (unsigned)((a.n_hrows + 3) / 4);
+      switch (log2m) {
+        case 4: hipLaunchKernelGGL(k_merge<4>, dim3(mg), dim3(256), 0, s, a); break;
+        case 5: hipLaunchKernelGGL(k_merge<5>, dim3(mg), dim3(256), 0, s, a); break;
+        case 6: hipLaunchKernelGGL(k_merge<6>, dim3(mg), dim3(256), 0, s, a); break;
+        case 7: hipLaunchKernelGGL(k_merge<7>, dim3(mg), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL(k_merge<8>, dim3(mg), dim3(256), 0, s, a); break;
+      }
+    }
+    return hipGetLastError();
+  }
+  const size_t lds = (size_t)1 << log2m;
+  if (lds > 32768) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_expand_wide),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_expand_wide, dim3((unsigned)a.n_blocks), dim3(256), lds, s, a, log2m);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (ev_mid) e = hipEventRecord(ev_mid, s);
+  return e;
+}
+
+hipError_t launch_finalize(int64_t n, const double* S, const double* H, const double* E, double* clo,
+                           double* lin, double* harm, double* core, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, S, H, E, clo, lin,
+                     harm, core);
+  return hipGetLastError();
+}
+
+hipError_t launch_widen_offsets(const int32_t* in, int64_t* out, int64_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_widen, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, in, out, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const int64_t* off, const int32_t* idx, int64_t n, int64_t m, int* bad,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(n + m + 1, 256, 16384)), dim3(256), 0, s, off, idx, n, m,
+                     bad);
+  return hipGetLastError();
+}
+
+}  // namespace hb

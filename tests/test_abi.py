@@ -1,0 +1,86 @@
+"""CPU checks of the C ABI boundary: the library loads, exports every entry
+point that include/hb.h declares, and rejects bad arguments on the host
+before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fname in os.listdir(os.path.join(ROOT, "include")):
+        if not fname.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fname)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(hb_[a-z_]+)\s*\(", text, re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("hb_init", "hb_iterate", "hb_centralities", "hb_free", "hb_run", "hb_reset",
+              "hb_get_registers", "hb_stats", "hb_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1308_2144_amd as hb
+
+    raw = ctypes.CDLL(hb.LIB_PATH)
+    missing = [n for n in sorted(declared_functions()) if not hasattr(raw, n)]
+    assert not missing, missing
+    assert hb.hb_version() == 1
+
+
+def test_host_side_argument_errors():
+    import paper_1308_2144_amd as hb
+
+    off = np.array([0, 1, 2], dtype=np.int64)
+    idx = np.array([1, 0], dtype=np.int32)
+    for b in (3, 17, -1):
+        with pytest.raises(hb.HBError) as e:
+            hb.hb_init(off, idx, b, 1)
+        assert e.value.status == hb.HB_EINVAL and "log2m" in str(e.value)
+    with pytest.raises(hb.HBError) as e:
+        hb.hb_init(np.array([0, 1, 3], dtype=np.int64), idx, 4, 1)   # offsets[n] != m
+    assert e.value.status == hb.HB_EINVAL
+    with pytest.raises(hb.HBError) as e:
+        hb.hb_init(np.array([1, 1, 2], dtype=np.int64), idx, 4, 1)   # offsets[0] != 0
+    assert e.value.status == hb.HB_EINVAL
+    L = hb.lib()
+    assert L.hb_init(None, None, 4, 1, None, None) == hb.HB_EINVAL
+    assert b"NULL" in L.hb_last_error()
+    ctx = ctypes.c_void_p()
+    assert L.hb_init(ctypes.byref(ctx), None, 4, 1, None, None) == hb.HB_EINVAL
+    # context-less calls fail cleanly, hb_free(NULL) is a no-op
+    assert L.hb_iterate(None, None) == hb.HB_EINVAL
+    assert L.hb_run(None, 0, None) == hb.HB_EINVAL
+    assert L.hb_centralities(None, None, None, None, None, 0) == hb.HB_EINVAL
+    assert L.hb_get_registers(None, None, 0) == hb.HB_EINVAL
+    assert L.hb_reset(None, 1) == hb.HB_EINVAL
+    L.hb_free(None)
+
+
+def test_default_options():
+    import paper_1308_2144_amd as hb
+
+    o = hb.default_options()
+    assert o.frontier == 1 and o.validate == 1 and o.timing == 0
+    assert 0 < o.light_max < o.heavy_min and o.chunk > 0
+    with pytest.raises(TypeError):
+        hb.default_options(nonsense=1)
+
+
+def test_binding_refuses_mixed_inputs():
+    import paper_1308_2144_amd as hb
+    import torch
+
+    with pytest.raises(TypeError):
+        hb.hb_init(torch.zeros(2, dtype=torch.int64), np.zeros(1, dtype=np.int32), 4, 1)

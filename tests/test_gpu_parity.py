@@ -1,0 +1,186 @@
+"""GPU parity: the HIP library against the oracle, element by element.
+
+Registers and pass counts must be bit-exact; FP64 accumulators and
+centralities must agree to 1e-12 relative (the implementation is designed to
+be bit-identical, and the checks below report any inexact entry).
+"""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from hbcheck import assert_fp, check, run_hb, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(*a):
+    print(*a, flush=True)
+
+
+def test_rmat_s10_undirected_p16():
+    # R-MAT scale 10, edge factor 8, undirected, int32 CSR, log2m = 4, seed 42.
+    off, idx = gg.rmat(10, 8, seed=1, directed=False)
+    _log("rmat s10 undirected n=1024 m=", len(idx))
+    got, ref = check(off.astype(np.int32), idx, 4, 42, "s10")
+    assert got["passes"] >= 3
+
+
+def random_cases():
+    yield "single", gg.empty(1)
+    yield "pair", gg.from_edges(2, [(0, 1)])
+    yield "self-loop", (np.array([0, 1], dtype=np.int64), np.array([0], dtype=np.int32))
+    yield "isolated100", gg.empty(100)
+    yield "cycle65", gg.directed_cycle(65)
+    yield "path130", gg.directed_path(130)
+    yield "star200", gg.star(200)
+    for s, (n, m) in enumerate([(63, 200), (64, 64), (65, 500), (200, 50), (1000, 8000), (3001, 30000)]):
+        yield f"rand{n}_{m}", gg.random_digraph(n, m, seed=10 + s, self_loops=bool(s % 2))
+    yield "rmat12t", gg.rmat(12, 16, seed=7, transpose=True, relabel=True)
+    yield "ba2000", gg.ba(2000, 4, seed=3)
+    yield "ws2000", gg.ws(2000, 10, 0.1, seed=3)
+
+
+@pytest.mark.parametrize("b", [4, 5, 6, 7, 8])
+def test_parity_small_graphs(b):
+    for name, (off, idx) in random_cases():
+        _log("case", name, "b", b)
+        check(off, idx, b, 1000 + b, f"{name}/b{b}")
+
+
+def test_duplicate_arcs_and_unsorted_rows():
+    # A CSR with repeated successors and unsorted rows is still a valid input.
+    off = np.array([0, 4, 6, 6, 9], dtype=np.int64)
+    idx = np.array([3, 1, 3, 1, 0, 0, 2, 1, 2], dtype=np.int32)
+    for b in (4, 7):
+        check(off, idx, b, 5, f"dups/b{b}")
+
+
+def test_every_pass_matches():
+    off, idx = gg.rmat(11, 8, seed=9, transpose=True, relabel=True)
+    full = run_oracle(off, idx, 6, 77)
+    for t in range(1, full["passes"] + 1):
+        _log("pass", t)
+        check(off, idx, 6, 77, f"t={t}", max_passes=t)
+
+
+@pytest.mark.parametrize("opts", [
+    dict(light_max=2, heavy_min=6, chunk=3),      # many heavy chunks
+    dict(light_max=1, heavy_min=100000),          # every row with 2+ arcs is medium
+    dict(light_max=4, heavy_min=40, chunk=17),
+    dict(frontier=0),
+    dict(frontier=0, light_max=2, heavy_min=6, chunk=5),
+])
+def test_parity_every_row_path(opts):
+    graphs = [("rmat11", gg.rmat(11, 16, seed=4, transpose=True)),
+              ("rmat10u", gg.rmat(10, 8, seed=5, directed=False)),
+              ("star300", gg.star(300))]
+    for name, (off, idx) in graphs:
+        for b in (4, 6, 8):
+            _log("opts", opts, name, "b", b)
+            check(off, idx, b, 31, f"{name}/b{b}/{opts}", **opts)
+
+
+@pytest.mark.parametrize("b,n,m", [(9, 300, 2000), (10, 200, 1500), (12, 90, 600)])
+def test_wide_counters(b, n, m):
+    off, idx = gg.random_digraph(n, m, seed=b)
+    check(off, idx, b, 11, f"wide b{b}")
+
+
+def test_exact_regime_p65536():
+    # p = 2^16, at most 48 nodes: linear counting is exact enough to recover
+    # distance sums; the GPU must match the oracle bit for bit here too.
+    for name, (off, idx) in [("cycle24", gg.directed_cycle(24)), ("grid", gg.grid(4, 6)),
+                             ("rand", gg.random_digraph(40, 120, seed=2))]:
+        check(off, idx, 16, 3, f"exact {name}")
+
+
+def test_device_inputs_borrowed():
+    import torch
+
+    off, idx = gg.rmat(12, 8, seed=12, transpose=True, relabel=True)
+    ref = run_oracle(off, idx, 7, 42)
+    for bits in (32, 64):
+        o = torch.from_numpy(off.astype(np.int32 if bits == 32 else np.int64)).cuda()
+        i = torch.from_numpy(idx).cuda()
+        got = run_hb(o, i, 7, 42)
+        assert got["passes"] == ref["passes"]
+        assert np.array_equal(got["regs"], ref["regs"])
+        assert_fp(got["S"], ref["S"], "S")
+        assert_fp(got["harmonic"], ref["harmonic"], "harmonic")
+        want = off.astype(np.int32 if bits == 32 else np.int64)
+        assert np.array_equal(o.cpu().numpy(), want)  # borrowed input left untouched
+
+
+def test_device_centralities_and_stream():
+    import torch
+
+    import paper_1308_2144_amd as hb
+
+    off, idx = gg.rmat(10, 8, seed=1, directed=False)
+    ref = run_oracle(off, idx, 5, 8)
+    s = torch.cuda.Stream()
+    with hb.HyperBall(off, idx, 5, 8, stream=s.cuda_stream) as g:
+        g.run()
+        cen = g.centralities(device=True)
+        for k in ("closeness", "lin", "harmonic", "coreach"):
+            assert_fp(cen[k].cpu().numpy(), ref[k], k)
+
+
+def test_edge_cases():
+    import paper_1308_2144_amd as hb
+
+    # n = 0
+    with hb.HyperBall(np.zeros(1, dtype=np.int64), np.zeros(0, dtype=np.int32), 4, 1) as g:
+        assert g.run() == 1 and g.iterate() == 0
+        assert g.registers().shape == (0, 16)
+    # converged contexts are inert; reset restarts with a new seed
+    off, idx = gg.rmat(9, 8, seed=2, transpose=True)
+    with hb.HyperBall(off, idx, 5, 100) as g:
+        T = g.run()
+        regs = g.registers()
+        S, H = g.accumulators()
+        assert g.iterate() == 0 and g.run() == T
+        assert np.array_equal(g.registers(), regs)
+        assert np.array_equal(g.accumulators()[0], S)
+        g.reset(101)
+        T2 = g.run()
+        ref = run_oracle(off, idx, 5, 101)
+        assert T2 == ref["passes"] and np.array_equal(g.registers(), ref["regs"])
+        assert_fp(g.accumulators()[0], ref["S"], "S after reset")
+
+
+def test_determinism():
+    off, idx = gg.rmat(12, 16, seed=21, transpose=True)
+    a = run_hb(off, idx, 6, 9, light_max=8, heavy_min=64, chunk=32)
+    b = run_hb(off, idx, 6, 9, light_max=8, heavy_min=64, chunk=32)
+    assert np.array_equal(a["regs"], b["regs"])
+    assert np.array_equal(a["S"], b["S"]) and np.array_equal(a["H"], b["H"])
+
+
+def test_pass_counters():
+    off, idx = gg.rmat(11, 8, seed=4, transpose=True)
+    m = len(idx)
+    on = run_hb(off, idx, 6, 3)
+    off_ = run_hb(off, idx, 6, 3, frontier=0)
+    for t, (a, b) in enumerate(zip(on["pass_stats"], off_["pass_stats"])):
+        assert a["arcs_scanned"] == m and b["arcs_scanned"] == m
+        assert b["counters_gathered"] == m              # frontier off gathers every arc
+        assert a["counters_gathered"] <= m
+        assert a["rows_changed"] == b["rows_changed"]
+        assert a["rows_written"] >= a["rows_changed"]
+    assert on["pass_stats"][0]["counters_gathered"] == m
+    assert sum(p["counters_gathered"] for p in on["pass_stats"]) < on["passes"] * m
+
+
+def test_validation_rejects_bad_indices():
+    import paper_1308_2144_amd as hb
+
+    off = np.array([0, 2, 3], dtype=np.int64)
+    for bad in ([0, 2, 1], [0, -1, 1]):
+        with pytest.raises(hb.HBError) as e:
+            hb.HyperBall(off, np.array(bad, dtype=np.int32), 4, 1)
+        assert e.value.status == hb.HB_EINVAL
+    with pytest.raises(hb.HBError) as e:
+        hb.HyperBall(np.array([0, 2, 1, 3], dtype=np.int64), np.array([0, 1, 2], dtype=np.int32), 4, 1)
+    assert e.value.status == hb.HB_EINVAL
