@@ -64,16 +64,18 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def pass_bytes(ps, n, m, p, n_hrows):
+def pass_bytes(ps, listed, p):
     """Algorithmic HBM bytes of one pass's expand kernel.
 
-    offsets 8 B/row, successor ids 4 B/arc, one p-byte counter per gathered
-    successor, own counter of every loaded row, every written counter, S/H/E
-    read+write for changed rows (48 B), both frontier bitmaps once (n/8 B
-    each).  The heavy rows' own loads are done by the merge kernel and are
-    left out."""
-    return (8 * n + 4 * m + p * ps["counters_gathered"] + p * max(ps["rows_loaded"] - n_hrows, 0)
-            + p * ps["rows_written"] + 48 * ps["rows_changed"] + 2 * (n // 8))
+    Every listed (non-empty) row: list entry, two offsets and its change-bit
+    word (28 B; plus its 4 B activation stamp in sparse passes).  Every row
+    that runs: own counter (p B) and the cached estimate and two accumulators
+    (24 B).  Every scanned arc: its successor id (4 B).  Every gathered
+    successor counter: p B.  Every written counter: p B.  Every changed row:
+    estimate and accumulators written back (24 B)."""
+    per_row = 28 + (4 if ps["mode"] == 2 else 0)
+    return (per_row * listed + (p + 24) * ps["rows_loaded"] + 4 * ps["arcs_scanned"]
+            + p * ps["counters_gathered"] + p * ps["rows_written"] + 24 * ps["rows_changed"])
 
 
 def cpu_baseline(w, seed):
@@ -108,6 +110,10 @@ def main():
     ap.add_argument("--heavy-min", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--frontier", type=int, default=1)
+    ap.add_argument("--dense-pct", type=int, default=-1)
+    ap.add_argument("--push", type=int, default=1)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 1 GiB device copy (torch) 3 times, to scale HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
@@ -129,9 +135,12 @@ def main():
     outs = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(4)]
     stream = torch.cuda.current_stream().cuda_stream
     g = hb.HyperBall(o_d, i_d, w["log2m"], seed, stream=stream, timing=1, frontier=args.frontier,
-                     light_max=args.light_max, heavy_min=args.heavy_min, chunk=args.chunk)
+                     light_max=args.light_max, heavy_min=args.heavy_min, chunk=args.chunk,
+                     dense_pct=args.dense_pct, push=args.push)
     st0 = g.stats()
-    log(f"rows: medium={st0['medium_rows']} heavy={st0['heavy_rows']} chunks={st0['heavy_chunks']}")
+    listed = st0["light_rows"] + st0["medium_rows"] + st0["heavy_rows"]
+    log(f"rows: light={st0['light_rows']} medium={st0['medium_rows']} heavy={st0['heavy_rows']} "
+        f"chunks={st0['heavy_chunks']} reverse={st0['reverse_built']}")
 
     def step():
         g.reset(seed)
@@ -153,7 +162,7 @@ def main():
         infos = [g.pass_stats(t) for t in range(passes)]
         for ps in infos:
             exp_ms += ps["expand_ms"]
-            exp_bytes += pass_bytes(ps, n, m, p, st0["heavy_rows"])
+            exp_bytes += pass_bytes(ps, listed, p)
             launches += 1
         if first is None:
             first = infos
@@ -161,14 +170,15 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = 1e3 * dt / args.steps
-    visits = m * sum(step_passes)
+    visits = m * sum(step_passes)  # every arc of every pass, as the paper counts time per arc
     value = visits / dt
 
     for t, ps in enumerate(first):
-        log(f"  pass {t:2d}: gathered={ps['counters_gathered']:>11d} loaded={ps['rows_loaded']:>9d} "
-            f"written={ps['rows_written']:>9d} changed={ps['rows_changed']:>9d} "
-            f"expand={ps['expand_ms']:.3f}ms merge={ps['merge_ms']:.3f}ms "
-            f"{pass_bytes(ps, n, m, p, st0['heavy_rows']) / (ps['expand_ms'] * 1e6):.0f} GB/s")
+        log(f"  pass {t:2d} mode {ps['mode']}: arcs={ps['arcs_scanned']:>10d} "
+            f"gathered={ps['counters_gathered']:>10d} loaded={ps['rows_loaded']:>8d} "
+            f"written={ps['rows_written']:>8d} changed={ps['rows_changed']:>8d} "
+            f"push={ps['push_ms']:.3f} expand={ps['expand_ms']:.3f} merge={ps['merge_ms']:.3f} ms "
+            f"{pass_bytes(ps, listed, p) / (ps['expand_ms'] * 1e6):.0f} GB/s")
 
     mean_ms = exp_ms / launches
     achieved = exp_bytes / launches / (mean_ms * 1e-3) / 1e9
@@ -194,12 +204,25 @@ def main():
                    "offsets": f"int{w['offsets']}"},
         "first_pass": {"ms": p0["expand_ms"] + p0["merge_ms"],
                        "edge_visits_per_s": m / ((p0["expand_ms"] + p0["merge_ms"]) * 1e-3),
-                       "GBps": pass_bytes(p0, n, m, p, st0["heavy_rows"]) / (p0["expand_ms"] * 1e6)},
+                       "GBps": pass_bytes(p0, listed, p) / (p0["expand_ms"] * 1e6)},
+        "arcs_scanned_per_s": sum(ps["arcs_scanned"] for ps in first) * len(step_passes) / dt,
         "roofline": roof,
     }
     g.close()
     del o_d, i_d, outs
     torch.cuda.empty_cache()
+    if args.copy_calib:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        cdt = (time.perf_counter() - t0) / 3
+        out["copy_calib"] = {"bytes_read": 1 << 30, "bytes_written": 1 << 30, "ms": cdt * 1e3,
+                             "GBps_rw": 2 * (1 << 30) / cdt / 1e9}
+        del src, dst
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle pass 0 ...")
         del off, idx

@@ -68,16 +68,24 @@ typedef struct {
 } hb_csr;
 
 /* Tuning and behaviour switches; hb_default_options fills the defaults.
- *   frontier   1: gather only successors whose counter changed in the
- *              previous pass (exact: an unchanged successor's counter is
- *              already contained in the node's own); 0: gather every arc.
- *   light_max  rows with at most this many arcs are handled by one lane group.
+ *   frontier   1: skip work the previous pass makes unnecessary (exact: a
+ *              successor whose counter did not change is already contained
+ *              in the node's own counter, and a node none of whose successors
+ *              changed cannot change); 0: every pass gathers every arc.
+ *   light_max  rows with 1..light_max arcs are handled by one lane group.
  *   heavy_min  rows with at least this many arcs are split into chunks of
  *              `chunk` arcs reduced by separate workgroups; rows in between
  *              are handled by a whole wavefront.  (<= 0: library default.)
  *   validate   1: check the CSR (offsets monotone and bounded, indices in
  *              range) at init and fail with HB_EINVAL if it is malformed.
- *   timing     1: time every pass's kernels with HIP events (hb_pass_info). */
+ *   timing     1: time every pass's kernels with HIP events (hb_pass_stats).
+ *   dense_pct  with the frontier on, a pass runs dense (every non-empty row,
+ *              every successor gathered, no per-arc test) when the previous
+ *              pass changed at least dense_pct percent of the non-empty rows,
+ *              sparse otherwise.  (< 0: library default.)
+ *   push       1: build the reverse CSR at init (m int32 + n+1 int64 more
+ *              device memory) so that sparse passes visit only rows with a
+ *              changed successor; 0: sparse passes visit every row. */
 typedef struct {
   int32_t frontier;
   int32_t light_max;
@@ -85,6 +93,8 @@ typedef struct {
   int32_t chunk;
   int32_t validate;
   int32_t timing;
+  int32_t dense_pct;
+  int32_t push;
 } hb_options;
 
 void hb_default_options(hb_options* opt);
@@ -141,25 +151,29 @@ typedef struct {
   int64_t heavy_rows;      /* rows split across workgroups */
   int64_t heavy_chunks;
   int64_t medium_rows;     /* rows handled by a whole wavefront */
+  int64_t light_rows;      /* rows handled by one lane group */
+  int32_t reverse_built;   /* 1 if the reverse CSR exists (push = 1) */
   double total_kernel_ms;  /* sum of timed pass kernels (timing = 1) */
 } hb_stats_t;
 
 hb_status hb_stats(hb_ctx* c, hb_stats_t* s);
 
 /* Per-pass record (pass in [0, passes)).  Work counters are exact:
- *   arcs_scanned       arcs whose successor id was read (every arc, every pass)
+ *   arcs_scanned       successor ids read (every arc of every row the pass runs)
  *   counters_gathered  successor counters read (p bytes each)
- *   rows_loaded        own counters read (rows with a gathered successor or
- *                      a counter changed in the previous pass)
+ *   rows_loaded        rows the pass ran (own counter read)
  *   rows_written       counters written into the next buffer
  *   rows_changed       counters that changed (= n_modified)
- *   expand_ms / merge_ms: kernel times from HIP events (timing = 1, else 0). */
+ *   mode               0 first pass, 1 dense, 2 sparse
+ *   push_ms / expand_ms / merge_ms: kernel times from HIP events (timing = 1). */
 typedef struct {
   int64_t arcs_scanned;
   int64_t counters_gathered;
   int64_t rows_loaded;
   int64_t rows_written;
   int64_t rows_changed;
+  int32_t mode;
+  double push_ms;
   double expand_ms;
   double merge_ms;
 } hb_pass_info;

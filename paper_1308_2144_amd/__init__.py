@@ -43,7 +43,8 @@ class hb_csr(ctypes.Structure):
 class hb_options(ctypes.Structure):
     _fields_ = [("frontier", ctypes.c_int32), ("light_max", ctypes.c_int32),
                 ("heavy_min", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("validate", ctypes.c_int32), ("timing", ctypes.c_int32)]
+                ("validate", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("dense_pct", ctypes.c_int32), ("push", ctypes.c_int32)]
 
 
 class hb_stats_t(ctypes.Structure):
@@ -51,13 +52,15 @@ class hb_stats_t(ctypes.Structure):
                 ("passes", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("last_modified", ctypes.c_int64), ("heavy_rows", ctypes.c_int64),
                 ("heavy_chunks", ctypes.c_int64), ("medium_rows", ctypes.c_int64),
+                ("light_rows", ctypes.c_int64), ("reverse_built", ctypes.c_int32),
                 ("total_kernel_ms", ctypes.c_double)]
 
 
 class hb_pass_info(ctypes.Structure):
     _fields_ = [("arcs_scanned", ctypes.c_int64), ("counters_gathered", ctypes.c_int64),
                 ("rows_loaded", ctypes.c_int64), ("rows_written", ctypes.c_int64),
-                ("rows_changed", ctypes.c_int64), ("expand_ms", ctypes.c_double),
+                ("rows_changed", ctypes.c_int64), ("mode", ctypes.c_int32),
+                ("push_ms", ctypes.c_double), ("expand_ms", ctypes.c_double),
                 ("merge_ms", ctypes.c_double)]
 
 

@@ -25,9 +25,10 @@ hb_status fail(hb_status st, const std::string& msg) {
     if (e_ != hipSuccess) return fail(HB_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int DEFAULT_LIGHT_MAX = 32;
+constexpr int DEFAULT_LIGHT_MAX = 64;
 constexpr int DEFAULT_HEAVY_MIN = 8192;
 constexpr int DEFAULT_CHUNK = 4096;
+constexpr int DEFAULT_DENSE_PCT = 10;
 
 // alpha_p of Flajolet-Fusy-Gandouet-Meunier 2007 (Algorithm 1 defers to it).
 double alpha_for(int p) {
@@ -69,6 +70,15 @@ struct hb_ctx {
   hb::HeavyRow* hrows = nullptr;
   int64_t n_hrows = 0;
   int64_t n_medium = 0;
+  int32_t* light = nullptr;
+  int32_t* medium = nullptr;
+  int64_t n_light = 0;
+  int64_t n_nonempty = 0;
+  int64_t* roff = nullptr;      // reverse CSR (push activation)
+  int32_t* ridx = nullptr;
+  int32_t* act = nullptr;
+  uint2* push_items = nullptr;
+  unsigned long long* push_count = nullptr;
   uint8_t* partial = nullptr;
   unsigned long long* stats = nullptr;       // 2 halves of STAT_SLOTS * STAT_K
   unsigned long long* stats_host = nullptr;  // pinned
@@ -78,7 +88,7 @@ struct hb_ctx {
   int32_t t = 0;
   bool converged = false;
   int64_t last_nmod = -1;
-  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hb_pass_info> hist;
   double total_ms = 0.0;
   bool failed = false;
@@ -98,6 +108,13 @@ void release(hb_ctx* c) {
   (void)hipFree(c->H);
   (void)hipFree(c->E);
   (void)hipFree(c->lc);
+  (void)hipFree(c->light);
+  (void)hipFree(c->medium);
+  (void)hipFree(c->roff);
+  (void)hipFree(c->ridx);
+  (void)hipFree(c->act);
+  (void)hipFree(c->push_items);
+  (void)hipFree(c->push_count);
   (void)hipFree(c->items);
   (void)hipFree(c->hrows);
   (void)hipFree(c->partial);
@@ -105,7 +122,7 @@ void release(hb_ctx* c) {
   (void)hipFree(c->out_tmp);
   (void)hipFree(c->bad);
   if (c->stats_host) (void)hipHostFree(c->stats_host);
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 4; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   delete c;
 }
@@ -116,16 +133,21 @@ hb_status check_ctx(hb_ctx* c) {
   return HB_OK;
 }
 
-// Classify rows by degree and cut heavy rows into chunks.
-void plan_rows(hb_ctx* c, const int64_t* off_host, std::vector<hb::HeavyItem>& items,
+// Classify the non-empty rows by degree (empty rows never change and are
+// left out of every pass) and cut heavy rows into chunks.
+void plan_rows(hb_ctx* c, const int64_t* off_host, std::vector<int32_t>& light,
+               std::vector<int32_t>& medium, std::vector<hb::HeavyItem>& items,
                std::vector<hb::HeavyRow>& hrows) {
   const int64_t lmax = c->opt.light_max, hmin = c->opt.heavy_min, chunk = c->opt.chunk;
-  c->n_medium = 0;
   for (int64_t v = 0; v < c->n; ++v) {
     const int64_t s = off_host[v], e = off_host[v + 1], deg = e - s;
-    if (deg <= lmax) continue;
+    if (deg == 0) continue;
+    if (deg <= lmax) {
+      light.push_back((int32_t)v);
+      continue;
+    }
     if (deg < hmin) {
-      ++c->n_medium;
+      medium.push_back((int32_t)v);
       continue;
     }
     hb::HeavyRow hr;
@@ -158,6 +180,7 @@ hb_status do_reset(hb_ctx* c, uint64_t seed) {
   HB_HIP(hb::launch_fill_zero(c->mod[1], (size_t)c->n_blocks * 8, c->stream));
   HB_HIP(hb::launch_fill_zero(c->stats, sizeof(unsigned long long) * 2 * hb::STAT_SLOTS * hb::STAT_K,
                               c->stream));
+  if (c->act) HB_HIP(hb::launch_fill_zero(c->act, sizeof(int32_t) * (size_t)c->n, c->stream));
   HB_HIP(hb::launch_init_nodes(c->b, c->n, seed, c->cnt[0], c->cnt[1], c->S, c->H, c->E, c->lc,
                                c->alpha_pp, c->stream));
   return HB_OK;
@@ -177,6 +200,7 @@ hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, co
   if (c->opt.light_max <= 0) c->opt.light_max = DEFAULT_LIGHT_MAX;
   if (c->opt.heavy_min <= 0) c->opt.heavy_min = DEFAULT_HEAVY_MIN;
   if (c->opt.chunk <= 0) c->opt.chunk = DEFAULT_CHUNK;
+  if (c->opt.dense_pct < 0) c->opt.dense_pct = DEFAULT_DENSE_PCT;
   if (c->opt.heavy_min <= c->opt.light_max) c->opt.heavy_min = c->opt.light_max + 1;
   const int64_t n = c->n, m = c->m;
   c->n_blocks = (n + 63) / 64;
@@ -228,19 +252,41 @@ hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, co
     HB_HIP(hipStreamSynchronize(c->stream));
   }
 
+  std::vector<int32_t> light, medium;
   std::vector<hb::HeavyItem> items;
   std::vector<hb::HeavyRow> hrows;
-  plan_rows(c, off_host.data(), items, hrows);
+  plan_rows(c, off_host.data(), light, medium, items, hrows);
+  c->n_light = (int64_t)light.size();
+  c->n_medium = (int64_t)medium.size();
   c->n_items = (int64_t)items.size();
   c->n_hrows = (int64_t)hrows.size();
+  c->n_nonempty = c->n_light + c->n_medium + c->n_hrows;
+  HB_HIP(dmalloc(&c->light, light.size()));
+  HB_HIP(dmalloc(&c->medium, medium.size()));
   HB_HIP(dmalloc(&c->items, items.size()));
   HB_HIP(dmalloc(&c->hrows, hrows.size()));
+  if (!light.empty())
+    HB_HIP(hipMemcpyAsync(c->light, light.data(), sizeof(int32_t) * light.size(), hipMemcpyHostToDevice,
+                          c->stream));
+  if (!medium.empty())
+    HB_HIP(hipMemcpyAsync(c->medium, medium.data(), sizeof(int32_t) * medium.size(), hipMemcpyHostToDevice,
+                          c->stream));
   if (!items.empty())
     HB_HIP(hipMemcpyAsync(c->items, items.data(), sizeof(hb::HeavyItem) * items.size(), hipMemcpyHostToDevice,
                           c->stream));
   if (!hrows.empty())
     HB_HIP(hipMemcpyAsync(c->hrows, hrows.data(), sizeof(hb::HeavyRow) * hrows.size(), hipMemcpyHostToDevice,
                           c->stream));
+
+  // Reverse CSR for push activation of sparse passes (lane-group kernels only).
+  if (c->opt.frontier && c->opt.push && c->p <= 256 && n > 0) {
+    if (dmalloc(&c->roff, (size_t)n + 1) != hipSuccess || dmalloc(&c->ridx, (size_t)m) != hipSuccess ||
+        dmalloc(&c->act, (size_t)n) != hipSuccess ||
+        dmalloc(&c->push_items, (size_t)n + (size_t)(m / hb::PUSH_CHUNK) + 1) != hipSuccess ||
+        dmalloc(&c->push_count, 1) != hipSuccess)
+      return fail(HB_ENOMEM, "cannot allocate the reverse CSR");
+    HB_HIP(hb::build_reverse(c->off, c->idx, n, m, c->roff, c->ridx, c->stream));
+  }
 
   // Counters, bitmaps, accumulators.
   const size_t cbytes = (size_t)n * (size_t)c->p;
@@ -257,7 +303,7 @@ hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, co
   HB_HIP(dmalloc(&c->stats, (size_t)2 * hb::STAT_SLOTS * hb::STAT_K));
   HB_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->stats_host),
                        sizeof(unsigned long long) * hb::STAT_SLOTS * hb::STAT_K, hipHostMallocDefault));
-  for (int i = 0; i < 3; ++i) HB_HIP(hipEventCreate(&c->ev[i]));
+  for (int i = 0; i < 4; ++i) HB_HIP(hipEventCreate(&c->ev[i]));
 
   // Estimator constants: alpha_p p^2 and the linear-counting table p ln(p/V).
   c->alpha_pp = (alpha_for(c->p) * (double)c->p) * (double)c->p;
@@ -282,6 +328,8 @@ void hb_default_options(hb_options* opt) {
   opt->chunk = DEFAULT_CHUNK;
   opt->validate = 1;
   opt->timing = 0;
+  opt->dense_pct = DEFAULT_DENSE_PCT;
+  opt->push = 1;
 }
 
 hb_status hb_init(hb_ctx** out, const hb_csr* g, int32_t log2m, uint64_t seed, const hb_options* opt,
@@ -341,6 +389,10 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
     c->last_nmod = 0;
     return HB_OK;
   }
+  const int32_t mode =
+      c->t == 0 ? hb::MODE_FIRST
+      : (!c->opt.frontier || 100 * c->last_nmod >= (int64_t)c->opt.dense_pct * c->n_nonempty) ? hb::MODE_DENSE
+                                                                                              : hb::MODE_SPARSE;
   hb::PassArgs a{};
   a.off = c->off;
   a.idx = c->idx;
@@ -352,9 +404,12 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
   a.H = c->H;
   a.E = c->E;
   a.lc = c->lc;
+  a.light = c->light;
+  a.medium = c->medium;
   a.items = c->items;
   a.hrows = c->hrows;
   a.partial = c->partial;
+  a.act = (mode == hb::MODE_SPARSE) ? c->act : nullptr;
   const size_t half = (size_t)hb::STAT_SLOTS * hb::STAT_K;
   a.stats = c->stats + (size_t)(c->t & 1) * half;
   a.stats_next = c->stats + (size_t)((c->t + 1) & 1) * half;
@@ -362,17 +417,22 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
   a.d = (double)(c->t + 1);
   a.n = c->n;
   a.n_blocks = c->n_blocks;
+  a.n_light = c->n_light;
+  a.n_medium = c->n_medium;
   a.n_items = c->n_items;
   a.n_hrows = c->n_hrows;
-  a.light_max = c->opt.light_max;
-  a.heavy_min = c->opt.heavy_min;
-  a.first = c->t == 0 ? 1 : 0;
-  a.gather_all = (c->t == 0 || !c->opt.frontier) ? 1 : 0;
+  a.epoch = c->t + 1;
+  a.mode = mode;
   const bool timing = c->opt.timing != 0;
   hipError_t e = hipSuccess;
   if (timing) e = hipEventRecord(c->ev[0], c->stream);
-  if (e == hipSuccess) e = hb::launch_pass(c->b, a, c->stream, timing ? c->ev[1] : nullptr);
-  if (e == hipSuccess && timing) e = hipEventRecord(c->ev[2], c->stream);
+  if (e == hipSuccess && a.act)
+    e = hb::launch_push(a.mod_prev, c->n_blocks, c->n, c->roff, c->ridx, c->push_items, c->push_count, c->act,
+                        a.epoch, c->stream);
+  if (e == hipSuccess) e = hb::launch_fill_zero(a.mod_cur, sizeof(uint64_t) * (size_t)c->n_blocks, c->stream);
+  if (e == hipSuccess && timing) e = hipEventRecord(c->ev[1], c->stream);
+  if (e == hipSuccess) e = hb::launch_pass(c->b, a, c->stream, timing ? c->ev[2] : nullptr);
+  if (e == hipSuccess && timing) e = hipEventRecord(c->ev[3], c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->stats_host, a.stats, sizeof(unsigned long long) * half, hipMemcpyDeviceToHost,
                        c->stream);
@@ -381,21 +441,24 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
     c->failed = true;
     return fail(HB_EDEVICE, std::string("pass ") + std::to_string(c->t) + ": " + hipGetErrorString(e));
   }
-  unsigned long long sum[hb::STAT_K] = {0, 0, 0, 0};
+  unsigned long long sum[hb::STAT_K] = {0, 0, 0, 0, 0};
   for (int s = 0; s < hb::STAT_SLOTS; ++s)
     for (int k = 0; k < hb::STAT_K; ++k) sum[k] += c->stats_host[s * hb::STAT_K + k];
-  info.arcs_scanned = c->m;
   info.counters_gathered = (int64_t)sum[0];
   info.rows_loaded = (int64_t)sum[1];
   info.rows_written = (int64_t)sum[2];
   info.rows_changed = (int64_t)sum[3];
+  info.arcs_scanned = (int64_t)sum[4];
+  info.mode = mode;
   if (timing) {
-    float ms1 = 0.f, ms2 = 0.f;
-    (void)hipEventElapsedTime(&ms1, c->ev[0], c->ev[1]);
-    (void)hipEventElapsedTime(&ms2, c->ev[1], c->ev[2]);
+    float ms0 = 0.f, ms1 = 0.f, ms2 = 0.f;
+    (void)hipEventElapsedTime(&ms0, c->ev[0], c->ev[1]);
+    (void)hipEventElapsedTime(&ms1, c->ev[1], c->ev[2]);
+    (void)hipEventElapsedTime(&ms2, c->ev[2], c->ev[3]);
+    info.push_ms = ms0;
     info.expand_ms = ms1;
     info.merge_ms = ms2;
-    c->total_ms += (double)ms1 + (double)ms2;
+    c->total_ms += (double)ms0 + (double)ms1 + (double)ms2;
   }
   c->hist.push_back(info);
   c->cur ^= 1;
@@ -476,6 +539,8 @@ hb_status hb_stats(hb_ctx* c, hb_stats_t* s) {
   s->heavy_rows = c->n_hrows;
   s->heavy_chunks = c->n_items;
   s->medium_rows = c->n_medium;
+  s->light_rows = c->n_light;
+  s->reverse_built = c->roff ? 1 : 0;
   s->total_kernel_ms = c->total_ms;
   return HB_OK;
 }

@@ -26,11 +26,22 @@ struct HeavyItem {
 // Number of slots the per-pass work counters are spread over (atomics to a
 // single address would serialise); STAT_K counters per slot.
 constexpr int STAT_SLOTS = 256;
-constexpr int STAT_K = 4;  // gathered, loaded, written, changed
+constexpr int STAT_K = 5;  // gathered, loaded, written, changed, arcs scanned
+
+// Reverse-CSR entries handled by one push item.
+constexpr int PUSH_CHUNK = 2048;
+
+// How a pass treats the previous pass's change bits.
+enum PassMode : int32_t {
+  MODE_FIRST = 0,   // pass 0: nothing changed before; every successor is gathered
+  MODE_DENSE = 1,   // every listed row runs and gathers every successor
+  MODE_SPARSE = 2,  // only rows with a changed successor (or a changed own
+                    // counter) run, and they gather only changed successors
+};
 
 // Everything one pass needs.  `cur` holds counters of radius t, `nxt`
 // receives radius t+1.  mod_prev has bit v set if counter v changed in the
-// previous pass; mod_cur receives this pass's bits (every word is written).
+// previous pass; mod_cur (zeroed before the pass) receives this pass's bits.
 struct PassArgs {
   const int64_t* off;
   const int32_t* idx;
@@ -41,22 +52,25 @@ struct PassArgs {
   double* S;
   double* H;
   double* E;
-  const double* lc;  // linear-counting table, entries 0..p
+  const double* lc;                  // linear-counting table, entries 0..p
+  const int32_t* light;              // rows with 1..light_max arcs, increasing
+  const int32_t* medium;             // rows handled by a whole wavefront
   const HeavyItem* items;
   const HeavyRow* hrows;
   uint8_t* partial;                  // n_items * p bytes
+  const int32_t* act;                // act[v] == epoch: v has a changed successor (sparse)
   unsigned long long* stats;         // this pass: STAT_SLOTS * STAT_K
   unsigned long long* stats_next;    // zeroed by this pass for the next one
   double alpha_pp;                   // (alpha_p * p) * p
   double d;                          // t + 1
   int64_t n;
   int64_t n_blocks;                  // ceil(n / 64)
+  int64_t n_light;
+  int64_t n_medium;
   int64_t n_items;
   int64_t n_hrows;
-  int32_t light_max;
-  int32_t heavy_min;
-  int32_t gather_all;                // pass 0 or frontier off
-  int32_t first;                     // pass 0: no previous-pass bits exist
+  int32_t epoch;
+  int32_t mode;                      // PassMode
 };
 
 // Launchers (hb_kernels.hip).  All return the launch status.
@@ -64,6 +78,7 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_init_nodes(int log2m, int64_t n, uint64_t seed, uint8_t* cur, uint8_t* nxt,
                              double* S, double* H, double* E, const double* lc, double alpha_pp,
                              hipStream_t s);
+// ev_mid (nullable) is recorded between the expand and merge kernels.
 hipError_t launch_pass(int log2m, const PassArgs& a, hipStream_t s, hipEvent_t ev_mid);
 hipError_t launch_finalize(int64_t n, const double* S, const double* H, const double* E,
                            double* clo, double* lin, double* harm, double* core, hipStream_t s);
@@ -71,5 +86,16 @@ hipError_t launch_widen_offsets(const int32_t* in, int64_t* out, int64_t count, 
 // Writes 1 to *bad if the CSR is malformed (bad must be zeroed first).
 hipError_t launch_validate(const int64_t* off, const int32_t* idx, int64_t n, int64_t m,
                            int* bad, hipStream_t s);
+
+// Reverse CSR (row w lists every v with an arc v->w).  roff: n+1 entries,
+// ridx: m entries.  Needs n+1 scratch counters (zeroed here) and hipcub scan
+// storage; both are allocated and freed inside.
+hipError_t build_reverse(const int64_t* off, const int32_t* idx, int64_t n, int64_t m, int64_t* roff,
+                         int32_t* ridx, hipStream_t s);
+// Marks act[v] = epoch for every v with an arc to a node whose bit is set in
+// mod_prev.  items/count are scratch (capacity `cap` items; count zeroed here).
+hipError_t launch_push(const uint64_t* mod_prev, int64_t n_words, int64_t n, const int64_t* roff,
+                       const int32_t* ridx, uint2* items, unsigned long long* count, int32_t* act,
+                       int32_t epoch, hipStream_t s);
 
 }  // namespace hb

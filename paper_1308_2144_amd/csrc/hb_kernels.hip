@@ -32,6 +32,8 @@
 //
 // There is no dense contraction here: the pass is a gather of p-byte rows and
 // byte-wise maxima, bound by HBM bandwidth, so no MFMA is involved.
+#include <hipcub/hipcub.hpp>
+
 #include "hb_internal.h"
 
 namespace hb {
@@ -177,6 +179,19 @@ __device__ __forceinline__ double estimate(double big, double small, int V, doub
   return E;
 }
 
+__device__ __forceinline__ bool bit_of(const uint64_t* bm, int64_t v) {
+  return ((bm[v >> 6] >> (v & 63)) & 1ull) != 0ull;
+}
+
+// own_mod: the row's counter changed in the previous pass (so the next buffer
+// holds a stale copy).  need: the row takes part in this pass.  In a sparse
+// pass a row without a changed successor cannot change; it only runs to
+// refresh a stale copy.
+__device__ __forceinline__ void row_flags(const PassArgs& A, int64_t row, bool& own_mod, bool& need) {
+  own_mod = A.mode != MODE_FIRST && bit_of(A.mod_prev, row);
+  need = A.mode != MODE_SPARSE || own_mod || A.act == nullptr || A.act[row] == A.epoch;
+}
+
 // Gather-max over the arcs k, k+st, k+2st, ... < e of a row: every lane of
 // the group loads its 16-byte slice of each selected successor counter.
 // `got` is set if at least one counter was gathered; `ngath` counts them.
@@ -186,6 +201,7 @@ __device__ __forceinline__ uint4 gather(const PassArgs& A, int64_t k, int64_t e,
   constexpr int P = 1 << B;
   SplitAcc acc{zero4(), zero4()};
   const uint8_t* base = A.cur + gl * 16;
+  const bool all = A.mode != MODE_SPARSE;
   for (; k < e; k += st * U) {
     int32_t w[U];
 #pragma unroll
@@ -197,7 +213,7 @@ __device__ __forceinline__ uint4 gather(const PassArgs& A, int64_t k, int64_t e,
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int32_t ws = w[u] < 0 ? 0 : w[u];
-      const bool bit = A.gather_all ? true : (((A.mod_prev[ws >> 6] >> (ws & 63)) & 1ull) != 0ull);
+      const bool bit = all ? true : bit_of(A.mod_prev, ws);
       m[u] = (w[u] >= 0) && bit;
     }
     uint4 v[U];
@@ -216,27 +232,52 @@ __device__ __forceinline__ uint4 gather(const PassArgs& A, int64_t k, int64_t e,
   return unsplit(acc);
 }
 
+// What a row needs besides its successors, loaded before the gather so the
+// loads overlap: the lane's slice of the own counter and, in the group's
+// first lane, the cached estimate and the two accumulators.
+struct RowPre {
+  uint4 own;
+  double e, s, h;
+};
+
+template <int B>
+__device__ __forceinline__ RowPre preload(const PassArgs& A, int64_t row, int gl) {
+  constexpr int P = 1 << B;
+  RowPre r;
+  r.own = *reinterpret_cast<const uint4*>(A.cur + (size_t)row * P + (size_t)gl * 16);
+  r.e = r.s = r.h = 0.0;
+  if (gl == 0) {
+    r.e = A.E[row];
+    r.s = A.S[row];
+    r.h = A.H[row];
+  }
+  return r;
+}
+
+struct Counts {
+  uint32_t gath, load, write, chg, arcs;
+};
+
 // Completes row `row` for a group of G lanes: a = own U gathered, write-back
-// rule, change detection and the fused estimator/accumulator.  Returns
-// whether the counter changed (uniform over the group).
+// rule, change detection, the fused estimator/accumulator and the change
+// bit.  Returns whether the counter changed (uniform over the group).
 template <int B>
 __device__ __forceinline__ bool finish_row(const PassArgs& A, int64_t row, uint4 acc, bool got,
-                                           bool own_mod, int gl, int grp, uint32_t& nload,
-                                           uint32_t& nwrite) {
+                                           const RowPre& pre, bool own_mod, int gl, int grp,
+                                           Counts& c) {
   constexpr int P = 1 << B;
   constexpr int G = P / 16;
   const size_t off = (size_t)row * P + (size_t)gl * 16;
-  uint4 own = zero4();
-  if (got || own_mod) own = *reinterpret_cast<const uint4*>(A.cur + off);
-  const uint4 a = got ? bmax(acc, own) : own;
-  const bool diff = got && differs(a, own);
+  const uint4 a = got ? bmax(acc, pre.own) : pre.own;
+  const bool diff = got && differs(a, pre.own);
   const uint64_t bal = __ballot(diff);
   const uint64_t gmask = (G >= 64) ? ~0ull : (((1ull << G) - 1ull) << (grp * G));
   const bool changed = (bal & gmask) != 0ull;
   if (changed || own_mod) *reinterpret_cast<uint4*>(A.nxt + off) = a;
   if (gl == 0) {
-    nload += (got || own_mod) ? 1u : 0u;
-    nwrite += (changed || own_mod) ? 1u : 0u;
+    c.load += 1u;
+    c.write += (changed || own_mod) ? 1u : 0u;
+    c.chg += changed ? 1u : 0u;
   }
   if (changed) {
     const Parts pr = reg_parts(a);
@@ -250,94 +291,114 @@ __device__ __forceinline__ bool finish_row(const PassArgs& A, int64_t row, uint4
     }
     if (gl == 0) {
       const double En = estimate(big, small, V, A.alpha_pp, (double)P, A.lc);
-      const double delta = En - A.E[row];
-      A.S[row] = A.S[row] + A.d * delta;
-      A.H[row] = A.H[row] + delta / A.d;
+      const double delta = En - pre.e;
+      A.S[row] = pre.s + A.d * delta;
+      A.H[row] = pre.h + delta / A.d;
       A.E[row] = En;
+      atomicOr(A.mod_cur + (row >> 6), 1ull << (row & 63));
     }
   }
   return changed;
 }
 
 __device__ __forceinline__ void add_stats(unsigned long long* st, uint32_t g, uint32_t l, uint32_t w,
-                                          uint32_t c) {
+                                          uint32_t c, unsigned long long a) {
   if (g) atomicAdd(st + 0, (unsigned long long)g);
   if (l) atomicAdd(st + 1, (unsigned long long)l);
   if (w) atomicAdd(st + 2, (unsigned long long)w);
   if (c) atomicAdd(st + 3, (unsigned long long)c);
+  if (a) atomicAdd(st + 4, (unsigned long long)a);
 }
 
+__device__ __forceinline__ void flush_counts(const PassArgs& A, Counts c, int64_t slot, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    c.gath += __shfl_xor(c.gath, o);
+    c.load += __shfl_xor(c.load, o);
+    c.write += __shfl_xor(c.write, o);
+    c.chg += __shfl_xor(c.chg, o);
+    c.arcs += __shfl_xor(c.arcs, o);
+  }
+  if (lane == 0) add_stats(A.stats + (slot & (STAT_SLOTS - 1)) * STAT_K, c.gath, c.load, c.write, c.chg, c.arcs);
+}
+
+// 64 consecutive entries of the light-row list per wavefront; entry
+// q*W + grp goes to lane group grp in round q.
 template <int B>
-__device__ __forceinline__ void light_block(const PassArgs& A, int64_t blk, int lane) {
+__device__ __forceinline__ void light_wave(const PassArgs& A, int64_t lw, int lane) {
   constexpr int P = 1 << B;
   constexpr int G = P / 16;
   constexpr int W = 64 / G;
   const int gl = lane % G;
   const int grp = lane / G;
-  const int64_t r0 = blk * 64;
-  const int64_t row = r0 + lane;
-  const bool valid = row < A.n;
-  int64_t s = 0, deg = 0;
-  if (valid) {
+  const int64_t i = lw * 64 + lane;
+  int64_t row = 0, s = 0, deg = 0;
+  bool own_mod = false, need = false;
+  if (i < A.n_light) {
+    row = A.light[i];
     s = A.off[row];
     deg = A.off[row + 1] - s;
+    row_flags(A, row, own_mod, need);
   }
-  const uint64_t own_word = A.first ? 0ull : A.mod_prev[blk];
-  uint64_t bits = 0;
-  uint32_t ngath = 0, nload = 0, nwrite = 0;
-
-  // Light rows: row q*W + grp goes to group grp in round q.
-  for (int q = 0; q < G; ++q) {
-    const int rl = q * W + grp;
-    const int64_t rs = __shfl(s, rl);
-    const int64_t rd = __shfl(deg, rl);
-    const int64_t rrow = r0 + rl;
-    if (rrow < A.n && rd <= A.light_max) {
-      const bool own_mod = ((own_word >> rl) & 1ull) != 0ull;
-      bool got = false;
-      uint32_t g = 0;
-      const uint4 acc = gather<B>(A, rs, rs + rd, 1, gl, got, g);
-      if (gl == 0) ngath += g;
-      if (finish_row<B>(A, rrow, acc, got, own_mod, gl, grp, nload, nwrite) && gl == 0)
-        bits |= 1ull << rl;
+  const uint64_t needs = __ballot(need);
+  const uint64_t mods = __ballot(own_mod);
+  Counts c{0u, 0u, 0u, 0u, 0u};
+  if (needs) {
+    for (int q = 0; q < G; ++q) {
+      const int rl = q * W + grp;
+      const int64_t rrow = __shfl(row, rl);
+      const int64_t rs = __shfl(s, rl);
+      const int64_t rd = __shfl(deg, rl);
+      if ((needs >> rl) & 1ull) {
+        const bool rmod = ((mods >> rl) & 1ull) != 0ull;
+        const RowPre pre = preload<B>(A, rrow, gl);
+        bool got = false;
+        uint32_t g = 0;
+        const uint4 acc = gather<B>(A, rs, rs + rd, 1, gl, got, g);
+        if (gl == 0) {
+          c.gath += g;
+          c.arcs += (uint32_t)rd;
+        }
+        finish_row<B>(A, rrow, acc, got, pre, rmod, gl, grp, c);
+      }
     }
   }
+  flush_counts(A, c, lw, lane);
+}
 
-  // Medium rows: the whole wavefront, groups striding over the arcs.
-  uint64_t mm = __ballot(valid && deg > A.light_max && deg < A.heavy_min);
-  while (mm) {
-    const int rl = __builtin_ctzll(mm);
-    mm &= mm - 1ull;
-    const int64_t rs = __shfl(s, rl);
-    const int64_t rd = __shfl(deg, rl);
+// One medium row per wavefront: the groups stride over its arcs and reduce
+// their partial maxima by shuffles.
+template <int B>
+__device__ __forceinline__ void medium_wave(const PassArgs& A, int64_t mi, int lane) {
+  constexpr int P = 1 << B;
+  constexpr int G = P / 16;
+  constexpr int W = 64 / G;
+  const int gl = lane % G;
+  const int grp = lane / G;
+  const int64_t row = A.medium[mi];
+  const int64_t s = A.off[row];
+  const int64_t deg = A.off[row + 1] - s;
+  bool own_mod, need;
+  row_flags(A, row, own_mod, need);
+  Counts c{0u, 0u, 0u, 0u, 0u};
+  if (need) {
+    RowPre pre;
+    if (grp == 0) pre = preload<B>(A, row, gl);
     bool got = false;
     uint32_t g = 0;
-    uint4 acc = gather<B>(A, rs + grp, rs + rd, W, gl, got, g);
-    if (gl == 0) ngath += g;
+    uint4 acc = gather<B>(A, s + grp, s + deg, W, gl, got, g);
+    if (gl == 0) c.gath += g;
+    if (lane == 0) c.arcs += (uint32_t)deg;
 #pragma unroll
     for (int o = G; o < 64; o <<= 1) acc = bmax(acc, shfl_xor4(acc, o));
     got = __ballot(got) != 0ull;
-    if (grp == 0) {
-      const bool own_mod = ((own_word >> rl) & 1ull) != 0ull;
-      if (finish_row<B>(A, r0 + rl, acc, got, own_mod, gl, 0, nload, nwrite) && gl == 0)
-        bits |= 1ull << rl;
-    }
+    if (grp == 0) finish_row<B>(A, row, acc, got, pre, own_mod, gl, 0, c);
   }
-
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    bits |= __shfl_xor(bits, o);
-    ngath += __shfl_xor(ngath, o);
-    nload += __shfl_xor(nload, o);
-    nwrite += __shfl_xor(nwrite, o);
-  }
-  if (lane == 0) {
-    A.mod_cur[blk] = bits;
-    add_stats(A.stats + (blk & (STAT_SLOTS - 1)) * STAT_K, ngath, nload, nwrite,
-              (uint32_t)__popcll(bits));
-  }
+  flush_counts(A, c, mi, lane);
 }
 
+// One chunk of a heavy row per workgroup (4 wavefronts, 4W lane groups):
+// writes the chunk's partial maximum for the merge kernel.
 template <int B>
 __device__ __forceinline__ void heavy_chunk(const PassArgs& A, int64_t item, int lane, int wave) {
   constexpr int P = 1 << B;
@@ -347,16 +408,17 @@ __device__ __forceinline__ void heavy_chunk(const PassArgs& A, int64_t item, int
   const int gl = lane % G;
   const int grp = lane / G;
   const HeavyItem it = A.items[item];
+  bool own_mod, need;
+  row_flags(A, it.row, own_mod, need);
+  if (!need) return;  // uniform over the workgroup; the merge kernel skips the row too
   bool got = false;
   uint32_t g = 0;
   uint4 acc = gather<B>(A, it.e0 + wave * W + grp, it.e1, 4 * W, gl, got, g);
 #pragma unroll
   for (int o = G; o < 64; o <<= 1) acc = bmax(acc, shfl_xor4(acc, o));
   if (grp == 0) red[wave][gl] = acc;
-  uint32_t ng = (gl == 0) ? g : 0u;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) ng += __shfl_xor(ng, o);
-  if (lane == 0) add_stats(A.stats + (item & (STAT_SLOTS - 1)) * STAT_K, ng, 0, 0, 0);
+  Counts c{(gl == 0) ? g : 0u, 0u, 0u, 0u, (lane == 0 && wave == 0) ? (uint32_t)(it.e1 - it.e0) : 0u};
+  flush_counts(A, c, item, lane);
   __syncthreads();
   if (wave == 0 && grp == 0) {
     uint4 a = red[0][gl];
@@ -367,18 +429,28 @@ __device__ __forceinline__ void heavy_chunk(const PassArgs& A, int64_t item, int
   }
 }
 
+// Grid: [heavy chunks][medium rows, 4 per workgroup][light rows, 256 per workgroup].
 template <int B>
 __global__ __launch_bounds__(256) void k_expand(PassArgs A) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   if (blockIdx.x == 0)
     for (int i = threadIdx.x; i < STAT_SLOTS * STAT_K; i += blockDim.x) A.stats_next[i] = 0ull;
-  if ((int64_t)blockIdx.x < A.n_items) {
-    heavy_chunk<B>(A, blockIdx.x, lane, wave);
+  int64_t b = blockIdx.x;
+  if (b < A.n_items) {
+    heavy_chunk<B>(A, b, lane, wave);
     return;
   }
-  const int64_t blk = ((int64_t)blockIdx.x - A.n_items) * 4 + wave;
-  if (blk < A.n_blocks) light_block<B>(A, blk, lane);
+  b -= A.n_items;
+  const int64_t med_wgs = (A.n_medium + 3) / 4;
+  if (b < med_wgs) {
+    const int64_t mi = b * 4 + wave;
+    if (mi < A.n_medium) medium_wave<B>(A, mi, lane);
+    return;
+  }
+  b -= med_wgs;
+  const int64_t lw = b * 4 + wave;
+  if (lw * 64 < A.n_light) light_wave<B>(A, lw, lane);
 }
 
 // Folds the partial counters of every heavy row into the row (one wavefront
@@ -395,22 +467,20 @@ __global__ __launch_bounds__(256) void k_merge(PassArgs A) {
   const int64_t h = (int64_t)blockIdx.x * 4 + wave;
   if (h >= A.n_hrows) return;
   const HeavyRow hr = A.hrows[h];
+  bool own_mod, need;
+  row_flags(A, hr.row, own_mod, need);
+  if (!need) return;
+  RowPre pre;
+  if (grp == 0) pre = preload<B>(A, hr.row, gl);
   uint4 acc = zero4();
   for (int64_t j = grp; j < hr.nitems; j += W)
     acc = bmax(acc, *reinterpret_cast<const uint4*>(A.partial + (size_t)(hr.item0 + j) * P +
                                                     (size_t)gl * 16));
 #pragma unroll
   for (int o = G; o < 64; o <<= 1) acc = bmax(acc, shfl_xor4(acc, o));
-  if (grp == 0) {
-    const bool own_mod =
-        A.first ? false : (((A.mod_prev[hr.row >> 6] >> (hr.row & 63)) & 1ull) != 0ull);
-    uint32_t nload = 0, nwrite = 0;
-    const bool changed = finish_row<B>(A, hr.row, acc, true, own_mod, gl, 0, nload, nwrite);
-    if (gl == 0) {
-      if (changed) atomicOr(A.mod_cur + (hr.row >> 6), 1ull << (hr.row & 63));
-      add_stats(A.stats + (h & (STAT_SLOTS - 1)) * STAT_K, 0, nload, nwrite, changed ? 1u : 0u);
-    }
-  }
+  Counts c{0u, 0u, 0u, 0u, 0u};
+  if (grp == 0) finish_row<B>(A, hr.row, acc, true, pre, own_mod, gl, 0, c);
+  flush_counts(A, c, h, lane);
 }
 
 // Counters wider than 256 bytes: one workgroup per 64-row block, rows in
@@ -428,9 +498,11 @@ __global__ __launch_bounds__(256) void k_expand_wide(PassArgs A, int log2m) {
     for (int i = tid; i < STAT_SLOTS * STAT_K; i += blockDim.x) A.stats_next[i] = 0ull;
   const int64_t blk = blockIdx.x;
   const int64_t r0 = blk * 64;
-  const uint64_t own_word = A.first ? 0ull : A.mod_prev[blk];
+  const uint64_t own_word = A.mode == MODE_FIRST ? 0ull : A.mod_prev[blk];
+  const bool all = A.mode != MODE_SPARSE;
   uint64_t bits = 0;
   uint32_t ngath = 0, nload = 0, nwrite = 0;
+  unsigned long long narcs = 0;
   for (int rl = 0; rl < 64; ++rl) {
     const int64_t row = r0 + rl;
     if (row >= A.n) break;
@@ -439,11 +511,12 @@ __global__ __launch_bounds__(256) void k_expand_wide(PassArgs A, int log2m) {
     int mine = 0;
     for (int64_t k = s + tid; k < e; k += 256) {
       const int32_t w = A.idx[k];
-      if (A.gather_all || ((A.mod_prev[w >> 6] >> (w & 63)) & 1ull)) ++mine;
+      if (all || bit_of(A.mod_prev, w)) ++mine;
     }
     const int ngot = __syncthreads_count(mine);
     const bool got = ngot > 0;
     ngath += (uint32_t)ngot;
+    narcs += (unsigned long long)(e - s);
     if (!got && !own_mod) continue;
     ++nload;
     int diff = 0;
@@ -453,7 +526,7 @@ __global__ __launch_bounds__(256) void k_expand_wide(PassArgs A, int log2m) {
       if (got)
         for (int64_t k = s; k < e; ++k) {
           const int32_t w = A.idx[k];
-          if (A.gather_all || ((A.mod_prev[w >> 6] >> (w & 63)) & 1ull))
+          if (all || bit_of(A.mod_prev, w))
             a = bmax(a, *reinterpret_cast<const uint4*>(A.cur + (size_t)w * P + (size_t)c * 16));
         }
       diff |= differs(a, own) ? 1 : 0;
@@ -500,7 +573,7 @@ __global__ __launch_bounds__(256) void k_expand_wide(PassArgs A, int log2m) {
   if (tid == 0) {
     A.mod_cur[blk] = bits;
     add_stats(A.stats + (blk & (STAT_SLOTS - 1)) * STAT_K, ngath, nload, nwrite,
-              (uint32_t)__popcll(bits));
+              (uint32_t)__popcll(bits), narcs);
   }
 }
 
@@ -569,6 +642,76 @@ __global__ void k_validate(const int64_t* off, const int32_t* idx, int64_t n, in
   }
 }
 
+// --- reverse CSR and push activation ---------------------------------------
+
+__global__ void k_count_in(const int32_t* idx, int64_t m, unsigned long long* cnt) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride)
+    atomicAdd(cnt + idx[e], 1ull);
+}
+
+// One wavefront per row (grid-stride): every arc v->w appends v to row w.
+__global__ void k_scatter_rev(const int64_t* off, const int32_t* idx, int64_t n,
+                              unsigned long long* cursor, int32_t* ridx) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); v < n; v += nw) {
+    const int64_t e1 = off[v + 1];
+    for (int64_t e = off[v] + lane; e < e1; e += 64) {
+      const unsigned long long pos = atomicAdd(cursor + idx[e], 1ull);
+      ridx[pos] = (int32_t)v;
+    }
+  }
+}
+
+// One thread per bitmap word: every set bit w (a counter changed in the
+// previous pass) becomes ceil(rdeg(w)/PUSH_CHUNK) items.  Slots are reserved
+// with one atomic per wavefront.
+__global__ void k_push_items(const uint64_t* mod_prev, int64_t n_words, int64_t n, const int64_t* roff,
+                             uint2* items, unsigned long long* count) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t word = i < n_words ? mod_prev[i] : 0ull;
+  uint32_t mine = 0;
+  for (uint64_t bits = word; bits; bits &= bits - 1ull) {
+    const int64_t w = i * 64 + __builtin_ctzll(bits);
+    if (w < n) mine += (uint32_t)((roff[w + 1] - roff[w] + PUSH_CHUNK - 1) / PUSH_CHUNK);
+  }
+  uint32_t incl = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  const uint32_t total = __shfl(incl, 63);
+  unsigned long long base = 0;
+  if (lane == 63 && total) base = atomicAdd(count, (unsigned long long)total);
+  base = __shfl(base, 63);
+  unsigned long long pos = base + incl - mine;
+  for (uint64_t bits = word; bits; bits &= bits - 1ull) {
+    const int64_t w = i * 64 + __builtin_ctzll(bits);
+    if (w >= n) continue;
+    const uint32_t k = (uint32_t)((roff[w + 1] - roff[w] + PUSH_CHUNK - 1) / PUSH_CHUNK);
+    for (uint32_t c = 0; c < k; ++c) items[pos++] = make_uint2((uint32_t)w, c);
+  }
+}
+
+// Grid-stride over the items: one wavefront stamps act[v] = epoch for the
+// (at most PUSH_CHUNK) predecessors of one item.
+__global__ void k_push_apply(const uint2* items, const unsigned long long* count, const int64_t* roff,
+                             const int32_t* ridx, int32_t* act, int32_t epoch) {
+  const int lane = threadIdx.x & 63;
+  const int64_t total = (int64_t)*count;
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t it = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); it < total; it += nw) {
+    const uint2 item = items[it];
+    const int64_t e0 = roff[item.x] + (int64_t)item.y * PUSH_CHUNK;
+    const int64_t end = roff[item.x + 1];
+    const int64_t e1 = e0 + PUSH_CHUNK < end ? e0 + PUSH_CHUNK : end;
+    for (int64_t e = e0 + lane; e < e1; e += 64) act[ridx[e]] = epoch;
+  }
+}
+
 int grid_for(int64_t work, int per_block, int cap) {
   int64_t g = (work + per_block - 1) / per_block;
   if (g < 1) g = 1;
@@ -599,13 +742,15 @@ hipError_t launch_init_nodes(int log2m, int64_t n, uint64_t seed, uint8_t* cur, 
 hipError_t launch_pass(int log2m, const PassArgs& a, hipStream_t s, hipEvent_t ev_mid) {
   if (a.n_blocks == 0) return hipSuccess;
   if (log2m <= 8) {
-    const int64_t grid = a.n_items + (a.n_blocks + 3) / 4;
-    switch (log2m) {
-      case 4: hipLaunchKernelGGL(k_expand<4>, dim3((unsigned)grid), dim3(256), 0, s, a); break;
-      case 5: hipLaunchKernelGGL(k_expand<5>, dim3((unsigned)grid), dim3(256), 0, s, a); break;
-      case 6: hipLaunchKernelGGL(k_expand<6>, dim3((unsigned)grid), dim3(256), 0, s, a); break;
-      case 7: hipLaunchKernelGGL(k_expand<7>, dim3((unsigned)grid), dim3(256), 0, s, a); break;
-      default: hipLaunchKernelGGL(k_expand<8>, dim3((unsigned)grid), dim3(256), 0, s, a); break;
+    const int64_t grid = a.n_items + (a.n_medium + 3) / 4 + (a.n_light + 255) / 256;
+    if (grid > 0) {
+      switch (log2m) {
+        case 4: hipLaunchKernelGGL(k_expand<4>, dim3((unsigned)grid), dim3(256), 0, s, a); break;
+        case 5: hipLaunchKernelGGL(k_expand<5>, dim3((unsigned)grid), dim3(256), 0, s, a); break;
+        case 6: hipLaunchKernelGGL(k_expand<6>, dim3((unsigned)grid), dim3(256), 0, s, a); break;
+        case 7: hipLaunchKernelGGL(k_expand<7>, dim3((unsigned)grid), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL(k_expand<8>, dim3((unsigned)grid), dim3(256), 0, s, a); break;
+      }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -656,6 +801,53 @@ hipError_t launch_validate(const int64_t* off, const int32_t* idx, int64_t n, in
                            hipStream_t s) {
   hipLaunchKernelGGL(k_validate, dim3(grid_for(n + m + 1, 256, 16384)), dim3(256), 0, s, off, idx, n, m,
                      bad);
+  return hipGetLastError();
+}
+
+hipError_t build_reverse(const int64_t* off, const int32_t* idx, int64_t n, int64_t m, int64_t* roff,
+                         int32_t* ridx, hipStream_t s) {
+  unsigned long long* cnt = nullptr;
+  void* tmp = nullptr;
+  size_t tmp_bytes = 0;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&cnt), sizeof(unsigned long long) * (size_t)(n + 1));
+  if (e != hipSuccess) return e;
+  e = launch_fill_zero(cnt, sizeof(unsigned long long) * (size_t)(n + 1), s);
+  if (e == hipSuccess && m > 0) {
+    hipLaunchKernelGGL(k_count_in, dim3(grid_for(m, 256, 65536)), dim3(256), 0, s, idx, m, cnt);
+    e = hipGetLastError();
+  }
+  // roff[0..n] = exclusive prefix sums of the counts (count[n] = 0 gives roff[n] = m).
+  if (e == hipSuccess)
+    e = hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt, reinterpret_cast<unsigned long long*>(roff),
+                                         (int)(n + 1), s);
+  if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1);
+  if (e == hipSuccess)
+    e = hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, cnt, reinterpret_cast<unsigned long long*>(roff),
+                                         (int)(n + 1), s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(cnt, roff, sizeof(int64_t) * (size_t)(n + 1), hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && n > 0) {
+    hipLaunchKernelGGL(k_scatter_rev, dim3(grid_for(n, 4, 65536)), dim3(256), 0, s, off, idx, n, cnt, ridx);
+    e = hipGetLastError();
+  }
+  const hipError_t e2 = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = e2;
+  (void)hipFree(tmp);
+  (void)hipFree(cnt);
+  return e;
+}
+
+hipError_t launch_push(const uint64_t* mod_prev, int64_t n_words, int64_t n, const int64_t* roff,
+                       const int32_t* ridx, uint2* items, unsigned long long* count, int32_t* act,
+                       int32_t epoch, hipStream_t s) {
+  if (n_words == 0) return hipSuccess;
+  hipError_t e = launch_fill_zero(count, sizeof(unsigned long long), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_push_items, dim3((unsigned)((n_words + 255) / 256)), dim3(256), 0, s, mod_prev, n_words,
+                     n, roff, items, count);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_push_apply, dim3(4096), dim3(256), 0, s, items, count, roff, ridx, act, epoch);
   return hipGetLastError();
 }
 

@@ -70,6 +70,10 @@ def test_every_pass_matches():
     dict(light_max=4, heavy_min=40, chunk=17),
     dict(frontier=0),
     dict(frontier=0, light_max=2, heavy_min=6, chunk=5),
+    dict(dense_pct=0),                            # every pass after the first is dense
+    dict(dense_pct=101),                          # every pass after the first is sparse
+    dict(dense_pct=101, push=0),                  # sparse passes without the reverse CSR
+    dict(dense_pct=101, light_max=2, heavy_min=6, chunk=3),
 ])
 def test_parity_every_row_path(opts):
     graphs = [("rmat11", gg.rmat(11, 16, seed=4, transpose=True)),
@@ -161,16 +165,21 @@ def test_determinism():
 def test_pass_counters():
     off, idx = gg.rmat(11, 8, seed=4, transpose=True)
     m = len(idx)
-    on = run_hb(off, idx, 6, 3)
-    off_ = run_hb(off, idx, 6, 3, frontier=0)
-    for t, (a, b) in enumerate(zip(on["pass_stats"], off_["pass_stats"])):
-        assert a["arcs_scanned"] == m and b["arcs_scanned"] == m
-        assert b["counters_gathered"] == m              # frontier off gathers every arc
-        assert a["counters_gathered"] <= m
+    nonempty = int((np.diff(off) > 0).sum())
+    on = run_hb(off, idx, 6, 3, dense_pct=101)       # sparse after pass 0
+    dense = run_hb(off, idx, 6, 3, frontier=0)
+    assert on["passes"] == dense["passes"]
+    for t, (a, b) in enumerate(zip(on["pass_stats"], dense["pass_stats"])):
+        assert b["mode"] == (0 if t == 0 else 1) and a["mode"] == (0 if t == 0 else 2)
+        assert b["arcs_scanned"] == m and b["counters_gathered"] == m and b["rows_loaded"] == nonempty
+        assert a["arcs_scanned"] <= m and a["counters_gathered"] <= a["arcs_scanned"]
         assert a["rows_changed"] == b["rows_changed"]
         assert a["rows_written"] >= a["rows_changed"]
+        assert a["rows_loaded"] >= a["rows_changed"]
     assert on["pass_stats"][0]["counters_gathered"] == m
-    assert sum(p["counters_gathered"] for p in on["pass_stats"]) < on["passes"] * m
+    assert sum(p["arcs_scanned"] for p in on["pass_stats"]) < on["passes"] * m
+    # the last pass visits only rows next to the previous pass's changes
+    assert on["pass_stats"][-1]["rows_loaded"] < nonempty
 
 
 def test_validation_rejects_bad_indices():
