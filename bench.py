@@ -68,14 +68,17 @@ def pass_bytes(ps, listed, p):
     """Algorithmic HBM bytes of one pass's expand kernel.
 
     Every listed (non-empty) row: list entry, two offsets and its change-bit
-    word (28 B; plus its 4 B activation stamp in sparse passes).  Every row
+    word (28 B; plus a 4 B activation stamp in sparse passes).  Every row
     that runs: own counter (p B) and the cached estimate and two accumulators
     (24 B).  Every scanned arc: its successor id (4 B).  Every gathered
-    successor counter: p B.  Every written counter: p B.  Every changed row:
-    estimate and accumulators written back (24 B)."""
+    successor in a slice pass: its 2 B slice mask.  Every gathered 16-byte
+    counter slice: 16 B.  Every written counter: p B.  Every changed row:
+    estimate, accumulators and slice mask written back (26 B)."""
     per_row = 28 + (4 if ps["mode"] == 2 else 0)
-    return (per_row * listed + (p + 24) * ps["rows_loaded"] + 4 * ps["arcs_scanned"]
-            + p * ps["counters_gathered"] + p * ps["rows_written"] + 24 * ps["rows_changed"])
+    per_arc = 4
+    return (per_row * listed + (p + 24) * ps["rows_loaded"] + per_arc * ps["arcs_scanned"]
+            + 16 * ps["slices_gathered"] + 2 * (ps["counters_gathered"] if ps["mode"] == 3 else 0)
+            + p * ps["rows_written"] + 26 * ps["rows_changed"])
 
 
 def cpu_baseline(w, seed):
@@ -112,6 +115,9 @@ def main():
     ap.add_argument("--frontier", type=int, default=1)
     ap.add_argument("--dense-pct", type=int, default=-1)
     ap.add_argument("--push", type=int, default=1)
+    ap.add_argument("--sparse-pct", type=int, default=-1)
+    ap.add_argument("--qdense", type=int, default=0)
+    ap.add_argument("--slice", type=int, default=0)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (torch) 3 times, to scale HBM counters")
     args = ap.parse_args()
@@ -136,7 +142,8 @@ def main():
     stream = torch.cuda.current_stream().cuda_stream
     g = hb.HyperBall(o_d, i_d, w["log2m"], seed, stream=stream, timing=1, frontier=args.frontier,
                      light_max=args.light_max, heavy_min=args.heavy_min, chunk=args.chunk,
-                     dense_pct=args.dense_pct, push=args.push)
+                     dense_pct=args.dense_pct, push=args.push, sparse_pct=args.sparse_pct,
+                     qdense=args.qdense, slice=args.slice)
     st0 = g.stats()
     listed = st0["light_rows"] + st0["medium_rows"] + st0["heavy_rows"]
     log(f"rows: light={st0['light_rows']} medium={st0['medium_rows']} heavy={st0['heavy_rows']} "
@@ -175,8 +182,10 @@ def main():
 
     for t, ps in enumerate(first):
         log(f"  pass {t:2d} mode {ps['mode']}: arcs={ps['arcs_scanned']:>10d} "
-            f"gathered={ps['counters_gathered']:>10d} loaded={ps['rows_loaded']:>8d} "
+            f"gathered={ps['counters_gathered']:>10d} slices={ps['slices_gathered']:>11d} "
+            f"loaded={ps['rows_loaded']:>8d} "
             f"written={ps['rows_written']:>8d} changed={ps['rows_changed']:>8d} "
+            f"sch={ps['slices_changed']:>9d} "
             f"push={ps['push_ms']:.3f} expand={ps['expand_ms']:.3f} merge={ps['merge_ms']:.3f} ms "
             f"{pass_bytes(ps, listed, p) / (ps['expand_ms'] * 1e6):.0f} GB/s")
 

@@ -79,13 +79,23 @@ typedef struct {
  *   validate   1: check the CSR (offsets monotone and bounded, indices in
  *              range) at init and fail with HB_EINVAL if it is malformed.
  *   timing     1: time every pass's kernels with HIP events (hb_pass_stats).
- *   dense_pct  with the frontier on, a pass runs dense (every non-empty row,
- *              every successor gathered, no per-arc test) when the previous
- *              pass changed at least dense_pct percent of the non-empty rows,
- *              sparse otherwise.  (< 0: library default.)
+ *   dense_pct  with the frontier on, a pass after the first runs dense (every
+ *              non-empty row gathers every successor, no per-arc test) when
+ *              at least dense_pct percent of the arcs lead to a counter that
+ *              changed in the previous pass (known exactly when push = 1,
+ *              else estimated from the fraction of changed rows).  (< 0:
+ *              default.)
+ *   sparse_pct below that, the pass runs in edge mode (every non-empty row
+ *              runs and gathers only its changed successors) when at least
+ *              sparse_pct percent of the non-empty rows changed, and sparse
+ *              (only rows with a changed successor run; needs push = 1)
+ *              otherwise.  (< 0: default.)
  *   push       1: build the reverse CSR at init (m int32 + n+1 int64 more
- *              device memory) so that sparse passes visit only rows with a
- *              changed successor; 0: sparse passes visit every row. */
+ *              device memory) for sparse passes and exact pass planning.
+ *   qdense     1: dense passes use the queued two-phase gather as well
+ *              (tuning knob; results are identical).
+ *   slice      1: keep a mask of changed 16-byte register slices per node
+ *              (2n bytes) and let edge passes gather only changed slices. */
 typedef struct {
   int32_t frontier;
   int32_t light_max;
@@ -95,6 +105,9 @@ typedef struct {
   int32_t timing;
   int32_t dense_pct;
   int32_t push;
+  int32_t sparse_pct;
+  int32_t qdense;
+  int32_t slice;
 } hb_options;
 
 void hb_default_options(hb_options* opt);
@@ -160,18 +173,26 @@ hb_status hb_stats(hb_ctx* c, hb_stats_t* s);
 
 /* Per-pass record (pass in [0, passes)).  Work counters are exact:
  *   arcs_scanned       successor ids read (every arc of every row the pass runs)
- *   counters_gathered  successor counters read (p bytes each)
+ *   counters_gathered  successors whose counter (or part of it) was read
+ *   slices_gathered    16-byte counter slices read for them
  *   rows_loaded        rows the pass ran (own counter read)
  *   rows_written       counters written into the next buffer
  *   rows_changed       counters that changed (= n_modified)
- *   mode               0 first pass, 1 dense, 2 sparse
+ *   slices_changed     16-byte slices that changed
+ *   arcs_to_changed    arcs whose successor changed in this pass (what the
+ *                      next pass gathers with edge skipping; needs push = 1)
+ *   mode               0 first pass, 1 dense, 2 sparse, 3 edge with slice
+ *                      masks, 4 edge
  *   push_ms / expand_ms / merge_ms: kernel times from HIP events (timing = 1). */
 typedef struct {
   int64_t arcs_scanned;
   int64_t counters_gathered;
+  int64_t slices_gathered;
   int64_t rows_loaded;
   int64_t rows_written;
   int64_t rows_changed;
+  int64_t slices_changed;
+  int64_t arcs_to_changed;
   int32_t mode;
   double push_ms;
   double expand_ms;

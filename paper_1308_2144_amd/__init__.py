@@ -21,7 +21,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhb.so")
+# HB_LIB may point at another build of the same library (tuning experiments).
+LIB_PATH = os.environ.get("HB_LIB") or os.path.join(_HERE, "libhb.so")
 
 HB_OK, HB_EINVAL, HB_ENOMEM, HB_EDEVICE, HB_ESTATE = 0, -1, -2, -3, -4
 _STATUS = {HB_EINVAL: "HB_EINVAL", HB_ENOMEM: "HB_ENOMEM", HB_EDEVICE: "HB_EDEVICE",
@@ -44,7 +45,9 @@ class hb_options(ctypes.Structure):
     _fields_ = [("frontier", ctypes.c_int32), ("light_max", ctypes.c_int32),
                 ("heavy_min", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("dense_pct", ctypes.c_int32), ("push", ctypes.c_int32)]
+                ("dense_pct", ctypes.c_int32), ("push", ctypes.c_int32),
+                ("sparse_pct", ctypes.c_int32), ("qdense", ctypes.c_int32),
+                ("slice", ctypes.c_int32)]
 
 
 class hb_stats_t(ctypes.Structure):
@@ -58,8 +61,10 @@ class hb_stats_t(ctypes.Structure):
 
 class hb_pass_info(ctypes.Structure):
     _fields_ = [("arcs_scanned", ctypes.c_int64), ("counters_gathered", ctypes.c_int64),
-                ("rows_loaded", ctypes.c_int64), ("rows_written", ctypes.c_int64),
-                ("rows_changed", ctypes.c_int64), ("mode", ctypes.c_int32),
+                ("slices_gathered", ctypes.c_int64), ("rows_loaded", ctypes.c_int64),
+                ("rows_written", ctypes.c_int64), ("rows_changed", ctypes.c_int64),
+                ("slices_changed", ctypes.c_int64), ("arcs_to_changed", ctypes.c_int64),
+                ("mode", ctypes.c_int32),
                 ("push_ms", ctypes.c_double), ("expand_ms", ctypes.c_double),
                 ("merge_ms", ctypes.c_double)]
 

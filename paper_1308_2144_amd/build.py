@@ -22,15 +22,18 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = LIB, defines: dict | None = None) -> str:
+    """Compile the library to `out`; `defines` sets compile-time tuning macros
+    (HB_U, HB_WAVES, HB_NT)."""
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + srcs + ["-o", tmp]
+    tmp = out + ".tmp"
+    dflags = [f"-D{k}={v}" for k, v in (defines or {}).items()]
+    cmd = [HIPCC] + FLAGS + dflags + srcs + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -28,7 +28,8 @@ hb_status fail(hb_status st, const std::string& msg) {
 constexpr int DEFAULT_LIGHT_MAX = 64;
 constexpr int DEFAULT_HEAVY_MIN = 8192;
 constexpr int DEFAULT_CHUNK = 4096;
-constexpr int DEFAULT_DENSE_PCT = 10;
+constexpr int DEFAULT_DENSE_PCT = 60;
+constexpr int DEFAULT_SPARSE_PCT = 20;
 
 // alpha_p of Flajolet-Fusy-Gandouet-Meunier 2007 (Algorithm 1 defers to it).
 double alpha_for(int p) {
@@ -59,6 +60,7 @@ struct hb_ctx {
   int32_t* idx_owned = nullptr;
   uint8_t* cnt[2] = {nullptr, nullptr};
   uint64_t* mod[2] = {nullptr, nullptr};
+  uint16_t* dmask[2] = {nullptr, nullptr};
   int64_t n_blocks = 0;
   double* S = nullptr;
   double* H = nullptr;
@@ -88,6 +90,8 @@ struct hb_ctx {
   int32_t t = 0;
   bool converged = false;
   int64_t last_nmod = -1;
+  int64_t last_slices = -1;
+  int64_t last_pairs = -1;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hb_pass_info> hist;
   double total_ms = 0.0;
@@ -103,6 +107,7 @@ void release(hb_ctx* c) {
   for (int i = 0; i < 2; ++i) {
     (void)hipFree(c->cnt[i]);
     (void)hipFree(c->mod[i]);
+    (void)hipFree(c->dmask[i]);
   }
   (void)hipFree(c->S);
   (void)hipFree(c->H);
@@ -171,11 +176,10 @@ hb_status do_reset(hb_ctx* c, uint64_t seed) {
   c->cur = 0;
   c->converged = false;
   c->last_nmod = -1;
+  c->last_slices = -1;
+  c->last_pairs = -1;
   c->hist.clear();
   c->total_ms = 0.0;
-  const size_t cbytes = (size_t)c->n * (size_t)c->p;
-  HB_HIP(hb::launch_fill_zero(c->cnt[0], cbytes, c->stream));
-  HB_HIP(hb::launch_fill_zero(c->cnt[1], cbytes, c->stream));
   HB_HIP(hb::launch_fill_zero(c->mod[0], (size_t)c->n_blocks * 8, c->stream));
   HB_HIP(hb::launch_fill_zero(c->mod[1], (size_t)c->n_blocks * 8, c->stream));
   HB_HIP(hb::launch_fill_zero(c->stats, sizeof(unsigned long long) * 2 * hb::STAT_SLOTS * hb::STAT_K,
@@ -201,6 +205,7 @@ hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, co
   if (c->opt.heavy_min <= 0) c->opt.heavy_min = DEFAULT_HEAVY_MIN;
   if (c->opt.chunk <= 0) c->opt.chunk = DEFAULT_CHUNK;
   if (c->opt.dense_pct < 0) c->opt.dense_pct = DEFAULT_DENSE_PCT;
+  if (c->opt.sparse_pct < 0) c->opt.sparse_pct = DEFAULT_SPARSE_PCT;
   if (c->opt.heavy_min <= c->opt.light_max) c->opt.heavy_min = c->opt.light_max + 1;
   const int64_t n = c->n, m = c->m;
   c->n_blocks = (n + 63) / 64;
@@ -294,6 +299,8 @@ hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, co
     if (dmalloc(&c->cnt[i], cbytes) != hipSuccess)
       return fail(HB_ENOMEM, "cannot allocate counter buffers (" + std::to_string(cbytes) + " bytes each)");
     if (dmalloc(&c->mod[i], (size_t)c->n_blocks) != hipSuccess) return fail(HB_ENOMEM, "cannot allocate bitmaps");
+    if (c->opt.slice && c->p <= 256 && dmalloc(&c->dmask[i], (size_t)n) != hipSuccess)
+      return fail(HB_ENOMEM, "cannot allocate slice masks");
   }
   if (dmalloc(&c->S, (size_t)n) != hipSuccess || dmalloc(&c->H, (size_t)n) != hipSuccess ||
       dmalloc(&c->E, (size_t)n) != hipSuccess)
@@ -330,6 +337,9 @@ void hb_default_options(hb_options* opt) {
   opt->timing = 0;
   opt->dense_pct = DEFAULT_DENSE_PCT;
   opt->push = 1;
+  opt->sparse_pct = DEFAULT_SPARSE_PCT;
+  opt->qdense = 0;
+  opt->slice = 0;
 }
 
 hb_status hb_init(hb_ctx** out, const hb_csr* g, int32_t log2m, uint64_t seed, const hb_options* opt,
@@ -389,10 +399,27 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
     c->last_nmod = 0;
     return HB_OK;
   }
-  const int32_t mode =
-      c->t == 0 ? hb::MODE_FIRST
-      : (!c->opt.frontier || 100 * c->last_nmod >= (int64_t)c->opt.dense_pct * c->n_nonempty) ? hb::MODE_DENSE
-                                                                                              : hb::MODE_SPARSE;
+  // Pass mode from the previous pass's changes (all modes give identical
+  // results; they differ only in the work they skip).
+  int32_t mode = hb::MODE_DENSE;
+  if (c->t == 0) {
+    mode = hb::MODE_FIRST;
+  } else if (c->opt.frontier) {
+    const int64_t N = c->n_nonempty > 0 ? c->n_nonempty : 1;
+    const bool lanes = c->p <= 256;
+    // Share of arcs the next pass must gather: exact with the reverse CSR.
+    const bool exact = lanes && c->roff && c->last_pairs >= 0;
+    const bool dense = exact ? 100 * c->last_pairs >= (int64_t)c->opt.dense_pct * (c->m > 0 ? c->m : 1)
+                             : 100 * c->last_nmod >= (int64_t)c->opt.dense_pct * N;
+    if (dense)
+      mode = hb::MODE_DENSE;
+    else if (c->roff && 100 * c->last_nmod < (int64_t)c->opt.sparse_pct * N)
+      mode = hb::MODE_SPARSE;
+    else if (!lanes)
+      mode = hb::MODE_SPARSE;  // the wide kernel visits every row in sparse passes without push
+    else
+      mode = c->dmask[0] ? hb::MODE_SLICE : hb::MODE_EDGE;
+  }
   hb::PassArgs a{};
   a.off = c->off;
   a.idx = c->idx;
@@ -400,6 +427,8 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
   a.nxt = c->cnt[c->cur ^ 1];
   a.mod_prev = c->mod[c->cur];
   a.mod_cur = c->mod[c->cur ^ 1];
+  a.dmask_prev = c->dmask[c->cur];
+  a.dmask_cur = c->dmask[c->cur ^ 1];
   a.S = c->S;
   a.H = c->H;
   a.E = c->E;
@@ -410,6 +439,7 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
   a.hrows = c->hrows;
   a.partial = c->partial;
   a.act = (mode == hb::MODE_SPARSE) ? c->act : nullptr;
+  a.roff = c->roff;
   const size_t half = (size_t)hb::STAT_SLOTS * hb::STAT_K;
   a.stats = c->stats + (size_t)(c->t & 1) * half;
   a.stats_next = c->stats + (size_t)((c->t + 1) & 1) * half;
@@ -423,6 +453,7 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
   a.n_hrows = c->n_hrows;
   a.epoch = c->t + 1;
   a.mode = mode;
+  a.qdense = c->opt.qdense ? 1 : 0;
   const bool timing = c->opt.timing != 0;
   hipError_t e = hipSuccess;
   if (timing) e = hipEventRecord(c->ev[0], c->stream);
@@ -430,6 +461,8 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
     e = hb::launch_push(a.mod_prev, c->n_blocks, c->n, c->roff, c->ridx, c->push_items, c->push_count, c->act,
                         a.epoch, c->stream);
   if (e == hipSuccess) e = hb::launch_fill_zero(a.mod_cur, sizeof(uint64_t) * (size_t)c->n_blocks, c->stream);
+  if (e == hipSuccess && a.dmask_cur)
+    e = hb::launch_fill_zero(a.dmask_cur, sizeof(uint16_t) * (size_t)c->n, c->stream);
   if (e == hipSuccess && timing) e = hipEventRecord(c->ev[1], c->stream);
   if (e == hipSuccess) e = hb::launch_pass(c->b, a, c->stream, timing ? c->ev[2] : nullptr);
   if (e == hipSuccess && timing) e = hipEventRecord(c->ev[3], c->stream);
@@ -441,7 +474,7 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
     c->failed = true;
     return fail(HB_EDEVICE, std::string("pass ") + std::to_string(c->t) + ": " + hipGetErrorString(e));
   }
-  unsigned long long sum[hb::STAT_K] = {0, 0, 0, 0, 0};
+  unsigned long long sum[hb::STAT_K] = {};
   for (int s = 0; s < hb::STAT_SLOTS; ++s)
     for (int k = 0; k < hb::STAT_K; ++k) sum[k] += c->stats_host[s * hb::STAT_K + k];
   info.counters_gathered = (int64_t)sum[0];
@@ -449,6 +482,9 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
   info.rows_written = (int64_t)sum[2];
   info.rows_changed = (int64_t)sum[3];
   info.arcs_scanned = (int64_t)sum[4];
+  info.slices_gathered = (int64_t)sum[5];
+  info.slices_changed = (int64_t)sum[6];
+  info.arcs_to_changed = c->roff ? (int64_t)sum[7] : -1;
   info.mode = mode;
   if (timing) {
     float ms0 = 0.f, ms1 = 0.f, ms2 = 0.f;
@@ -464,6 +500,8 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
   c->cur ^= 1;
   c->t += 1;
   c->last_nmod = info.rows_changed;
+  c->last_slices = info.slices_changed;
+  c->last_pairs = info.arcs_to_changed;
   if (info.rows_changed == 0) c->converged = true;
   if (n_modified) *n_modified = info.rows_changed;
   return HB_OK;

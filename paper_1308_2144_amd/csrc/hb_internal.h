@@ -26,7 +26,10 @@ struct HeavyItem {
 // Number of slots the per-pass work counters are spread over (atomics to a
 // single address would serialise); STAT_K counters per slot.
 constexpr int STAT_SLOTS = 256;
-constexpr int STAT_K = 5;  // gathered, loaded, written, changed, arcs scanned
+// gathered successors, rows run, rows written, rows changed, arcs scanned,
+// 16-byte slices gathered, 16-byte slices changed, arcs into changed rows
+// (the number of successors the next pass would gather with edge skipping)
+constexpr int STAT_K = 8;
 
 // Reverse-CSR entries handled by one push item.
 constexpr int PUSH_CHUNK = 2048;
@@ -37,6 +40,9 @@ enum PassMode : int32_t {
   MODE_DENSE = 1,   // every listed row runs and gathers every successor
   MODE_SPARSE = 2,  // only rows with a changed successor (or a changed own
                     // counter) run, and they gather only changed successors
+  MODE_SLICE = 3,   // every listed row runs and gathers only the 16-byte slices
+                    // of its successors that changed in the previous pass
+  MODE_EDGE = 4,    // every listed row runs and gathers only changed successors
 };
 
 // Everything one pass needs.  `cur` holds counters of radius t, `nxt`
@@ -49,6 +55,8 @@ struct PassArgs {
   uint8_t* nxt;
   const uint64_t* mod_prev;
   uint64_t* mod_cur;
+  const uint16_t* dmask_prev;        // changed 16-byte slices per node, previous pass
+  uint16_t* dmask_cur;               // this pass (zeroed before the pass)
   double* S;
   double* H;
   double* E;
@@ -59,6 +67,7 @@ struct PassArgs {
   const HeavyRow* hrows;
   uint8_t* partial;                  // n_items * p bytes
   const int32_t* act;                // act[v] == epoch: v has a changed successor (sparse)
+  const int64_t* roff;               // reverse CSR offsets (nullable): in-degrees for the stats
   unsigned long long* stats;         // this pass: STAT_SLOTS * STAT_K
   unsigned long long* stats_next;    // zeroed by this pass for the next one
   double alpha_pp;                   // (alpha_p * p) * p
@@ -71,6 +80,7 @@ struct PassArgs {
   int64_t n_hrows;
   int32_t epoch;
   int32_t mode;                      // PassMode
+  int32_t qdense;                    // dense passes use the queued gather too
 };
 
 // Launchers (hb_kernels.hip).  All return the launch status.

@@ -39,7 +39,61 @@
 namespace hb {
 namespace {
 
-constexpr int U = 8;  // successor counters in flight per lane group
+// Compile-time tuning: successor counters in flight per lane group, a cap on
+// waves per SIMD for the expand kernels (0: compiler's choice), and
+// non-temporal hints for data that is streamed once per pass.
+#ifndef HB_U
+#define HB_U 8
+#endif
+#ifndef HB_WAVES
+#define HB_WAVES 5
+#endif
+#ifndef HB_NT
+#define HB_NT 0
+#endif
+constexpr int U = HB_U;
+
+template <class T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+#if HB_NT
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+
+template <class T>
+__device__ __forceinline__ void st_stream(T* p, T v) {
+#if HB_NT
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint4 ld_stream(const uint4* p) {
+#if HB_NT
+  const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+  return make_uint4(v.x, v.y, v.z, v.w);
+#else
+  return *p;
+#endif
+}
+
+__device__ __forceinline__ void st_stream(uint4* p, uint4 v) {
+#if HB_NT
+  u32x4 x;
+  x.x = v.x;
+  x.y = v.y;
+  x.z = v.z;
+  x.w = v.w;
+  __builtin_nontemporal_store(x, reinterpret_cast<u32x4*>(p));
+#else
+  *p = v;
+#endif
+}
 
 // Node hash: SplitMix64 finalizer (Steele, Lea, Flood 2014) of
 // v + (seed+1) * golden-ratio increment.  The paper asks only for a fixed
@@ -183,6 +237,11 @@ __device__ __forceinline__ bool bit_of(const uint64_t* bm, int64_t v) {
   return ((bm[v >> 6] >> (v & 63)) & 1ull) != 0ull;
 }
 
+// Per-wavefront work counters (summed over lanes before the atomics).
+struct Counts {
+  uint32_t gath, load, write, chg, arcs, slices, sch, pairs;
+};
+
 // own_mod: the row's counter changed in the previous pass (so the next buffer
 // holds a stale copy).  need: the row takes part in this pass.  In a sparse
 // pass a row without a changed successor cannot change; it only runs to
@@ -192,42 +251,152 @@ __device__ __forceinline__ void row_flags(const PassArgs& A, int64_t row, bool& 
   need = A.mode != MODE_SPARSE || own_mod || A.act == nullptr || A.act[row] == A.epoch;
 }
 
-// Gather-max over the arcs k, k+st, k+2st, ... < e of a row: every lane of
-// the group loads its 16-byte slice of each selected successor counter.
-// `got` is set if at least one counter was gathered; `ngath` counts them.
+// Direct gather-max (dense passes) over the arcs k, k+st, k+2st, ... < e of
+// a row: every lane of the group loads its 16-byte slice of each successor
+// counter, U successors in flight.
 template <int B>
 __device__ __forceinline__ uint4 gather(const PassArgs& A, int64_t k, int64_t e, int64_t st, int gl,
-                                        bool& got, uint32_t& ngath) {
+                                        bool& got, Counts& c) {
   constexpr int P = 1 << B;
+  constexpr int G = P / 16;
   SplitAcc acc{zero4(), zero4()};
   const uint8_t* base = A.cur + gl * 16;
-  const bool all = A.mode != MODE_SPARSE;
   for (; k < e; k += st * U) {
     int32_t w[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t kk = k + u * st;
-      w[u] = kk < e ? A.idx[kk] : -1;
-    }
-    bool m[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int32_t ws = w[u] < 0 ? 0 : w[u];
-      const bool bit = all ? true : bit_of(A.mod_prev, ws);
-      m[u] = (w[u] >= 0) && bit;
+      w[u] = kk < e ? ld_stream(A.idx + kk) : -1;
     }
     uint4 v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       v[u] = zero4();
-      if (m[u]) v[u] = *reinterpret_cast<const uint4*>(base + (size_t)w[u] * P);
+      if (w[u] >= 0) v[u] = *reinterpret_cast<const uint4*>(base + (size_t)w[u] * P);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       fold(acc, v[u]);
-      got |= m[u];
-      ngath += m[u] ? 1u : 0u;
+      const uint32_t hit = w[u] >= 0 ? 1u : 0u;
+      got |= hit != 0u;
+      c.slices += hit;
+      if (gl == 0) c.gath += hit;
     }
+  }
+  (void)G;
+  return unsplit(acc);
+}
+
+// Queued gather (slice, sparse and optionally dense passes), in two phases:
+// (1) a team of lanes reads successor ids and their change masks with
+// consecutive lanes on consecutive arcs, and appends every successor with a
+// nonzero mask to a queue in LDS; (2) lane groups drain the queue, each lane
+// loading its 16-byte slice of a queued counter only if that slice changed.
+struct QEnt {
+  int32_t w;
+  uint32_t msk;
+};
+
+constexpr int QCAP = 64 * U;  // queue entries per wavefront
+
+template <int B>
+__device__ __forceinline__ uint32_t change_mask(const PassArgs& A, int32_t w) {
+  constexpr uint32_t FULL = (1u << ((1 << B) / 16)) - 1u;
+  if (w < 0) return 0u;
+  if (A.mode == MODE_FIRST || A.mode == MODE_DENSE) return FULL;
+  // The change bitmap (n/8 bytes) stays in L2; the slice masks (2n bytes) are
+  // read only for successors that changed.
+  if (!bit_of(A.mod_prev, w)) return 0u;
+  return A.mode == MODE_SLICE ? (uint32_t)A.dmask_prev[w] : FULL;
+}
+
+// Phase 1 for a team of TL lanes (a lane group or the wavefront): arcs
+// k + tid + u*TL for u < U.  Returns the number of queued successors.
+template <int B, int TL>
+__device__ __forceinline__ int scan_chunk(const PassArgs& A, QEnt* q, int64_t k, int64_t e, int tid,
+                                          uint64_t team, uint64_t below) {
+  int32_t w[U];
+  uint32_t m[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t kk = k + tid + (int64_t)u * TL;
+    w[u] = kk < e ? ld_stream(A.idx + kk) : -1;
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) m[u] = change_mask<B>(A, w[u]);
+  int nh = 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const bool hit = m[u] != 0u;
+    const uint64_t hb = __ballot(hit) & team;
+    if (hit) {
+      QEnt ent;
+      ent.w = w[u];
+      ent.msk = m[u];
+      q[nh + __popcll(hb & below)] = ent;
+    }
+    nh += __popcll(hb);
+  }
+  return nh;
+}
+
+// Phase 2: entries first, first+step, ... < nh of the queue, U in flight.
+template <int B>
+__device__ __forceinline__ void drain(const PassArgs& A, const QEnt* q, int first, int nh, int step, int gl,
+                                      SplitAcc& acc, Counts& c) {
+  constexpr int P = 1 << B;
+  const uint8_t* base = A.cur + gl * 16;
+  for (int i = first; i < nh; i += step * U) {
+    uint4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v[u] = zero4();
+      const int j = i + u * step;
+      if (j < nh) {
+        const QEnt ent = q[j];
+        if ((ent.msk >> gl) & 1u) {
+          v[u] = *reinterpret_cast<const uint4*>(base + (size_t)ent.w * P);
+          c.slices += 1u;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) fold(acc, v[u]);
+  }
+}
+
+// Queued gather of one row's arcs [s, e) by one lane group (light rows).
+template <int B>
+__device__ __forceinline__ uint4 gather_group_q(const PassArgs& A, QEnt* q, int64_t s, int64_t e, int gl,
+                                                uint64_t gmask, uint64_t below, bool& got, Counts& c) {
+  constexpr int G = (1 << B) / 16;
+  SplitAcc acc{zero4(), zero4()};
+  for (int64_t k = s; k < e; k += (int64_t)G * U) {
+    const int nh = scan_chunk<B, G>(A, q, k, e, gl, gmask, below);
+    __builtin_amdgcn_wave_barrier();
+    if (gl == 0) c.gath += (uint32_t)nh;
+    got |= nh > 0;
+    drain<B>(A, q, 0, nh, 1, gl, acc, c);
+    __builtin_amdgcn_wave_barrier();
+  }
+  return unsplit(acc);
+}
+
+// Queued gather of arcs [s, e) by a whole wavefront; group grp drains
+// entries grp, grp+W, ...  Returns the group's partial maximum.
+template <int B>
+__device__ __forceinline__ uint4 gather_wave_q(const PassArgs& A, QEnt* q, int64_t s, int64_t e, int lane,
+                                               int gl, int grp, uint64_t below, bool& got, Counts& c) {
+  constexpr int G = (1 << B) / 16;
+  constexpr int W = 64 / G;
+  SplitAcc acc{zero4(), zero4()};
+  for (int64_t k = s; k < e; k += 64 * U) {
+    const int nh = scan_chunk<B, 64>(A, q, k, e, lane, ~0ull, below);
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) c.gath += (uint32_t)nh;
+    got |= nh > 0;
+    drain<B>(A, q, grp, nh, W, gl, acc, c);
+    __builtin_amdgcn_wave_barrier();
   }
   return unsplit(acc);
 }
@@ -244,23 +413,19 @@ template <int B>
 __device__ __forceinline__ RowPre preload(const PassArgs& A, int64_t row, int gl) {
   constexpr int P = 1 << B;
   RowPre r;
-  r.own = *reinterpret_cast<const uint4*>(A.cur + (size_t)row * P + (size_t)gl * 16);
+  r.own = ld_stream(reinterpret_cast<const uint4*>(A.cur + (size_t)row * P + (size_t)gl * 16));
   r.e = r.s = r.h = 0.0;
   if (gl == 0) {
-    r.e = A.E[row];
-    r.s = A.S[row];
-    r.h = A.H[row];
+    r.e = ld_stream(A.E + row);
+    r.s = ld_stream(A.S + row);
+    r.h = ld_stream(A.H + row);
   }
   return r;
 }
 
-struct Counts {
-  uint32_t gath, load, write, chg, arcs;
-};
-
 // Completes row `row` for a group of G lanes: a = own U gathered, write-back
-// rule, change detection, the fused estimator/accumulator and the change
-// bit.  Returns whether the counter changed (uniform over the group).
+// rule, change detection, the fused estimator/accumulator, the change bit
+// and the mask of changed slices.  Returns whether the counter changed.
 template <int B>
 __device__ __forceinline__ bool finish_row(const PassArgs& A, int64_t row, uint4 acc, bool got,
                                            const RowPre& pre, bool own_mod, int gl, int grp,
@@ -271,13 +436,15 @@ __device__ __forceinline__ bool finish_row(const PassArgs& A, int64_t row, uint4
   const uint4 a = got ? bmax(acc, pre.own) : pre.own;
   const bool diff = got && differs(a, pre.own);
   const uint64_t bal = __ballot(diff);
-  const uint64_t gmask = (G >= 64) ? ~0ull : (((1ull << G) - 1ull) << (grp * G));
-  const bool changed = (bal & gmask) != 0ull;
-  if (changed || own_mod) *reinterpret_cast<uint4*>(A.nxt + off) = a;
+  const uint32_t msk = (uint32_t)((bal >> (grp * G)) & ((1ull << G) - 1ull));
+  const bool changed = msk != 0u;
+  if (changed || own_mod) st_stream(reinterpret_cast<uint4*>(A.nxt + off), a);
   if (gl == 0) {
     c.load += 1u;
     c.write += (changed || own_mod) ? 1u : 0u;
     c.chg += changed ? 1u : 0u;
+    c.sch += (uint32_t)__popc(msk);
+    if (changed && A.roff) c.pairs += (uint32_t)(A.roff[row + 1] - A.roff[row]);
   }
   if (changed) {
     const Parts pr = reg_parts(a);
@@ -292,22 +459,21 @@ __device__ __forceinline__ bool finish_row(const PassArgs& A, int64_t row, uint4
     if (gl == 0) {
       const double En = estimate(big, small, V, A.alpha_pp, (double)P, A.lc);
       const double delta = En - pre.e;
-      A.S[row] = pre.s + A.d * delta;
-      A.H[row] = pre.h + delta / A.d;
-      A.E[row] = En;
+      st_stream(A.S + row, pre.s + A.d * delta);
+      st_stream(A.H + row, pre.h + delta / A.d);
+      st_stream(A.E + row, En);
+      if (A.dmask_cur) A.dmask_cur[row] = (uint16_t)msk;
       atomicOr(A.mod_cur + (row >> 6), 1ull << (row & 63));
     }
   }
   return changed;
 }
 
-__device__ __forceinline__ void add_stats(unsigned long long* st, uint32_t g, uint32_t l, uint32_t w,
-                                          uint32_t c, unsigned long long a) {
-  if (g) atomicAdd(st + 0, (unsigned long long)g);
-  if (l) atomicAdd(st + 1, (unsigned long long)l);
-  if (w) atomicAdd(st + 2, (unsigned long long)w);
-  if (c) atomicAdd(st + 3, (unsigned long long)c);
-  if (a) atomicAdd(st + 4, (unsigned long long)a);
+__device__ __forceinline__ void add_stats(unsigned long long* st, const Counts& c) {
+  const unsigned long long v[STAT_K] = {c.gath, c.load, c.write, c.chg, c.arcs, c.slices, c.sch, c.pairs};
+#pragma unroll
+  for (int k = 0; k < STAT_K; ++k)
+    if (v[k]) atomicAdd(st + k, v[k]);
 }
 
 __device__ __forceinline__ void flush_counts(const PassArgs& A, Counts c, int64_t slot, int lane) {
@@ -318,14 +484,19 @@ __device__ __forceinline__ void flush_counts(const PassArgs& A, Counts c, int64_
     c.write += __shfl_xor(c.write, o);
     c.chg += __shfl_xor(c.chg, o);
     c.arcs += __shfl_xor(c.arcs, o);
+    c.slices += __shfl_xor(c.slices, o);
+    c.sch += __shfl_xor(c.sch, o);
+    c.pairs += __shfl_xor(c.pairs, o);
   }
-  if (lane == 0) add_stats(A.stats + (slot & (STAT_SLOTS - 1)) * STAT_K, c.gath, c.load, c.write, c.chg, c.arcs);
+  if (lane == 0) add_stats(A.stats + (slot & (STAT_SLOTS - 1)) * STAT_K, c);
 }
+
+__device__ __forceinline__ uint64_t lanes_below(int lane) { return (1ull << lane) - 1ull; }
 
 // 64 consecutive entries of the light-row list per wavefront; entry
 // q*W + grp goes to lane group grp in round q.
-template <int B>
-__device__ __forceinline__ void light_wave(const PassArgs& A, int64_t lw, int lane) {
+template <int B, bool Q>
+__device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, int64_t lw, int lane) {
   constexpr int P = 1 << B;
   constexpr int G = P / 16;
   constexpr int W = 64 / G;
@@ -342,10 +513,12 @@ __device__ __forceinline__ void light_wave(const PassArgs& A, int64_t lw, int la
   }
   const uint64_t needs = __ballot(need);
   const uint64_t mods = __ballot(own_mod);
-  Counts c{0u, 0u, 0u, 0u, 0u};
+  const uint64_t gmask = (G >= 64) ? ~0ull : (((1ull << G) - 1ull) << (grp * G));
+  QEnt* q = qw + grp * (G * U);
+  Counts c{};
   if (needs) {
-    for (int q = 0; q < G; ++q) {
-      const int rl = q * W + grp;
+    for (int r = 0; r < G; ++r) {
+      const int rl = r * W + grp;
       const int64_t rrow = __shfl(row, rl);
       const int64_t rs = __shfl(s, rl);
       const int64_t rd = __shfl(deg, rl);
@@ -353,12 +526,12 @@ __device__ __forceinline__ void light_wave(const PassArgs& A, int64_t lw, int la
         const bool rmod = ((mods >> rl) & 1ull) != 0ull;
         const RowPre pre = preload<B>(A, rrow, gl);
         bool got = false;
-        uint32_t g = 0;
-        const uint4 acc = gather<B>(A, rs, rs + rd, 1, gl, got, g);
-        if (gl == 0) {
-          c.gath += g;
-          c.arcs += (uint32_t)rd;
-        }
+        uint4 acc;
+        if constexpr (Q)
+          acc = gather_group_q<B>(A, q, rs, rs + rd, gl, gmask, lanes_below(lane), got, c);
+        else
+          acc = gather<B>(A, rs, rs + rd, 1, gl, got, c);
+        if (gl == 0) c.arcs += (uint32_t)rd;
         finish_row<B>(A, rrow, acc, got, pre, rmod, gl, grp, c);
       }
     }
@@ -366,10 +539,10 @@ __device__ __forceinline__ void light_wave(const PassArgs& A, int64_t lw, int la
   flush_counts(A, c, lw, lane);
 }
 
-// One medium row per wavefront: the groups stride over its arcs and reduce
-// their partial maxima by shuffles.
-template <int B>
-__device__ __forceinline__ void medium_wave(const PassArgs& A, int64_t mi, int lane) {
+// One medium row per wavefront: the groups share its arcs and reduce their
+// partial maxima by shuffles.
+template <int B, bool Q>
+__device__ __forceinline__ void medium_wave(const PassArgs& A, QEnt* qw, int64_t mi, int lane) {
   constexpr int P = 1 << B;
   constexpr int G = P / 16;
   constexpr int W = 64 / G;
@@ -380,14 +553,16 @@ __device__ __forceinline__ void medium_wave(const PassArgs& A, int64_t mi, int l
   const int64_t deg = A.off[row + 1] - s;
   bool own_mod, need;
   row_flags(A, row, own_mod, need);
-  Counts c{0u, 0u, 0u, 0u, 0u};
+  Counts c{};
   if (need) {
     RowPre pre;
     if (grp == 0) pre = preload<B>(A, row, gl);
     bool got = false;
-    uint32_t g = 0;
-    uint4 acc = gather<B>(A, s + grp, s + deg, W, gl, got, g);
-    if (gl == 0) c.gath += g;
+    uint4 acc;
+    if constexpr (Q)
+      acc = gather_wave_q<B>(A, qw, s, s + deg, lane, gl, grp, lanes_below(lane), got, c);
+    else
+      acc = gather<B>(A, s + grp, s + deg, W, gl, got, c);
     if (lane == 0) c.arcs += (uint32_t)deg;
 #pragma unroll
     for (int o = G; o < 64; o <<= 1) acc = bmax(acc, shfl_xor4(acc, o));
@@ -397,10 +572,10 @@ __device__ __forceinline__ void medium_wave(const PassArgs& A, int64_t mi, int l
   flush_counts(A, c, mi, lane);
 }
 
-// One chunk of a heavy row per workgroup (4 wavefronts, 4W lane groups):
-// writes the chunk's partial maximum for the merge kernel.
-template <int B>
-__device__ __forceinline__ void heavy_chunk(const PassArgs& A, int64_t item, int lane, int wave) {
+// One chunk of a heavy row per workgroup (4 wavefronts): writes the chunk's
+// partial maximum for the merge kernel.
+template <int B, bool Q>
+__device__ __forceinline__ void heavy_chunk(const PassArgs& A, QEnt* qw, int64_t item, int lane, int wave) {
   constexpr int P = 1 << B;
   constexpr int G = P / 16;
   constexpr int W = 64 / G;
@@ -412,12 +587,20 @@ __device__ __forceinline__ void heavy_chunk(const PassArgs& A, int64_t item, int
   row_flags(A, it.row, own_mod, need);
   if (!need) return;  // uniform over the workgroup; the merge kernel skips the row too
   bool got = false;
-  uint32_t g = 0;
-  uint4 acc = gather<B>(A, it.e0 + wave * W + grp, it.e1, 4 * W, gl, got, g);
+  Counts c{};
+  uint4 acc;
+  if constexpr (Q) {
+    const int64_t quarter = (it.e1 - it.e0 + 3) / 4;
+    const int64_t a0 = it.e0 + wave * quarter;
+    const int64_t a1 = a0 + quarter < it.e1 ? a0 + quarter : it.e1;
+    acc = gather_wave_q<B>(A, qw, a0, a1, lane, gl, grp, lanes_below(lane), got, c);
+  } else {
+    acc = gather<B>(A, it.e0 + wave * W + grp, it.e1, 4 * W, gl, got, c);
+  }
+  if (lane == 0 && wave == 0) c.arcs += (uint32_t)(it.e1 - it.e0);
 #pragma unroll
   for (int o = G; o < 64; o <<= 1) acc = bmax(acc, shfl_xor4(acc, o));
   if (grp == 0) red[wave][gl] = acc;
-  Counts c{(gl == 0) ? g : 0u, 0u, 0u, 0u, (lane == 0 && wave == 0) ? (uint32_t)(it.e1 - it.e0) : 0u};
   flush_counts(A, c, item, lane);
   __syncthreads();
   if (wave == 0 && grp == 0) {
@@ -429,28 +612,47 @@ __device__ __forceinline__ void heavy_chunk(const PassArgs& A, int64_t item, int
   }
 }
 
-// Grid: [heavy chunks][medium rows, 4 per workgroup][light rows, 256 per workgroup].
-template <int B>
-__global__ __launch_bounds__(256) void k_expand(PassArgs A) {
+// Grid: [heavy chunks][medium rows, 4 per workgroup][light rows, 256 per
+// workgroup].  Q selects the queued gather (slice and sparse passes, or dense
+// passes on request) over the direct one.
+template <int B, bool Q>
+__device__ __forceinline__ void expand_body(const PassArgs& A, QEnt* qw) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   if (blockIdx.x == 0)
     for (int i = threadIdx.x; i < STAT_SLOTS * STAT_K; i += blockDim.x) A.stats_next[i] = 0ull;
   int64_t b = blockIdx.x;
   if (b < A.n_items) {
-    heavy_chunk<B>(A, b, lane, wave);
+    heavy_chunk<B, Q>(A, qw, b, lane, wave);
     return;
   }
   b -= A.n_items;
   const int64_t med_wgs = (A.n_medium + 3) / 4;
   if (b < med_wgs) {
     const int64_t mi = b * 4 + wave;
-    if (mi < A.n_medium) medium_wave<B>(A, mi, lane);
+    if (mi < A.n_medium) medium_wave<B, Q>(A, qw, mi, lane);
     return;
   }
   b -= med_wgs;
   const int64_t lw = b * 4 + wave;
-  if (lw * 64 < A.n_light) light_wave<B>(A, lw, lane);
+  if (lw * 64 < A.n_light) light_wave<B, Q>(A, qw, lw, lane);
+}
+
+#if HB_WAVES > 0
+#define HB_EXPAND_ATTR __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HB_WAVES)))
+#else
+#define HB_EXPAND_ATTR __launch_bounds__(256)
+#endif
+
+template <int B>
+__global__ HB_EXPAND_ATTR void k_expand(PassArgs A) {
+  expand_body<B, false>(A, nullptr);
+}
+
+template <int B>
+__global__ HB_EXPAND_ATTR void k_expand_q(PassArgs A) {
+  __shared__ QEnt qbuf[4][QCAP];
+  expand_body<B, true>(A, qbuf[threadIdx.x >> 6]);
 }
 
 // Folds the partial counters of every heavy row into the row (one wavefront
@@ -478,7 +680,7 @@ __global__ __launch_bounds__(256) void k_merge(PassArgs A) {
                                                     (size_t)gl * 16));
 #pragma unroll
   for (int o = G; o < 64; o <<= 1) acc = bmax(acc, shfl_xor4(acc, o));
-  Counts c{0u, 0u, 0u, 0u, 0u};
+  Counts c{};
   if (grp == 0) finish_row<B>(A, hr.row, acc, true, pre, own_mod, gl, 0, c);
   flush_counts(A, c, h, lane);
 }
@@ -572,8 +774,15 @@ __global__ __launch_bounds__(256) void k_expand_wide(PassArgs A, int log2m) {
   }
   if (tid == 0) {
     A.mod_cur[blk] = bits;
-    add_stats(A.stats + (blk & (STAT_SLOTS - 1)) * STAT_K, ngath, nload, nwrite,
-              (uint32_t)__popcll(bits), narcs);
+    unsigned long long* st = A.stats + (blk & (STAT_SLOTS - 1)) * STAT_K;
+    Counts c{};
+    c.gath = ngath;
+    c.load = nload;
+    c.write = nwrite;
+    c.chg = (uint32_t)__popcll(bits);
+    add_stats(st, c);
+    if (narcs) atomicAdd(st + 4, narcs);
+    if (ngath) atomicAdd(st + 5, (unsigned long long)ngath * (unsigned long long)C);
   }
 }
 
@@ -584,27 +793,37 @@ __global__ void k_fill_zero(uint4* p, size_t n16, uint8_t* tail, size_t ntail) {
     for (size_t i = threadIdx.x; i < ntail; i += blockDim.x) tail[i] = 0;
 }
 
-// Algorithm 2 initialisation: add(c[v], v) into both buffers, zero S and H,
-// and cache E(c[v]) for the singleton counter (p-1 empty registers).
+// Algorithm 2 initialisation: c[v] = add(empty counter, v) written into both
+// buffers, one thread per 16-byte chunk of a counter (coalesced stores, no
+// separate zero fill); the first chunk's thread also zeroes S and H and
+// caches E(c[v]) for the singleton counter (p-1 empty registers).
 __global__ void k_init_nodes(int log2m, int64_t n, uint64_t seed, uint8_t* cur, uint8_t* nxt,
                              double* S, double* H, double* E, const double* lc, double alpha_pp) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const int P = 1 << log2m;
+  const int64_t P = (int64_t)1 << log2m;
+  const int64_t C = P / 16;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * C) return;
+  const int64_t v = i / C;
+  const int64_t chunk = i - v * C;
   const uint64_t h = node_hash((uint64_t)v, seed);
   const uint32_t j = (uint32_t)(h >> (64 - log2m));
   const uint64_t rest = h << log2m;
   const uint32_t r = rest == 0ull ? (uint32_t)(65 - log2m) : (uint32_t)__clzll((long long)rest) + 1u;
-  cur[(size_t)v * P + j] = (uint8_t)r;
-  nxt[(size_t)v * P + j] = (uint8_t)r;
-  S[v] = 0.0;
-  H[v] = 0.0;
-  double big = (double)(P - 1), small = 0.0;
-  if (r <= 26u)
-    big += pow2neg(r);
-  else
-    small += pow2neg(r);
-  E[v] = estimate(big, small, P - 1, alpha_pp, (double)P, lc);
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
+  if ((int64_t)(j >> 4) == chunk) w[(j >> 2) & 3u] = r << (8u * (j & 3u));
+  const uint4 val = make_uint4(w[0], w[1], w[2], w[3]);
+  *reinterpret_cast<uint4*>(cur + v * P + chunk * 16) = val;
+  *reinterpret_cast<uint4*>(nxt + v * P + chunk * 16) = val;
+  if (chunk == 0) {
+    S[v] = 0.0;
+    H[v] = 0.0;
+    double big = (double)(P - 1), small = 0.0;
+    if (r <= 26u)
+      big += pow2neg(r);
+    else
+      small += pow2neg(r);
+    E[v] = estimate(big, small, (int)(P - 1), alpha_pp, (double)P, lc);
+  }
 }
 
 // Sec. 3 / Sec. 5 finalisation.
@@ -734,7 +953,8 @@ hipError_t launch_init_nodes(int log2m, int64_t n, uint64_t seed, uint8_t* cur, 
                              double* S, double* H, double* E, const double* lc, double alpha_pp,
                              hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_init_nodes, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, log2m, n, seed,
+  const int64_t threads = n * (((int64_t)1 << log2m) / 16);
+  hipLaunchKernelGGL(k_init_nodes, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, log2m, n, seed,
                      cur, nxt, S, H, E, lc, alpha_pp);
   return hipGetLastError();
 }
@@ -743,13 +963,20 @@ hipError_t launch_pass(int log2m, const PassArgs& a, hipStream_t s, hipEvent_t e
   if (a.n_blocks == 0) return hipSuccess;
   if (log2m <= 8) {
     const int64_t grid = a.n_items + (a.n_medium + 3) / 4 + (a.n_light + 255) / 256;
+    const bool q = !(a.mode == MODE_FIRST || a.mode == MODE_DENSE) || a.qdense;
     if (grid > 0) {
-      switch (log2m) {
-        case 4: hipLaunchKernelGGL(k_expand<4>, dim3((unsigned)grid), dim3(256), 0, s, a); break;
-        case 5: hipLaunchKernelGGL(k_expand<5>, dim3((unsigned)grid), dim3(256), 0, s, a); break;
-        case 6: hipLaunchKernelGGL(k_expand<6>, dim3((unsigned)grid), dim3(256), 0, s, a); break;
-        case 7: hipLaunchKernelGGL(k_expand<7>, dim3((unsigned)grid), dim3(256), 0, s, a); break;
-        default: hipLaunchKernelGGL(k_expand<8>, dim3((unsigned)grid), dim3(256), 0, s, a); break;
+      const dim3 g((unsigned)grid), t(256);
+      switch (log2m * 2 + (q ? 1 : 0)) {
+        case 8: hipLaunchKernelGGL(k_expand<4>, g, t, 0, s, a); break;
+        case 9: hipLaunchKernelGGL(k_expand_q<4>, g, t, 0, s, a); break;
+        case 10: hipLaunchKernelGGL(k_expand<5>, g, t, 0, s, a); break;
+        case 11: hipLaunchKernelGGL(k_expand_q<5>, g, t, 0, s, a); break;
+        case 12: hipLaunchKernelGGL(k_expand<6>, g, t, 0, s, a); break;
+        case 13: hipLaunchKernelGGL(k_expand_q<6>, g, t, 0, s, a); break;
+        case 14: hipLaunchKernelGGL(k_expand<7>, g, t, 0, s, a); break;
+        case 15: hipLaunchKernelGGL(k_expand_q<7>, g, t, 0, s, a); break;
+        case 16: hipLaunchKernelGGL(k_expand<8>, g, t, 0, s, a); break;
+        default: hipLaunchKernelGGL(k_expand_q<8>, g, t, 0, s, a); break;
       }
     }
     hipError_t e = hipGetLastError();

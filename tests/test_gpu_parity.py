@@ -71,9 +71,15 @@ def test_every_pass_matches():
     dict(frontier=0),
     dict(frontier=0, light_max=2, heavy_min=6, chunk=5),
     dict(dense_pct=0),                            # every pass after the first is dense
-    dict(dense_pct=101),                          # every pass after the first is sparse
-    dict(dense_pct=101, push=0),                  # sparse passes without the reverse CSR
-    dict(dense_pct=101, light_max=2, heavy_min=6, chunk=3),
+    dict(dense_pct=0, qdense=1),                  # dense passes through the queued gather
+    dict(dense_pct=101, sparse_pct=0),            # every pass after the first is an edge pass
+    dict(dense_pct=101, sparse_pct=0, slice=1),   # edge passes with slice masks
+    dict(dense_pct=101, sparse_pct=101),          # every pass after the first is sparse
+    dict(dense_pct=101),                          # edge passes, then sparse ones
+    dict(dense_pct=101, push=0),                  # edge passes only (no reverse CSR)
+    dict(dense_pct=101, sparse_pct=0, slice=1, light_max=2, heavy_min=6, chunk=3),
+    dict(dense_pct=101, sparse_pct=101, light_max=2, heavy_min=6, chunk=3),
+    dict(slice=1),                                # default planning with slice masks
 ])
 def test_parity_every_row_path(opts):
     graphs = [("rmat11", gg.rmat(11, 16, seed=4, transpose=True)),
@@ -166,20 +172,36 @@ def test_pass_counters():
     off, idx = gg.rmat(11, 8, seed=4, transpose=True)
     m = len(idx)
     nonempty = int((np.diff(off) > 0).sum())
-    on = run_hb(off, idx, 6, 3, dense_pct=101)       # sparse after pass 0
-    dense = run_hb(off, idx, 6, 3, frontier=0)
-    assert on["passes"] == dense["passes"]
-    for t, (a, b) in enumerate(zip(on["pass_stats"], dense["pass_stats"])):
-        assert b["mode"] == (0 if t == 0 else 1) and a["mode"] == (0 if t == 0 else 2)
-        assert b["arcs_scanned"] == m and b["counters_gathered"] == m and b["rows_loaded"] == nonempty
+    b = 6
+    G = (1 << b) // 16
+    sparse = run_hb(off, idx, b, 3, dense_pct=101, sparse_pct=101)
+    sliced = run_hb(off, idx, b, 3, dense_pct=101, sparse_pct=0, slice=1)
+    edge = run_hb(off, idx, b, 3, dense_pct=101, sparse_pct=0)
+    dense = run_hb(off, idx, b, 3, frontier=0)
+    assert sparse["passes"] == dense["passes"] == sliced["passes"] == edge["passes"]
+    # the arcs into counters changed by pass t are exactly what edge pass t+1 gathers
+    es = edge["pass_stats"]
+    for t in range(1, edge["passes"]):
+        assert es[t]["mode"] == 4 and es[t]["counters_gathered"] == es[t - 1]["arcs_to_changed"]
+        assert es[t]["slices_gathered"] == G * es[t]["counters_gathered"]
+    for t, (a, b_, c) in enumerate(zip(sparse["pass_stats"], dense["pass_stats"], sliced["pass_stats"])):
+        assert b_["mode"] == (0 if t == 0 else 1)
+        assert a["mode"] == (0 if t == 0 else 2) and c["mode"] == (0 if t == 0 else 3)
+        assert b_["arcs_scanned"] == m and b_["counters_gathered"] == m and b_["rows_loaded"] == nonempty
+        assert b_["slices_gathered"] == m * G
+        assert c["arcs_scanned"] == m and c["rows_loaded"] == nonempty
+        assert c["slices_gathered"] <= G * c["counters_gathered"] and c["counters_gathered"] <= m
         assert a["arcs_scanned"] <= m and a["counters_gathered"] <= a["arcs_scanned"]
-        assert a["rows_changed"] == b["rows_changed"]
+        assert a["rows_changed"] == b_["rows_changed"] == c["rows_changed"]
+        assert a["slices_changed"] == b_["slices_changed"] == c["slices_changed"]
+        assert b_["rows_changed"] <= b_["slices_changed"] <= G * b_["rows_changed"]
         assert a["rows_written"] >= a["rows_changed"]
         assert a["rows_loaded"] >= a["rows_changed"]
-    assert on["pass_stats"][0]["counters_gathered"] == m
-    assert sum(p["arcs_scanned"] for p in on["pass_stats"]) < on["passes"] * m
+    assert sparse["pass_stats"][0]["counters_gathered"] == m
+    assert sum(p["arcs_scanned"] for p in sparse["pass_stats"]) < sparse["passes"] * m
+    assert sum(p["slices_gathered"] for p in sliced["pass_stats"]) < sliced["passes"] * m * G
     # the last pass visits only rows next to the previous pass's changes
-    assert on["pass_stats"][-1]["rows_loaded"] < nonempty
+    assert sparse["pass_stats"][-1]["rows_loaded"] < nonempty
 
 
 def test_validation_rejects_bad_indices():
