@@ -201,6 +201,35 @@ typedef struct {
 
 hb_status hb_pass_stats(hb_ctx* c, int32_t pass, hb_pass_info* info);
 
+/* ---- Batched form: many independent graphs in one context -------------
+ * hb_batch_init packs k host CSRs into one device arena (graph i keeps its
+ * own node ids 0..n_i-1 for hashing, with seed seeds[i]) and runs every graph
+ * exactly as hb_init/hb_run would run it alone: the same registers, pass
+ * counts and floating-point results, bit for bit.  Passes are driven from the
+ * device (mode, pass index and convergence live in device memory), run
+ * persistent kernels over all unconverged graphs at once, and hb_run replays
+ * them as a captured hipGraph with one small readback per replay.
+ * log2m in [4, 8].  With stream NULL the context creates its own stream.
+ * On a batched context: hb_run runs until every graph converged (or the
+ * engine pass cap); hb_iterate runs one pass over all graphs; outputs of
+ * hb_centralities / hb_get_accumulators / hb_get_registers are packed: graph
+ * 0's n_0 nodes, then graph 1's, ... (sum n_i entries); hb_reset restarts with
+ * the same seeds (hb_batch_reset changes them); hb_pass_stats is not kept. */
+typedef struct {
+  int64_t n;              /* nodes of the graph */
+  int64_t packed_offset;  /* its first entry in packed outputs */
+  int32_t passes;         /* its pass count (valid once converged) */
+  int32_t converged;
+} hb_graph_info;
+
+hb_status hb_batch_init(hb_ctx** out, const hb_csr* graphs, int32_t k, int32_t log2m,
+                        const uint64_t* seeds, const hb_options* opt, void* stream);
+/* New seeds (k entries; NULL keeps them) and a restart from pass 0. */
+hb_status hb_batch_reset(hb_ctx* c, const uint64_t* seeds);
+hb_status hb_batch_graph(hb_ctx* c, int32_t g, hb_graph_info* info);
+/* Per-graph pass counts (k entries; -1 for a graph not converged yet). */
+hb_status hb_batch_passes(hb_ctx* c, int32_t* passes);
+
 /* Releases everything the context owns (never borrowed memory).  NULL-safe. */
 void hb_free(hb_ctx* c);
 

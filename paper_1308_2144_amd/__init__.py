@@ -69,6 +69,11 @@ class hb_pass_info(ctypes.Structure):
                 ("merge_ms", ctypes.c_double)]
 
 
+class hb_graph_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("packed_offset", ctypes.c_int64), ("passes", ctypes.c_int32),
+                ("converged", ctypes.c_int32)]
+
+
 def _declare(L):
     vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
     P = ctypes.POINTER
@@ -86,6 +91,10 @@ def _declare(L):
         "hb_free": (None, [vp]),
         "hb_last_error": (ctypes.c_char_p, []),
         "hb_version": (i32, []),
+        "hb_batch_init": (ctypes.c_int, [P(vp), vp, i32, i32, vp, P(hb_options), vp]),
+        "hb_batch_reset": (ctypes.c_int, [vp, vp]),
+        "hb_batch_graph": (ctypes.c_int, [vp, i32, P(hb_graph_info)]),
+        "hb_batch_passes": (ctypes.c_int, [vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -228,7 +237,47 @@ def hb_version() -> int:
     return lib().hb_version()
 
 
-# --- convenience wrapper --------------------------------------------------------
+def hb_batch_init(graphs, log2m: int, seeds, options: hb_options | None = None, stream=None):
+    """graphs: list of (offsets, indices) numpy CSRs.  Returns (ctx, keepalive)."""
+    k = len(graphs)
+    arr = (hb_csr * k)()
+    keep = []
+    for i, (o, x) in enumerate(graphs):
+        o = np.ascontiguousarray(o)
+        if o.dtype not in (np.int32, np.int64):
+            o = o.astype(np.int64)
+        x = np.ascontiguousarray(x, dtype=np.int32)
+        keep.append((o, x))
+        arr[i] = hb_csr(o.shape[0] - 1, x.shape[0], o.ctypes.data, 64 if o.dtype == np.int64 else 32,
+                        x.ctypes.data if x.size else None, 0)
+    sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+    if sd.shape[0] != k:
+        raise ValueError("need one seed per graph")
+    ctx = ctypes.c_void_p()
+    opt = ctypes.byref(options) if options is not None else None
+    _check(lib().hb_batch_init(ctypes.byref(ctx), ctypes.cast(arr, ctypes.c_void_p), k, int(log2m),
+                               sd.ctypes.data, opt, ctypes.c_void_p(stream) if stream else None))
+    return ctx, (arr, keep, sd)
+
+
+def hb_batch_reset(ctx, seeds=None):
+    sd = None if seeds is None else np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+    _check(lib().hb_batch_reset(ctx, None if sd is None else sd.ctypes.data))
+
+
+def hb_batch_graph(ctx, g: int) -> dict:
+    info = hb_graph_info()
+    _check(lib().hb_batch_graph(ctx, int(g), ctypes.byref(info)))
+    return {k: getattr(info, k) for k, _ in hb_graph_info._fields_}
+
+
+def hb_batch_passes(ctx, k: int) -> np.ndarray:
+    out = np.empty(k, dtype=np.int32)
+    _check(lib().hb_batch_passes(ctx, out.ctypes.data))
+    return out
+
+
+# --- convenience wrappers -------------------------------------------------------
 
 class HyperBall:
     """One HyperBall computation on one graph (see include/hb.h)."""
@@ -295,3 +344,72 @@ class HyperBall:
 
     def pass_stats(self, t: int) -> dict:
         return hb_pass_stats(self._ctx, t)
+
+
+class Batch:
+    """Many graphs in one batched context (see hb_batch_init in include/hb.h).
+    Packed outputs are split per graph with split()."""
+
+    def __init__(self, graphs, log2m: int, seeds, *, stream=None, **options):
+        self.log2m = int(log2m)
+        self.p = 1 << self.log2m
+        self.k = len(graphs)
+        self.sizes = np.array([len(o) - 1 for o, _ in graphs], dtype=np.int64)
+        self.bounds = np.concatenate([[0], np.cumsum(self.sizes)])
+        self.total = int(self.bounds[-1])
+        opt = default_options(**options)
+        self._ctx, self._keep = hb_batch_init(graphs, log2m, seeds, opt, stream)
+
+    def close(self):
+        if self._ctx is not None:
+            hb_free(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def split(self, packed):
+        return [packed[self.bounds[i]:self.bounds[i + 1]] for i in range(self.k)]
+
+    def run(self, max_passes: int = 0) -> int:
+        return hb_run(self._ctx, max_passes)
+
+    def iterate(self) -> int:
+        return hb_iterate(self._ctx)
+
+    def reset(self, seeds=None):
+        hb_batch_reset(self._ctx, seeds)
+
+    def passes(self) -> np.ndarray:
+        return hb_batch_passes(self._ctx, self.k)
+
+    def graph(self, g: int) -> dict:
+        return hb_batch_graph(self._ctx, g)
+
+    def registers(self) -> np.ndarray:
+        out = np.empty((max(self.total, 1), self.p), dtype=np.uint8)
+        hb_get_registers(self._ctx, out, False)
+        return out[: self.total]
+
+    def accumulators(self):
+        S = np.empty(max(self.total, 1))
+        H = np.empty(max(self.total, 1))
+        hb_get_accumulators(self._ctx, S, H, False)
+        return S[: self.total], H[: self.total]
+
+    def centralities(self):
+        outs = [np.empty(max(self.total, 1)) for _ in range(4)]
+        hb_centralities(self._ctx, *outs, False)
+        return dict(zip(("closeness", "lin", "harmonic", "coreach"), (o[: self.total] for o in outs)))
+
+    def stats(self) -> dict:
+        return hb_stats(self._ctx)

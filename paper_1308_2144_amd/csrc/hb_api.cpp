@@ -93,6 +93,19 @@ struct hb_ctx {
   int64_t last_slices = -1;
   int64_t last_pairs = -1;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // Multi-graph (batched) contexts.
+  int32_t n_graphs = 0;
+  std::vector<hb::GraphDev> graphs_host;
+  hb::GraphDev* graphs = nullptr;
+  int32_t* blk_graph = nullptr;
+  hb::PassCtl* ctl = nullptr;
+  hb::PassCtl* ctl_host = nullptr;  // pinned
+  int64_t n_packed = 0;
+  int persist_wgs = 0;
+  int graph_passes = 0;              // passes per hipGraph replay
+  hipGraphExec_t gexec = nullptr;
+  bool own_stream = false;
+  double* arena_tmp = nullptr;       // n doubles, arena layout staging for packed outputs
   std::vector<hb_pass_info> hist;
   double total_ms = 0.0;
   bool failed = false;
@@ -126,6 +139,13 @@ void release(hb_ctx* c) {
   (void)hipFree(c->stats);
   (void)hipFree(c->out_tmp);
   (void)hipFree(c->bad);
+  (void)hipFree(c->graphs);
+  (void)hipFree(c->blk_graph);
+  (void)hipFree(c->ctl);
+  (void)hipFree(c->arena_tmp);
+  if (c->ctl_host) (void)hipHostFree(c->ctl_host);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   if (c->stats_host) (void)hipHostFree(c->stats_host);
   for (int i = 0; i < 4; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
@@ -185,13 +205,33 @@ hb_status do_reset(hb_ctx* c, uint64_t seed) {
   HB_HIP(hb::launch_fill_zero(c->stats, sizeof(unsigned long long) * 2 * hb::STAT_SLOTS * hb::STAT_K,
                               c->stream));
   if (c->act) HB_HIP(hb::launch_fill_zero(c->act, sizeof(int32_t) * (size_t)c->n, c->stream));
+  if (c->n_graphs > 0) {
+    for (auto& gd : c->graphs_host) {
+      gd.t0 = 0;
+      gd.done = 0;
+      gd.passes = 0;
+    }
+    HB_HIP(hipMemcpyAsync(c->graphs, c->graphs_host.data(), sizeof(hb::GraphDev) * c->graphs_host.size(),
+                          hipMemcpyHostToDevice, c->stream));
+    hb::PassCtl& k = *c->ctl_host;
+    k.t = 0;
+    k.mode = hb::MODE_FIRST;
+    k.parity = 0;
+    k.n_done = 0;
+    k.work = 0;
+    HB_HIP(hipMemcpyAsync(c->ctl, c->ctl_host, sizeof(hb::PassCtl), hipMemcpyHostToDevice, c->stream));
+    HB_HIP(hb::launch_init_arena(c->b, 0, c->n, c->blk_graph, c->graphs, c->cnt[0], c->cnt[1], c->S, c->H, c->E,
+                                 c->lc, c->alpha_pp, c->stream));
+    HB_HIP(hipStreamSynchronize(c->stream));  // ctl_host is reused by the next readback
+    return HB_OK;
+  }
   HB_HIP(hb::launch_init_nodes(c->b, c->n, seed, c->cnt[0], c->cnt[1], c->S, c->H, c->E, c->lc,
                                c->alpha_pp, c->stream));
   return HB_OK;
 }
 
 hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, const hb_options* opt,
-                    void* stream) {
+                    void* stream, const std::vector<int32_t>* blk_graph = nullptr) {
   c->n = g->n;
   c->m = g->m;
   c->b = log2m;
@@ -317,9 +357,129 @@ hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, co
   std::vector<double> lc((size_t)c->p + 1, 0.0);
   for (int V = 1; V <= c->p; ++V) lc[(size_t)V] = (double)c->p * std::log((double)c->p / (double)V);
   HB_HIP(hipMemcpyAsync(c->lc, lc.data(), sizeof(double) * lc.size(), hipMemcpyHostToDevice, c->stream));
+  if (blk_graph) {
+    // Multi-graph context: per-graph state, block map and device pass control.
+    HB_HIP(dmalloc(&c->graphs, c->graphs_host.size()));
+    HB_HIP(dmalloc(&c->blk_graph, blk_graph->size()));
+    if (!blk_graph->empty())
+      HB_HIP(hipMemcpyAsync(c->blk_graph, blk_graph->data(), sizeof(int32_t) * blk_graph->size(),
+                            hipMemcpyHostToDevice, c->stream));
+    HB_HIP(dmalloc(&c->ctl, 1));
+    HB_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->ctl_host), sizeof(hb::PassCtl), hipHostMallocDefault));
+    std::memset(c->ctl_host, 0, sizeof(hb::PassCtl));
+    hb::PassCtl& k = *c->ctl_host;
+    k.listed_rows = c->n_nonempty;
+    k.arcs = c->m;
+    k.frontier = c->opt.frontier;
+    k.dense_pct = c->opt.dense_pct;
+    k.sparse_pct = c->opt.sparse_pct;
+    k.has_reverse = c->roff ? 1 : 0;
+    k.n_graphs = c->n_graphs;
+    HB_HIP(dmalloc(&c->arena_tmp, (size_t)n));
+    int dev = 0;
+    HB_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HB_HIP(hipGetDeviceProperties(&prop, dev));
+    c->persist_wgs = prop.multiProcessorCount * 5;
+    c->graph_passes = 4;
+  }
   hb_status st = do_reset(c, seed);
   if (st != HB_OK) return st;
   HB_HIP(hipStreamSynchronize(c->stream));  // host staging vectors die here
+  return HB_OK;
+}
+
+// Arguments of a device-driven pass (buffers, mode and pass index are
+// resolved on the device from ctl).
+hb::PassArgs device_args(hb_ctx* c) {
+  hb::PassArgs a{};
+  a.off = c->off;
+  a.idx = c->idx;
+  a.S = c->S;
+  a.H = c->H;
+  a.E = c->E;
+  a.lc = c->lc;
+  a.light = c->light;
+  a.medium = c->medium;
+  a.items = c->items;
+  a.hrows = c->hrows;
+  a.partial = c->partial;
+  a.act = c->act;
+  a.roff = c->roff;
+  a.ridx = c->ridx;
+  a.alpha_pp = c->alpha_pp;
+  a.n = c->n;
+  a.n_blocks = c->n_blocks;
+  a.n_light = c->n_light;
+  a.n_medium = c->n_medium;
+  a.n_items = c->n_items;
+  a.n_hrows = c->n_hrows;
+  a.qdense = c->opt.qdense ? 1 : 0;
+  a.blk_graph = c->blk_graph;
+  a.graphs = c->graphs;
+  a.ctl = c->ctl;
+  a.cntb[0] = c->cnt[0];
+  a.cntb[1] = c->cnt[1];
+  a.modb[0] = c->mod[0];
+  a.modb[1] = c->mod[1];
+  a.stats_base = c->stats;
+  a.n_graphs = c->n_graphs;
+  return a;
+}
+
+hb_status read_ctl(hb_ctx* c) {
+  HB_HIP(hipMemcpyAsync(c->ctl_host, c->ctl, sizeof(hb::PassCtl), hipMemcpyDeviceToHost, c->stream));
+  HB_HIP(hipStreamSynchronize(c->stream));
+  c->t = c->ctl_host->t;
+  c->converged = c->ctl_host->n_done >= c->n_graphs;
+  return HB_OK;
+}
+
+// Passes of a multi-graph context until every graph converged (or
+// max_passes engine passes ran): replays of a hipGraph holding graph_passes
+// device-driven passes, one 64-byte readback per replay.  Passes after a
+// graph converged skip its rows, so overshooting is harmless; with a pass
+// cap the passes are enqueued one by one instead.
+hb_status multi_run(hb_ctx* c, int32_t max_passes) {
+  hb_status st = read_ctl(c);
+  if (st != HB_OK) return st;
+  const hb::PassArgs a = device_args(c);
+  if (max_passes > 0) {
+    while (!c->converged && c->t < max_passes) {
+      HB_HIP(hb::launch_device_pass(c->b, a, c->persist_wgs, c->push_items, c->push_count, c->n, c->stream));
+      st = read_ctl(c);
+      if (st != HB_OK) return st;
+    }
+    return HB_OK;
+  }
+  if (!c->gexec) {
+    hipGraph_t graph = nullptr;
+    HB_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < c->graph_passes && e == hipSuccess; ++k)
+      e = hb::launch_device_pass(c->b, a, c->persist_wgs, c->push_items, c->push_count, c->n, c->stream);
+    const hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
+    if (e != hipSuccess) return fail(HB_EDEVICE, std::string("pass capture: ") + hipGetErrorString(e));
+    if (e2 != hipSuccess) return fail(HB_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
+    e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(HB_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  while (!c->converged) {
+    HB_HIP(hipGraphLaunch(c->gexec, c->stream));
+    st = read_ctl(c);
+    if (st != HB_OK) return st;
+  }
+  return HB_OK;
+}
+
+hb_status multi_pack(hb_ctx* c, const double* src, double* dst, int32_t dst_on_device) {
+  if (dst_on_device) return hb::launch_pack(src, dst, c->n, c->blk_graph, c->graphs, c->stream) == hipSuccess
+                                ? HB_OK
+                                : fail(HB_EDEVICE, "pack");
+  double* tmp = c->arena_tmp;
+  HB_HIP(hb::launch_pack(src, tmp, c->n, c->blk_graph, c->graphs, c->stream));
+  HB_HIP(hipMemcpyAsync(dst, tmp, sizeof(double) * (size_t)c->n_packed, hipMemcpyDeviceToHost, c->stream));
   return HB_OK;
 }
 
@@ -391,6 +551,23 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
   if (st != HB_OK) return st;
   if (n_modified) *n_modified = 0;
   if (c->converged) return HB_OK;
+  if (c->n_graphs > 0) {
+    // One device-driven pass over every unconverged graph of the batch.
+    const int32_t t_before = c->t;
+    HB_HIP(hb::launch_device_pass(c->b, device_args(c), c->persist_wgs, c->push_items, c->push_count, c->n,
+                                  c->stream));
+    st = read_ctl(c);
+    if (st != HB_OK) return st;
+    const size_t half = (size_t)hb::STAT_SLOTS * hb::STAT_K;
+    HB_HIP(hipMemcpyAsync(c->stats_host, c->stats + (size_t)(t_before & 1) * half,
+                          sizeof(unsigned long long) * half, hipMemcpyDeviceToHost, c->stream));
+    HB_HIP(hipStreamSynchronize(c->stream));
+    int64_t chg = 0;
+    for (int sl = 0; sl < hb::STAT_SLOTS; ++sl) chg += (int64_t)c->stats_host[sl * hb::STAT_K + 3];
+    c->last_nmod = chg;
+    if (n_modified) *n_modified = chg;
+    return HB_OK;
+  }
   hb_pass_info info{};
   if (c->n == 0) {
     c->hist.push_back(info);
@@ -510,6 +687,15 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
 hb_status hb_run(hb_ctx* c, int32_t max_passes, int32_t* passes) {
   hb_status st = check_ctx(c);
   if (st != HB_OK) return st;
+  if (c->n_graphs > 0) {
+    st = multi_run(c, max_passes);
+    if (st != HB_OK) {
+      c->failed = true;
+      return st;
+    }
+    if (passes) *passes = c->t;
+    return HB_OK;
+  }
   while (!c->converged && (max_passes <= 0 || c->t < max_passes)) {
     st = hb_iterate(c, nullptr);
     if (st != HB_OK) return st;
@@ -534,6 +720,23 @@ hb_status hb_centralities(hb_ctx* c, double* closeness, double* lin, double* har
   }
   double* d[4] = {c->out_tmp, c->out_tmp + n, c->out_tmp + 2 * n, c->out_tmp + 3 * n};
   double* h[4] = {closeness, lin, harmonic, coreach};
+  if (c->n_graphs > 0) {
+    // Arena-layout results, then packed graph by graph (padding dropped).
+    HB_HIP(hb::launch_finalize(c->n, c->S, c->H, c->E, d[0], d[1], d[2], d[3], c->stream));
+    for (int i = 0; i < 4; ++i) {
+      if (!h[i]) continue;
+      if (dst_on_device) {
+        HB_HIP(hb::launch_pack(d[i], h[i], c->n, c->blk_graph, c->graphs, c->stream));
+      } else {
+        HB_HIP(hb::launch_pack(d[i], c->arena_tmp, c->n, c->blk_graph, c->graphs, c->stream));
+        HB_HIP(hipMemcpyAsync(h[i], c->arena_tmp, sizeof(double) * (size_t)c->n_packed, hipMemcpyDeviceToHost,
+                              c->stream));
+        HB_HIP(hipStreamSynchronize(c->stream));
+      }
+    }
+    HB_HIP(hipStreamSynchronize(c->stream));
+    return HB_OK;
+  }
   HB_HIP(hb::launch_finalize(c->n, c->S, c->H, c->E, h[0] ? d[0] : nullptr, h[1] ? d[1] : nullptr,
                              h[2] ? d[2] : nullptr, h[3] ? d[3] : nullptr, c->stream));
   for (int i = 0; i < 4; ++i)
@@ -548,6 +751,24 @@ hb_status hb_get_registers(hb_ctx* c, uint8_t* dst, int32_t dst_on_device) {
   if (!dst) return fail(HB_EINVAL, "dst is NULL");
   const size_t bytes = (size_t)c->n * (size_t)c->p;
   if (bytes == 0) return HB_OK;
+  if (c->n_graphs > 0) {
+    const uint8_t* src = c->cnt[c->ctl_host->parity];
+    if (dst_on_device) {
+      HB_HIP(hb::launch_pack_u8(src, dst, c->n, c->p, c->blk_graph, c->graphs, c->stream));
+    } else {
+      uint8_t* tmp = nullptr;
+      if (dmalloc(&tmp, (size_t)c->n_packed * (size_t)c->p) != hipSuccess)
+        return fail(HB_ENOMEM, "cannot allocate register staging");
+      hipError_t e = hb::launch_pack_u8(src, tmp, c->n, c->p, c->blk_graph, c->graphs, c->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(dst, tmp, (size_t)c->n_packed * (size_t)c->p, hipMemcpyDeviceToHost, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      (void)hipFree(tmp);
+      if (e != hipSuccess) return fail(HB_EDEVICE, std::string("registers: ") + hipGetErrorString(e));
+    }
+    HB_HIP(hipStreamSynchronize(c->stream));
+    return HB_OK;
+  }
   HB_HIP(hipMemcpyAsync(dst, c->cnt[c->cur], bytes,
                         dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
   HB_HIP(hipStreamSynchronize(c->stream));
@@ -559,6 +780,19 @@ hb_status hb_get_accumulators(hb_ctx* c, double* S, double* H, int32_t dst_on_de
   if (st != HB_OK) return st;
   const size_t bytes = sizeof(double) * (size_t)c->n;
   if (bytes == 0) return HB_OK;
+  if (c->n_graphs > 0) {
+    if (S) {
+      st = multi_pack(c, c->S, S, dst_on_device);
+      if (st != HB_OK) return st;
+    }
+    if (H) {
+      HB_HIP(hipStreamSynchronize(c->stream));
+      st = multi_pack(c, c->H, H, dst_on_device);
+      if (st != HB_OK) return st;
+    }
+    HB_HIP(hipStreamSynchronize(c->stream));
+    return HB_OK;
+  }
   const hipMemcpyKind k = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   if (S) HB_HIP(hipMemcpyAsync(S, c->S, bytes, k, c->stream));
   if (H) HB_HIP(hipMemcpyAsync(H, c->H, bytes, k, c->stream));
@@ -585,8 +819,133 @@ hb_status hb_stats(hb_ctx* c, hb_stats_t* s) {
 
 hb_status hb_pass_stats(hb_ctx* c, int32_t pass, hb_pass_info* info) {
   if (!c || !info) return fail(HB_EINVAL, "NULL argument");
+  if (c->n_graphs > 0) return fail(HB_EINVAL, "batched contexts keep no per-pass records");
   if (pass < 0 || pass >= (int32_t)c->hist.size()) return fail(HB_EINVAL, "no such pass");
   *info = c->hist[(size_t)pass];
+  return HB_OK;
+}
+
+hb_status hb_batch_init(hb_ctx** out, const hb_csr* graphs, int32_t k, int32_t log2m, const uint64_t* seeds,
+                        const hb_options* opt, void* stream) {
+  if (!out) return fail(HB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!graphs || !seeds || k <= 0) return fail(HB_EINVAL, "need k >= 1 graphs and k seeds");
+  if (log2m < 4 || log2m > 8) return fail(HB_EINVAL, "batched contexts need log2m in [4, 8]");
+  // Arena: graph i owns nodes [base_i, base_i + n_i), padded to a multiple of
+  // 64 so that no 64-node block spans two graphs; arcs are concatenated.
+  std::vector<hb::GraphDev> gh((size_t)k);
+  int64_t nodes = 0, arcs = 0, packed = 0;
+  for (int32_t i = 0; i < k; ++i) {
+    const hb_csr& g = graphs[i];
+    if (g.on_device) return fail(HB_EINVAL, "batched graphs must be host CSRs");
+    if (g.n < 0 || g.m < 0 || (g.offsets_bits != 32 && g.offsets_bits != 64) || !g.offsets ||
+        (g.m > 0 && !g.indices))
+      return fail(HB_EINVAL, "graph " + std::to_string(i) + ": malformed CSR description");
+    gh[(size_t)i].node_base = nodes;
+    gh[(size_t)i].n = g.n;
+    gh[(size_t)i].packed = packed;
+    gh[(size_t)i].seed = seeds[i];
+    gh[(size_t)i].active = 1;
+    nodes += (g.n + 63) / 64 * 64;
+    arcs += g.m;
+    packed += g.n;
+  }
+  if (nodes > 0x7fffffffLL) return fail(HB_EINVAL, "batch too large for int32 node ids");
+  std::vector<int64_t> off((size_t)nodes + 1);
+  std::vector<int32_t> idx((size_t)(arcs > 0 ? arcs : 1));
+  std::vector<int32_t> blk((size_t)(nodes / 64));
+  int64_t a = 0;
+  const bool validate = !opt || opt->validate;
+  for (int32_t i = 0; i < k; ++i) {
+    const hb_csr& g = graphs[i];
+    const int64_t base = gh[(size_t)i].node_base;
+    const int64_t npad = (g.n + 63) / 64 * 64;
+    for (int64_t b = base / 64; b < (base + npad) / 64; ++b) blk[(size_t)b] = i;
+    for (int64_t v = 0; v <= g.n; ++v) {
+      const int64_t o = g.offsets_bits == 64 ? static_cast<const int64_t*>(g.offsets)[v]
+                                             : static_cast<const int32_t*>(g.offsets)[v];
+      if (validate && (o < 0 || o > g.m || (v > 0 && o < off[(size_t)(base + v - 1)] - a) ||
+                       (v == 0 && o != 0) || (v == g.n && o != g.m)))
+        return fail(HB_EINVAL, "graph " + std::to_string(i) + ": malformed offsets");
+      off[(size_t)(base + v)] = a + o;
+    }
+    for (int64_t v = g.n + 1; v <= npad; ++v) off[(size_t)(base + v)] = a + g.m;
+    for (int64_t e = 0; e < g.m; ++e) {
+      const int32_t w = g.indices[e];
+      if (validate && (w < 0 || w >= g.n))
+        return fail(HB_EINVAL, "graph " + std::to_string(i) + ": index outside [0, n)");
+      idx[(size_t)(a + e)] = (int32_t)(base + w);
+    }
+    a += g.m;
+  }
+  hb_ctx* c = new (std::nothrow) hb_ctx();
+  if (!c) return fail(HB_ENOMEM, "cannot allocate context");
+  c->n_graphs = k;
+  c->graphs_host = gh;
+  c->n_packed = packed;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (!s) {
+    // hipGraph capture needs a stream other than the legacy default one.
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return fail(HB_EDEVICE, "cannot create a stream");
+    }
+    c->own_stream = true;
+  }
+  hb_csr arena;
+  arena.n = nodes;
+  arena.m = arcs;
+  arena.offsets = off.data();
+  arena.offsets_bits = 64;
+  arena.indices = idx.data();
+  arena.on_device = 0;
+  const hb_status st = init_impl(c, &arena, log2m, 0, opt, s, &blk);
+  if (st != HB_OK) {
+    const std::string msg = g_err;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    release(c);
+    g_err = msg;
+    return st;
+  }
+  *out = c;
+  return HB_OK;
+}
+
+hb_status hb_batch_reset(hb_ctx* c, const uint64_t* seeds) {
+  hb_status st = check_ctx(c);
+  if (st != HB_OK) return st;
+  if (c->n_graphs == 0) return fail(HB_EINVAL, "not a batched context");
+  if (seeds)
+    for (int32_t i = 0; i < c->n_graphs; ++i) c->graphs_host[(size_t)i].seed = seeds[i];
+  st = do_reset(c, 0);
+  if (st != HB_OK) c->failed = true;
+  return st;
+}
+
+hb_status hb_batch_graph(hb_ctx* c, int32_t g, hb_graph_info* info) {
+  hb_status st = check_ctx(c);
+  if (st != HB_OK) return st;
+  if (!info) return fail(HB_EINVAL, "info is NULL");
+  if (c->n_graphs == 0 || g < 0 || g >= c->n_graphs) return fail(HB_EINVAL, "no such graph");
+  hb::GraphDev gd;
+  HB_HIP(hipMemcpyAsync(&gd, c->graphs + g, sizeof(gd), hipMemcpyDeviceToHost, c->stream));
+  HB_HIP(hipStreamSynchronize(c->stream));
+  info->n = gd.n;
+  info->packed_offset = gd.packed;
+  info->passes = gd.passes;
+  info->converged = gd.done;
+  return HB_OK;
+}
+
+hb_status hb_batch_passes(hb_ctx* c, int32_t* passes) {
+  hb_status st = check_ctx(c);
+  if (st != HB_OK) return st;
+  if (!passes) return fail(HB_EINVAL, "passes is NULL");
+  if (c->n_graphs == 0) return fail(HB_EINVAL, "not a batched context");
+  std::vector<hb::GraphDev> gh((size_t)c->n_graphs);
+  HB_HIP(hipMemcpyAsync(gh.data(), c->graphs, sizeof(hb::GraphDev) * gh.size(), hipMemcpyDeviceToHost, c->stream));
+  HB_HIP(hipStreamSynchronize(c->stream));
+  for (size_t i = 0; i < gh.size(); ++i) passes[i] = gh[i].done ? gh[i].passes : -1;
   return HB_OK;
 }
 

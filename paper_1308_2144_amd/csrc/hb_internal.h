@@ -45,6 +45,38 @@ enum PassMode : int32_t {
   MODE_EDGE = 4,    // every listed row runs and gathers only changed successors
 };
 
+// Per-graph state of a multi-graph context (batched or served graphs).
+// Nodes node_base .. node_base+n-1 of the arena belong to the graph; the
+// region is padded to a multiple of 64 with empty rows.
+struct GraphDev {
+  int64_t node_base;
+  int64_t n;
+  int64_t packed;     // first index of the graph in packed (unpadded) outputs
+  uint64_t seed;
+  int32_t t0;         // engine pass at which the graph's pass 0 runs
+  int32_t done;       // 1 once one of its passes changed none of its counters
+  int32_t passes;     // its pass count at convergence (the unchanged pass included)
+  int32_t active;     // slot in use
+};
+
+// Device-resident pass control of a multi-graph context: every pass reads
+// its mode, pass index and buffer parity here, and the bookkeeping kernels at
+// the end of the pass write the next ones, so passes need no host round trip
+// (and can be captured in a hipGraph).
+struct PassCtl {
+  int32_t t;                   // engine pass index
+  int32_t mode;                // PassMode of the pass about to run
+  int32_t parity;              // counter buffer holding the current counters
+  int32_t n_done;              // graphs converged so far
+  unsigned long long work;     // persistent work-queue cursor
+  // planning inputs (set by the host)
+  int64_t listed_rows;         // non-empty rows of the resident graphs
+  int64_t arcs;                // arcs of the resident graphs
+  int32_t frontier, dense_pct, sparse_pct, has_reverse;
+  int32_t n_graphs;
+  int32_t pad;
+};
+
 // Everything one pass needs.  `cur` holds counters of radius t, `nxt`
 // receives radius t+1.  mod_prev has bit v set if counter v changed in the
 // previous pass; mod_cur (zeroed before the pass) receives this pass's bits.
@@ -68,6 +100,7 @@ struct PassArgs {
   uint8_t* partial;                  // n_items * p bytes
   const int32_t* act;                // act[v] == epoch: v has a changed successor (sparse)
   const int64_t* roff;               // reverse CSR offsets (nullable): in-degrees for the stats
+  const int32_t* ridx;               // reverse CSR indices (nullable)
   unsigned long long* stats;         // this pass: STAT_SLOTS * STAT_K
   unsigned long long* stats_next;    // zeroed by this pass for the next one
   double alpha_pp;                   // (alpha_p * p) * p
@@ -81,6 +114,17 @@ struct PassArgs {
   int32_t epoch;
   int32_t mode;                      // PassMode
   int32_t qdense;                    // dense passes use the queued gather too
+  // Multi-graph contexts (null otherwise): graph of each 64-node block, the
+  // per-graph state, and the device pass control; with ctl set, cur/nxt,
+  // mod_prev/mod_cur, mode, epoch and the stats halves are taken from ctl
+  // (buffers cntb[], modb[], stats_base).
+  const int32_t* blk_graph;
+  GraphDev* graphs;
+  PassCtl* ctl;
+  uint8_t* cntb[2];
+  uint64_t* modb[2];
+  unsigned long long* stats_base;
+  int32_t n_graphs;                  // graph slots (multi-graph contexts)
 };
 
 // Launchers (hb_kernels.hip).  All return the launch status.
@@ -88,6 +132,21 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_init_nodes(int log2m, int64_t n, uint64_t seed, uint8_t* cur, uint8_t* nxt,
                              double* S, double* H, double* E, const double* lc, double alpha_pp,
                              hipStream_t s);
+// Multi-graph initialisation of arena nodes [v0, v1): node v hashes its
+// graph-local id with its graph's seed; padding rows get empty counters.
+hipError_t launch_init_arena(int log2m, int64_t v0, int64_t v1, const int32_t* blk_graph,
+                             const GraphDev* graphs, uint8_t* cur, uint8_t* nxt, double* S, double* H,
+                             double* E, const double* lc, double alpha_pp, hipStream_t s);
+// One device-driven pass of a multi-graph context: push (sparse passes
+// only), persistent expand, merge, per-graph convergence, next-pass planning
+// and clearing of the next change bitmap.  Enqueues only (capturable).
+hipError_t launch_device_pass(int log2m, const PassArgs& a, int persist_wgs, uint2* push_items,
+                              unsigned long long* push_count, int64_t n_arena, hipStream_t s);
+// Copies arena-layout values of graph nodes into packed graph-order arrays.
+hipError_t launch_pack(const double* src, double* dst, int64_t n_arena, const int32_t* blk_graph,
+                       const GraphDev* graphs, hipStream_t s);
+hipError_t launch_pack_u8(const uint8_t* src, uint8_t* dst, int64_t n_arena, int p, const int32_t* blk_graph,
+                          const GraphDev* graphs, hipStream_t s);
 // ev_mid (nullable) is recorded between the expand and merge kernels.
 hipError_t launch_pass(int log2m, const PassArgs& a, hipStream_t s, hipEvent_t ev_mid);
 hipError_t launch_finalize(int64_t n, const double* S, const double* H, const double* E,

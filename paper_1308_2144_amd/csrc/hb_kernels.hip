@@ -245,10 +245,41 @@ struct Counts {
 // own_mod: the row's counter changed in the previous pass (so the next buffer
 // holds a stale copy).  need: the row takes part in this pass.  In a sparse
 // pass a row without a changed successor cannot change; it only runs to
-// refresh a stale copy.
+// refresh a stale copy.  Rows of converged graphs never run.
+template <bool MG>
 __device__ __forceinline__ void row_flags(const PassArgs& A, int64_t row, bool& own_mod, bool& need) {
   own_mod = A.mode != MODE_FIRST && bit_of(A.mod_prev, row);
   need = A.mode != MODE_SPARSE || own_mod || A.act == nullptr || A.act[row] == A.epoch;
+  if constexpr (MG) {
+    if (A.graphs[A.blk_graph[row >> 6]].done) need = false;
+  }
+}
+
+// Distance weight of this pass for a row: t+1, counted from the pass at which
+// the row's graph started.
+template <bool MG>
+__device__ __forceinline__ double row_d(const PassArgs& A, int64_t row) {
+  if constexpr (MG) return (double)(A.epoch - A.graphs[A.blk_graph[row >> 6]].t0);
+  return A.d;
+}
+
+// With device pass control, the pass's buffers and mode come from ctl.
+__device__ __forceinline__ PassArgs resolve(const PassArgs& A) {
+  if (!A.ctl) return A;
+  PassArgs L = A;
+  const int par = A.ctl->parity;
+  const int t = A.ctl->t;
+  L.cur = A.cntb[par];
+  L.nxt = A.cntb[par ^ 1];
+  L.mod_prev = A.modb[par];
+  L.mod_cur = A.modb[par ^ 1];
+  L.mode = A.ctl->mode;
+  L.epoch = t + 1;
+  L.d = (double)(t + 1);
+  L.act = (L.mode == MODE_SPARSE) ? A.act : nullptr;
+  L.stats = A.stats_base + (size_t)(t & 1) * STAT_SLOTS * STAT_K;
+  L.stats_next = A.stats_base + (size_t)((t + 1) & 1) * STAT_SLOTS * STAT_K;
+  return L;
 }
 
 // Direct gather-max (dense passes) over the arcs k, k+st, k+2st, ... < e of
@@ -426,7 +457,7 @@ __device__ __forceinline__ RowPre preload(const PassArgs& A, int64_t row, int gl
 // Completes row `row` for a group of G lanes: a = own U gathered, write-back
 // rule, change detection, the fused estimator/accumulator, the change bit
 // and the mask of changed slices.  Returns whether the counter changed.
-template <int B>
+template <int B, bool MG>
 __device__ __forceinline__ bool finish_row(const PassArgs& A, int64_t row, uint4 acc, bool got,
                                            const RowPre& pre, bool own_mod, int gl, int grp,
                                            Counts& c) {
@@ -459,8 +490,9 @@ __device__ __forceinline__ bool finish_row(const PassArgs& A, int64_t row, uint4
     if (gl == 0) {
       const double En = estimate(big, small, V, A.alpha_pp, (double)P, A.lc);
       const double delta = En - pre.e;
-      st_stream(A.S + row, pre.s + A.d * delta);
-      st_stream(A.H + row, pre.h + delta / A.d);
+      const double d = row_d<MG>(A, row);
+      st_stream(A.S + row, pre.s + d * delta);
+      st_stream(A.H + row, pre.h + delta / d);
       st_stream(A.E + row, En);
       if (A.dmask_cur) A.dmask_cur[row] = (uint16_t)msk;
       atomicOr(A.mod_cur + (row >> 6), 1ull << (row & 63));
@@ -495,7 +527,7 @@ __device__ __forceinline__ uint64_t lanes_below(int lane) { return (1ull << lane
 
 // 64 consecutive entries of the light-row list per wavefront; entry
 // q*W + grp goes to lane group grp in round q.
-template <int B, bool Q>
+template <int B, bool Q, bool MG>
 __device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, int64_t lw, int lane) {
   constexpr int P = 1 << B;
   constexpr int G = P / 16;
@@ -509,7 +541,7 @@ __device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, int64_t 
     row = A.light[i];
     s = A.off[row];
     deg = A.off[row + 1] - s;
-    row_flags(A, row, own_mod, need);
+    row_flags<MG>(A, row, own_mod, need);
   }
   const uint64_t needs = __ballot(need);
   const uint64_t mods = __ballot(own_mod);
@@ -532,7 +564,7 @@ __device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, int64_t 
         else
           acc = gather<B>(A, rs, rs + rd, 1, gl, got, c);
         if (gl == 0) c.arcs += (uint32_t)rd;
-        finish_row<B>(A, rrow, acc, got, pre, rmod, gl, grp, c);
+        finish_row<B, MG>(A, rrow, acc, got, pre, rmod, gl, grp, c);
       }
     }
   }
@@ -541,7 +573,7 @@ __device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, int64_t 
 
 // One medium row per wavefront: the groups share its arcs and reduce their
 // partial maxima by shuffles.
-template <int B, bool Q>
+template <int B, bool Q, bool MG>
 __device__ __forceinline__ void medium_wave(const PassArgs& A, QEnt* qw, int64_t mi, int lane) {
   constexpr int P = 1 << B;
   constexpr int G = P / 16;
@@ -552,7 +584,7 @@ __device__ __forceinline__ void medium_wave(const PassArgs& A, QEnt* qw, int64_t
   const int64_t s = A.off[row];
   const int64_t deg = A.off[row + 1] - s;
   bool own_mod, need;
-  row_flags(A, row, own_mod, need);
+  row_flags<MG>(A, row, own_mod, need);
   Counts c{};
   if (need) {
     RowPre pre;
@@ -567,14 +599,14 @@ __device__ __forceinline__ void medium_wave(const PassArgs& A, QEnt* qw, int64_t
 #pragma unroll
     for (int o = G; o < 64; o <<= 1) acc = bmax(acc, shfl_xor4(acc, o));
     got = __ballot(got) != 0ull;
-    if (grp == 0) finish_row<B>(A, row, acc, got, pre, own_mod, gl, 0, c);
+    if (grp == 0) finish_row<B, MG>(A, row, acc, got, pre, own_mod, gl, 0, c);
   }
   flush_counts(A, c, mi, lane);
 }
 
 // One chunk of a heavy row per workgroup (4 wavefronts): writes the chunk's
 // partial maximum for the merge kernel.
-template <int B, bool Q>
+template <int B, bool Q, bool MG>
 __device__ __forceinline__ void heavy_chunk(const PassArgs& A, QEnt* qw, int64_t item, int lane, int wave) {
   constexpr int P = 1 << B;
   constexpr int G = P / 16;
@@ -584,7 +616,7 @@ __device__ __forceinline__ void heavy_chunk(const PassArgs& A, QEnt* qw, int64_t
   const int grp = lane / G;
   const HeavyItem it = A.items[item];
   bool own_mod, need;
-  row_flags(A, it.row, own_mod, need);
+  row_flags<MG>(A, it.row, own_mod, need);
   if (!need) return;  // uniform over the workgroup; the merge kernel skips the row too
   bool got = false;
   Counts c{};
@@ -612,30 +644,38 @@ __device__ __forceinline__ void heavy_chunk(const PassArgs& A, QEnt* qw, int64_t
   }
 }
 
-// Grid: [heavy chunks][medium rows, 4 per workgroup][light rows, 256 per
-// workgroup].  Q selects the queued gather (slice and sparse passes, or dense
-// passes on request) over the direct one.
-template <int B, bool Q>
-__device__ __forceinline__ void expand_body(const PassArgs& A, QEnt* qw) {
+// Work items of a pass, one per workgroup: [heavy chunks][medium rows, 4
+// per workgroup][light rows, 256 per workgroup].  Q selects the queued
+// gather (slice, edge and sparse passes, or dense passes on request) over
+// the direct one.
+template <int B, bool Q, bool MG>
+__device__ __forceinline__ void expand_item(const PassArgs& A, QEnt* qw, int64_t b) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  if (blockIdx.x == 0)
+  if (b == 0)
     for (int i = threadIdx.x; i < STAT_SLOTS * STAT_K; i += blockDim.x) A.stats_next[i] = 0ull;
-  int64_t b = blockIdx.x;
   if (b < A.n_items) {
-    heavy_chunk<B, Q>(A, qw, b, lane, wave);
+    heavy_chunk<B, Q, MG>(A, qw, b, lane, wave);
     return;
   }
   b -= A.n_items;
   const int64_t med_wgs = (A.n_medium + 3) / 4;
   if (b < med_wgs) {
     const int64_t mi = b * 4 + wave;
-    if (mi < A.n_medium) medium_wave<B, Q>(A, qw, mi, lane);
+    if (mi < A.n_medium) medium_wave<B, Q, MG>(A, qw, mi, lane);
     return;
   }
   b -= med_wgs;
   const int64_t lw = b * 4 + wave;
-  if (lw * 64 < A.n_light) light_wave<B, Q>(A, qw, lw, lane);
+  if (lw * 64 < A.n_light) light_wave<B, Q, MG>(A, qw, lw, lane);
+}
+
+__device__ __forceinline__ int64_t pass_items(const PassArgs& A) {
+  return A.n_items + (A.n_medium + 3) / 4 + (A.n_light + 255) / 256;
+}
+
+__device__ __forceinline__ bool queued_mode(const PassArgs& A) {
+  return !(A.mode == MODE_FIRST || A.mode == MODE_DENSE) || A.qdense;
 }
 
 #if HB_WAVES > 0
@@ -646,19 +686,41 @@ __device__ __forceinline__ void expand_body(const PassArgs& A, QEnt* qw) {
 
 template <int B>
 __global__ HB_EXPAND_ATTR void k_expand(PassArgs A) {
-  expand_body<B, false>(A, nullptr);
+  expand_item<B, false, false>(A, nullptr, blockIdx.x);
 }
 
 template <int B>
 __global__ HB_EXPAND_ATTR void k_expand_q(PassArgs A) {
   __shared__ QEnt qbuf[4][QCAP];
-  expand_body<B, true>(A, qbuf[threadIdx.x >> 6]);
+  expand_item<B, true, false>(A, qbuf[threadIdx.x >> 6], blockIdx.x);
+}
+
+// Persistent form for device-driven passes: a fixed grid whose workgroups
+// take items from the pass's work cursor until none is left.  Both gather
+// forms are launched every pass; the one that does not match the pass mode
+// returns at once.
+template <int B, bool Q>
+__global__ HB_EXPAND_ATTR void k_expand_p(PassArgs A0) {
+  const PassArgs A = resolve(A0);
+  if (queued_mode(A) != Q) return;
+  __shared__ QEnt qbuf[Q ? 4 : 1][Q ? QCAP : 1];
+  __shared__ int64_t item;
+  const int64_t total = pass_items(A);
+  for (;;) {
+    if (threadIdx.x == 0) item = (int64_t)atomicAdd(&A0.ctl->work, 1ull);
+    __syncthreads();
+    const int64_t b = item;
+    __syncthreads();
+    if (b >= total) break;
+    expand_item<B, Q, true>(A, Q ? qbuf[threadIdx.x >> 6] : nullptr, b);
+  }
 }
 
 // Folds the partial counters of every heavy row into the row (one wavefront
 // per heavy row) and finishes it like any other row.
-template <int B>
-__global__ __launch_bounds__(256) void k_merge(PassArgs A) {
+template <int B, bool MG>
+__global__ __launch_bounds__(256) void k_merge(PassArgs A0) {
+  const PassArgs A = resolve(A0);
   constexpr int P = 1 << B;
   constexpr int G = P / 16;
   constexpr int W = 64 / G;
@@ -670,7 +732,7 @@ __global__ __launch_bounds__(256) void k_merge(PassArgs A) {
   if (h >= A.n_hrows) return;
   const HeavyRow hr = A.hrows[h];
   bool own_mod, need;
-  row_flags(A, hr.row, own_mod, need);
+  row_flags<MG>(A, hr.row, own_mod, need);
   if (!need) return;
   RowPre pre;
   if (grp == 0) pre = preload<B>(A, hr.row, gl);
@@ -681,7 +743,7 @@ __global__ __launch_bounds__(256) void k_merge(PassArgs A) {
 #pragma unroll
   for (int o = G; o < 64; o <<= 1) acc = bmax(acc, shfl_xor4(acc, o));
   Counts c{};
-  if (grp == 0) finish_row<B>(A, hr.row, acc, true, pre, own_mod, gl, 0, c);
+  if (grp == 0) finish_row<B, MG>(A, hr.row, acc, true, pre, own_mod, gl, 0, c);
   flush_counts(A, c, h, lane);
 }
 
@@ -886,8 +948,8 @@ __global__ void k_scatter_rev(const int64_t* off, const int32_t* idx, int64_t n,
 // One thread per bitmap word: every set bit w (a counter changed in the
 // previous pass) becomes ceil(rdeg(w)/PUSH_CHUNK) items.  Slots are reserved
 // with one atomic per wavefront.
-__global__ void k_push_items(const uint64_t* mod_prev, int64_t n_words, int64_t n, const int64_t* roff,
-                             uint2* items, unsigned long long* count) {
+__device__ __forceinline__ void push_items_body(const uint64_t* mod_prev, int64_t n_words, int64_t n,
+                                                const int64_t* roff, uint2* items, unsigned long long* count) {
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t word = i < n_words ? mod_prev[i] : 0ull;
@@ -917,8 +979,9 @@ __global__ void k_push_items(const uint64_t* mod_prev, int64_t n_words, int64_t 
 
 // Grid-stride over the items: one wavefront stamps act[v] = epoch for the
 // (at most PUSH_CHUNK) predecessors of one item.
-__global__ void k_push_apply(const uint2* items, const unsigned long long* count, const int64_t* roff,
-                             const int32_t* ridx, int32_t* act, int32_t epoch) {
+__device__ __forceinline__ void push_apply_body(const uint2* items, const unsigned long long* count,
+                                                const int64_t* roff, const int32_t* ridx, int32_t* act,
+                                                int32_t epoch) {
   const int lane = threadIdx.x & 63;
   const int64_t total = (int64_t)*count;
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
@@ -929,6 +992,160 @@ __global__ void k_push_apply(const uint2* items, const unsigned long long* count
     const int64_t e1 = e0 + PUSH_CHUNK < end ? e0 + PUSH_CHUNK : end;
     for (int64_t e = e0 + lane; e < e1; e += 64) act[ridx[e]] = epoch;
   }
+}
+
+__global__ void k_push_items(const uint64_t* mod_prev, int64_t n_words, int64_t n, const int64_t* roff,
+                             uint2* items, unsigned long long* count) {
+  push_items_body(mod_prev, n_words, n, roff, items, count);
+}
+
+__global__ void k_push_apply(const uint2* items, const unsigned long long* count, const int64_t* roff,
+                             const int32_t* ridx, int32_t* act, int32_t epoch) {
+  push_apply_body(items, count, roff, ridx, act, epoch);
+}
+
+// Device-driven forms: no-ops unless the pass is sparse.
+__global__ void k_push_items_d(PassArgs A0, uint2* items, unsigned long long* count) {
+  const PassArgs A = resolve(A0);
+  if (A.mode != MODE_SPARSE) return;
+  push_items_body(A.mod_prev, A.n_blocks, A.n, A.roff, items, count);
+}
+
+__global__ void k_push_apply_d(PassArgs A0, const uint2* items, const unsigned long long* count) {
+  const PassArgs A = resolve(A0);
+  if (A.mode != MODE_SPARSE) return;
+  push_apply_body(items, count, A.roff, A.ridx, const_cast<int32_t*>(A0.act), A.epoch);
+}
+
+// --- end-of-pass bookkeeping of multi-graph contexts ------------------------
+
+// One wavefront per graph: a started, unconverged graph none of whose
+// counters changed in this pass has converged after epoch - t0 passes.
+__global__ void k_graph_done(PassArgs A0) {
+  const PassArgs A = resolve(A0);
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (g >= A0.n_graphs) return;
+  GraphDev* gd = A0.graphs + g;
+  if (!gd->active || gd->done || A.epoch - 1 < gd->t0) return;
+  const int64_t w0 = gd->node_base >> 6;
+  const int64_t w1 = (gd->node_base + gd->n + 63) >> 6;
+  uint64_t any = 0;
+  for (int64_t w = w0 + lane; w < w1; w += 64) any |= A.mod_cur[w];
+  const uint64_t changed = __ballot(any != 0ull);
+  if (lane == 0 && changed == 0ull) {
+    gd->done = 1;
+    gd->passes = A.epoch - gd->t0;
+    atomicAdd(&A0.ctl->n_done, 1);
+  }
+}
+
+// Plans the next pass from this pass's counters (the same rule the host
+// applies to single graphs), then advances the pass index and parity.
+__global__ void k_pass_ctl(PassArgs A0) {
+  const PassArgs A = resolve(A0);
+  PassCtl* c = A0.ctl;
+  const int lane = threadIdx.x;
+  unsigned long long chg = 0, pairs = 0;
+  for (int sl = lane; sl < STAT_SLOTS; sl += 64) {
+    chg += A.stats[sl * STAT_K + 3];
+    pairs += A.stats[sl * STAT_K + 7];
+  }
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    chg += __shfl_xor(chg, o);
+    pairs += __shfl_xor(pairs, o);
+  }
+  for (int i = lane; i < STAT_SLOTS * STAT_K; i += 64) A.stats_next[i] = 0ull;
+  if (lane == 0) {
+    const int64_t N = c->listed_rows > 0 ? c->listed_rows : 1;
+    const int64_t M = c->arcs > 0 ? c->arcs : 1;
+    int32_t mode = MODE_DENSE;
+    if (c->frontier) {
+      const bool dense = c->has_reverse ? 100 * (int64_t)pairs >= (int64_t)c->dense_pct * M
+                                        : 100 * (int64_t)chg >= (int64_t)c->dense_pct * N;
+      if (dense)
+        mode = MODE_DENSE;
+      else if (c->has_reverse && 100 * (int64_t)chg < (int64_t)c->sparse_pct * N)
+        mode = MODE_SPARSE;
+      else
+        mode = MODE_EDGE;
+    }
+    c->mode = mode;
+    c->t += 1;
+    c->parity ^= 1;
+    c->work = 0ull;
+  }
+}
+
+// Clears the change bitmap the next pass writes (the one this pass read).
+__global__ void k_clear_next(PassArgs A0) {
+  uint64_t* m = A0.modb[A0.ctl->parity ^ 1];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < A0.n_blocks; i += stride) m[i] = 0ull;
+}
+
+// Multi-graph initialisation (see k_init_nodes): graph-local ids, per-graph
+// seeds, padding rows empty.
+__global__ void k_init_arena(int log2m, int64_t v0, int64_t v1, const int32_t* blk_graph, const GraphDev* graphs,
+                             uint8_t* cur, uint8_t* nxt, double* S, double* H, double* E, const double* lc,
+                             double alpha_pp) {
+  const int64_t P = (int64_t)1 << log2m;
+  const int64_t C = P / 16;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (v1 - v0) * C) return;
+  const int64_t v = v0 + i / C;
+  const int64_t chunk = i % C;
+  const GraphDev gd = graphs[blk_graph[v >> 6]];
+  const int64_t local = v - gd.node_base;
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
+  uint32_t r = 0;
+  if (local < gd.n) {
+    const uint64_t h = node_hash((uint64_t)local, gd.seed);
+    const uint32_t j = (uint32_t)(h >> (64 - log2m));
+    const uint64_t rest = h << log2m;
+    r = rest == 0ull ? (uint32_t)(65 - log2m) : (uint32_t)__clzll((long long)rest) + 1u;
+    if ((int64_t)(j >> 4) == chunk) w[(j >> 2) & 3u] = r << (8u * (j & 3u));
+  }
+  const uint4 val = make_uint4(w[0], w[1], w[2], w[3]);
+  *reinterpret_cast<uint4*>(cur + v * P + chunk * 16) = val;
+  *reinterpret_cast<uint4*>(nxt + v * P + chunk * 16) = val;
+  if (chunk == 0) {
+    S[v] = 0.0;
+    H[v] = 0.0;
+    if (local < gd.n) {
+      double big = (double)(P - 1), small = 0.0;
+      if (r <= 26u)
+        big += pow2neg(r);
+      else
+        small += pow2neg(r);
+      E[v] = estimate(big, small, (int)(P - 1), alpha_pp, (double)P, lc);
+    } else {
+      E[v] = 0.0;
+    }
+  }
+}
+
+__global__ void k_pack(const double* src, double* dst, int64_t n_arena, const int32_t* blk_graph,
+                       const GraphDev* graphs) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n_arena) return;
+  const GraphDev gd = graphs[blk_graph[v >> 6]];
+  const int64_t local = v - gd.node_base;
+  if (gd.active && local < gd.n) dst[gd.packed + local] = src[v];
+}
+
+__global__ void k_pack_u8(const uint8_t* src, uint8_t* dst, int64_t n_arena, int p, const int32_t* blk_graph,
+                          const GraphDev* graphs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t C = p / 16;
+  if (i >= n_arena * C) return;
+  const int64_t v = i / C, chunk = i % C;
+  const GraphDev gd = graphs[blk_graph[v >> 6]];
+  const int64_t local = v - gd.node_base;
+  if (gd.active && local < gd.n)
+    *reinterpret_cast<uint4*>(dst + (gd.packed + local) * p + chunk * 16) =
+        *reinterpret_cast<const uint4*>(src + v * p + chunk * 16);
 }
 
 int grid_for(int64_t work, int per_block, int cap) {
@@ -988,11 +1205,11 @@ hipError_t launch_pass(int log2m, const PassArgs& a, hipStream_t s, hipEvent_t e
     if (a.n_hrows > 0) {
       const unsigned mg = (unsigned)((a.n_hrows + 3) / 4);
       switch (log2m) {
-        case 4: hipLaunchKernelGGL(k_merge<4>, dim3(mg), dim3(256), 0, s, a); break;
-        case 5: hipLaunchKernelGGL(k_merge<5>, dim3(mg), dim3(256), 0, s, a); break;
-        case 6: hipLaunchKernelGGL(k_merge<6>, dim3(mg), dim3(256), 0, s, a); break;
-        case 7: hipLaunchKernelGGL(k_merge<7>, dim3(mg), dim3(256), 0, s, a); break;
-        default: hipLaunchKernelGGL(k_merge<8>, dim3(mg), dim3(256), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_merge<4, false>), dim3(mg), dim3(256), 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_merge<5, false>), dim3(mg), dim3(256), 0, s, a); break;
+        case 6: hipLaunchKernelGGL((k_merge<6, false>), dim3(mg), dim3(256), 0, s, a); break;
+        case 7: hipLaunchKernelGGL((k_merge<7, false>), dim3(mg), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_merge<8, false>), dim3(mg), dim3(256), 0, s, a); break;
       }
     }
     return hipGetLastError();
@@ -1075,6 +1292,67 @@ hipError_t launch_push(const uint64_t* mod_prev, int64_t n_words, int64_t n, con
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_push_apply, dim3(4096), dim3(256), 0, s, items, count, roff, ridx, act, epoch);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_arena(int log2m, int64_t v0, int64_t v1, const int32_t* blk_graph,
+                             const GraphDev* graphs, uint8_t* cur, uint8_t* nxt, double* S, double* H,
+                             double* E, const double* lc, double alpha_pp, hipStream_t s) {
+  if (v1 <= v0) return hipSuccess;
+  const int64_t threads = (v1 - v0) * (((int64_t)1 << log2m) / 16);
+  hipLaunchKernelGGL(k_init_arena, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, log2m, v0, v1,
+                     blk_graph, graphs, cur, nxt, S, H, E, lc, alpha_pp);
+  return hipGetLastError();
+}
+
+template <int B>
+hipError_t device_pass_b(const PassArgs& a, int persist_wgs, uint2* push_items, unsigned long long* push_count,
+                         hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (a.roff && a.act && a.n_blocks > 0) {
+    e = launch_fill_zero(push_count, sizeof(unsigned long long), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_push_items_d, dim3((unsigned)((a.n_blocks + 255) / 256)), dim3(256), 0, s, a, push_items,
+                       push_count);
+    hipLaunchKernelGGL(k_push_apply_d, dim3(4096), dim3(256), 0, s, a, push_items, push_count);
+  }
+  hipLaunchKernelGGL((k_expand_p<B, false>), dim3(persist_wgs), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_expand_p<B, true>), dim3(persist_wgs), dim3(256), 0, s, a);
+  if (a.n_hrows > 0) hipLaunchKernelGGL((k_merge<B, true>), dim3((unsigned)((a.n_hrows + 3) / 4)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_graph_done, dim3((unsigned)((a.n_graphs + 3) / 4)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_pass_ctl, dim3(1), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(k_clear_next, dim3(grid_for(a.n_blocks, 256, 4096)), dim3(256), 0, s, a);
+  e = hipGetLastError();
+  return e;
+}
+
+hipError_t launch_device_pass(int log2m, const PassArgs& a, int persist_wgs, uint2* push_items,
+                              unsigned long long* push_count, int64_t n_arena, hipStream_t s) {
+  (void)n_arena;
+  switch (log2m) {
+    case 4: return device_pass_b<4>(a, persist_wgs, push_items, push_count, s);
+    case 5: return device_pass_b<5>(a, persist_wgs, push_items, push_count, s);
+    case 6: return device_pass_b<6>(a, persist_wgs, push_items, push_count, s);
+    case 7: return device_pass_b<7>(a, persist_wgs, push_items, push_count, s);
+    case 8: return device_pass_b<8>(a, persist_wgs, push_items, push_count, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_pack(const double* src, double* dst, int64_t n_arena, const int32_t* blk_graph,
+                       const GraphDev* graphs, hipStream_t s) {
+  if (n_arena == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack, dim3((unsigned)((n_arena + 255) / 256)), dim3(256), 0, s, src, dst, n_arena,
+                     blk_graph, graphs);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_u8(const uint8_t* src, uint8_t* dst, int64_t n_arena, int p, const int32_t* blk_graph,
+                          const GraphDev* graphs, hipStream_t s) {
+  if (n_arena == 0) return hipSuccess;
+  const int64_t threads = n_arena * (p / 16);
+  hipLaunchKernelGGL(k_pack_u8, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, src, dst, n_arena, p,
+                     blk_graph, graphs);
   return hipGetLastError();
 }
 

@@ -1,0 +1,116 @@
+"""Batched form: many graphs in one context must give, graph by graph, the
+same registers, pass counts and FP64 results as running each graph alone
+(and hence as the oracle)."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+from hbcheck import assert_fp, run_hb, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(*a):
+    print(*a, flush=True)
+
+
+def mixed_graphs(seed=0, count=24):
+    rng = np.random.default_rng(seed)
+    out = [gg.empty(0), gg.empty(1), gg.from_edges(2, [(0, 1)]), gg.directed_cycle(70), gg.star(130)]
+    while len(out) < count:
+        kind = len(out) % 4
+        n = int(rng.integers(50, 3000))
+        s = int(rng.integers(1 << 30))
+        if kind == 0:
+            out.append(gg.ba(n, 4, seed=s))
+        elif kind == 1:
+            out.append(gg.ws(n, 10, 0.1, seed=s))
+        elif kind == 2:
+            out.append(gg.random_digraph(n, 6 * n, seed=s))
+        else:
+            sc = int(rng.integers(6, 12))
+            out.append(gg.rmat(sc, 8, seed=s, transpose=True))
+    return out
+
+
+def compare_batch(graphs, b, seeds, max_passes=0, **opts):
+    import paper_1308_2144_amd as hb
+
+    with hb.Batch(graphs, b, seeds, **opts) as bt:
+        bt.run(max_passes)
+        regs = bt.split(bt.registers())
+        S, H = (bt.split(x) for x in bt.accumulators())
+        cen = {k: bt.split(v) for k, v in bt.centralities().items()}
+        passes = bt.passes()
+        infos = [bt.graph(i) for i in range(len(graphs))]
+    for i, (off, idx) in enumerate(graphs):
+        solo = run_hb(off, idx, b, int(seeds[i]), max_passes=max_passes, **opts)
+        what = f"graph {i} (n={len(off) - 1})"
+        if max_passes == 0:
+            assert passes[i] == solo["passes"], (what, passes[i], solo["passes"])
+            assert infos[i]["converged"] == 1 and infos[i]["n"] == len(off) - 1
+        assert np.array_equal(regs[i], solo["regs"]), what
+        assert_fp(S[i], solo["S"], what + " S")
+        assert_fp(H[i], solo["H"], what + " H")
+        for k in ("closeness", "lin", "harmonic", "coreach"):
+            assert_fp(cen[k][i], solo[k], what + " " + k)
+
+
+@pytest.mark.parametrize("b", [4, 5, 7, 8])
+def test_batch_equals_solo(b):
+    graphs = mixed_graphs(b)
+    seeds = np.arange(len(graphs), dtype=np.uint64) + 42
+    _log("batch of", len(graphs), "b", b)
+    compare_batch(graphs, b, seeds)
+
+
+@pytest.mark.parametrize("opts", [
+    dict(light_max=2, heavy_min=6, chunk=3),
+    dict(frontier=0),
+    dict(dense_pct=101, sparse_pct=0),     # edge passes
+    dict(dense_pct=101, sparse_pct=101),   # sparse passes
+    dict(push=0, dense_pct=101),
+])
+def test_batch_row_paths_and_modes(opts):
+    graphs = mixed_graphs(11, count=14)
+    seeds = np.arange(len(graphs), dtype=np.uint64) * 7 + 1
+    _log("opts", opts)
+    compare_batch(graphs, 5, seeds, **opts)
+
+
+def test_batch_partial_runs_and_reset():
+    import paper_1308_2144_amd as hb
+
+    graphs = mixed_graphs(3, count=10)
+    seeds = np.arange(10, dtype=np.uint64) + 5
+    for t in (1, 2, 4):
+        compare_batch(graphs, 6, seeds, max_passes=t)
+    # reset with new seeds equals a fresh batch with those seeds
+    seeds2 = seeds + 100
+    with hb.Batch(graphs, 6, seeds) as bt:
+        bt.run()
+        bt.reset(seeds2)
+        bt.run()
+        regs = bt.split(bt.registers())
+        passes = bt.passes()
+    for i, (off, idx) in enumerate(graphs):
+        ref = run_oracle(off, idx, 6, int(seeds2[i]))
+        assert passes[i] == ref["passes"] and np.array_equal(regs[i], ref["regs"]), i
+
+
+def test_batch_against_oracle_directly():
+    graphs = mixed_graphs(7, count=8)
+    seeds = np.arange(8, dtype=np.uint64) * 3 + 9
+    import paper_1308_2144_amd as hb
+
+    with hb.Batch(graphs, 5, seeds) as bt:
+        bt.run()
+        regs = bt.split(bt.registers())
+        cen = {k: bt.split(v) for k, v in bt.centralities().items()}
+        passes = bt.passes()
+    for i, (off, idx) in enumerate(graphs):
+        ref = run_oracle(off, idx, 5, int(seeds[i]))
+        assert passes[i] == ref["passes"]
+        assert np.array_equal(regs[i], ref["regs"])
+        for k in ("closeness", "lin", "harmonic", "coreach"):
+            assert_fp(cen[k][i], ref[k], f"{i} {k}")
