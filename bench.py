@@ -125,6 +125,94 @@ def cpu_baseline(w, seed):
             "seconds": round(dt, 2)}
 
 
+def bench_batch(args, torch, hb, plain_sample: int = 512):
+    """Batched form on the 4096-graph workload: graphs/s of one batched
+    context (reset + passes to convergence for every graph + centralities,
+    inputs resident) against repeated plain per-graph runs on the same GPU,
+    with identical results required."""
+    import graphgen
+
+    t = time.time()
+    graphs = graphgen.batch_workload()
+    k = len(graphs)
+    seeds = np.arange(k, dtype=np.uint64) + 42
+    b = 5
+    log(f"batch: {k} graphs, n={sum(len(o) - 1 for o, _ in graphs)}, m={sum(len(i) for _, i in graphs)}, "
+        f"generated in {time.time() - t:.1f}s")
+    t = time.time()
+    bt = hb.Batch(graphs, b, seeds)
+    log(f"batch: context built in {time.time() - t:.1f}s; stats {bt.stats()}")
+    outs = [torch.empty(max(bt.total, 1), dtype=torch.float64, device="cuda") for _ in range(4)]
+
+    def bstep():
+        bt.reset()
+        passes = bt.run()
+        hb.hb_centralities(bt._ctx, *outs, True)
+        return passes
+
+    bstep()
+    steps = max(args.steps, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        engine_passes = bstep()
+    torch.cuda.synchronize()
+    bdt = (time.perf_counter() - t0) / steps
+    passes = bt.passes()
+    regs = bt.split(bt.registers())
+    harm = bt.split(outs[2].cpu().numpy())
+    bt.close()
+    del outs
+    # Plain runs: one context per graph (created before timing), each reset,
+    # run and finalised in turn; a seeded sample of the graphs, scaled to all.
+    rng = np.random.default_rng(7)
+    sample = np.sort(rng.choice(k, size=min(plain_sample, k), replace=False))
+    ctxs = []
+    for i in sample:
+        o, x = graphs[i]
+        ctxs.append(hb.HyperBall(torch.from_numpy(o).cuda(), torch.from_numpy(x).cuda(), b, int(seeds[i]),
+                                 stream=torch.cuda.current_stream().cuda_stream))
+    pouts = [torch.empty(200_001, dtype=torch.float64, device="cuda") for _ in range(4)]
+    plain_passes = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j, i in enumerate(sample):
+        g = ctxs[j]
+        g.reset(int(seeds[i]))
+        plain_passes.append(g.run())
+        hb.hb_centralities(g._ctx, *pouts, True)
+    torch.cuda.synchronize()
+    pdt = (time.perf_counter() - t0) / len(sample) * k
+    mismatch = {"passes": 0, "registers": 0, "harmonic": 0}
+    for j, i in enumerate(sample):
+        g = ctxs[j]
+        mismatch["passes"] += int(plain_passes[j] != int(passes[i]))
+        mismatch["registers"] += int(not np.array_equal(g.registers(), regs[i]))
+        mismatch["harmonic"] += int(not np.array_equal(g.centralities()["harmonic"], harm[i]))
+        g.close()
+    identical = not any(mismatch.values())
+    # Cold plain runs (init, passes, centralities, free) on a smaller sample.
+    cold = sample[:64]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in cold:
+        o, x = graphs[i]
+        with hb.HyperBall(o, x, b, int(seeds[i])) as g:
+            g.run()
+            g.centralities()
+    torch.cuda.synchronize()
+    cdt = (time.perf_counter() - t0) / len(cold) * k
+    return {"workload": "4096 graphs: 2048 Barabasi-Albert (m=4) + 2048 Watts-Strogatz (k=10, beta=0.1), "
+                        "n log-uniform in [1000, 200000], log2m=5, hash seeds 42+i",
+            "graphs": k, "batched_graphs_per_s": k / bdt, "batched_ms": bdt * 1e3,
+            "engine_passes": int(engine_passes), "max_graph_passes": int(passes.max()),
+            "plain_graphs_per_s": k / pdt, "plain_ms_estimated": pdt * 1e3,
+            "plain_sample": int(len(sample)),
+            "plain_cold_graphs_per_s": k / cdt, "plain_cold_sample": int(len(cold)),
+            "speedup_vs_plain": pdt / bdt, "identical_on_sample": bool(identical),
+            "mismatches_on_sample": mismatch}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +229,7 @@ def main():
     ap.add_argument("--sparse-pct", type=int, default=-1)
     ap.add_argument("--qdense", type=int, default=0)
     ap.add_argument("--slice", type=int, default=0)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (torch) 3 times, to scale HBM counters")
     args = ap.parse_args()
@@ -246,6 +335,10 @@ def main():
     g.close()
     del o_d, i_d, outs
     torch.cuda.empty_cache()
+    if not args.no_batch:
+        log("batched form ...")
+        out["batched"] = bench_batch(args, torch, hb)
+        torch.cuda.empty_cache()
     if args.copy_calib:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)

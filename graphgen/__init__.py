@@ -63,6 +63,11 @@ def _load():
         lib.gg_ba_edges.restype = i64
         lib.gg_ws_edges.argtypes = [i64, ctypes.c_int, ctypes.c_double, u64, i32p, i32p]
         lib.gg_ws_edges.restype = i64
+        lib.gg_batch_arcs.argtypes = [ctypes.c_int32, i64, ctypes.c_int]
+        lib.gg_batch_arcs.restype = i64
+        lib.gg_batch_build.argtypes = [ctypes.c_int32, i32p, i64p, i64p, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_double, i64p, i64p, i64p, i32p]
+        lib.gg_batch_build.restype = ctypes.c_int32
         lib.gg_num_threads.argtypes = []
         lib.gg_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -214,3 +219,37 @@ def transpose(offsets: np.ndarray, indices: np.ndarray):
     n = offsets.shape[0] - 1
     rows = np.repeat(np.arange(n, dtype=np.int32), np.diff(offsets))
     return csr_from_pairs(n, indices, rows, drop_self=False, dedup=False)
+
+
+def batch(kinds, ns, seeds, ba_m: int = 4, ws_k: int = 10, ws_beta: float = 0.1):
+    """Many undirected graphs at once (C, parallel over graphs): kinds[i] 0 =
+    Barabasi-Albert (ba_m edges per node), 1 = Watts-Strogatz (ws_k, ws_beta).
+    Returns a list of (offsets, indices) views into two shared arrays."""
+    lib = _load()
+    kinds = np.ascontiguousarray(kinds, dtype=np.int32)
+    ns = np.ascontiguousarray(ns, dtype=np.int64)
+    seeds = np.ascontiguousarray(seeds, dtype=np.uint64)
+    k = kinds.shape[0]
+    arcs = np.array([lib.gg_batch_arcs(int(kinds[i]), int(ns[i]), ba_m if kinds[i] == 0 else ws_k)
+                     for i in range(k)], dtype=np.int64)
+    off_start = np.concatenate([[0], np.cumsum(ns + 1)[:-1]]).astype(np.int64)
+    idx_start = np.concatenate([[0], np.cumsum(arcs)[:-1]]).astype(np.int64)
+    offsets_all = np.empty(int((ns + 1).sum()), dtype=np.int64)
+    indices_all = np.empty(max(int(arcs.sum()), 1), dtype=np.int32)
+    bad = lib.gg_batch_build(k, _ptr(kinds), _ptr(ns), _ptr(seeds), ba_m, ws_k, ws_beta, _ptr(off_start),
+                             _ptr(idx_start), _ptr(offsets_all), _ptr(indices_all))
+    if bad:
+        raise RuntimeError(f"graph {bad - 1}: unexpected edge count")
+    return [(offsets_all[off_start[i]:off_start[i] + ns[i] + 1],
+             indices_all[idx_start[i]:idx_start[i] + arcs[i]]) for i in range(k)]
+
+
+def batch_workload(count: int = 4096, n_min: int = 1000, n_max: int = 200_000, seed: int = 4):
+    """The batched workload: `count` graphs, first half Barabasi-Albert (m = 4),
+    second half Watts-Strogatz (k = 10, beta = 0.1), sizes log-uniform in
+    [n_min, n_max] drawn with numpy's PCG64 from `seed`."""
+    rng = np.random.default_rng(seed)
+    ns = np.exp(rng.uniform(np.log(n_min), np.log(n_max), size=count)).astype(np.int64)
+    kinds = (np.arange(count) >= count // 2).astype(np.int32)
+    gseeds = rng.integers(1, 2**62, size=count, dtype=np.int64).astype(np.uint64)
+    return batch(kinds, ns, gseeds)

@@ -278,6 +278,58 @@ int64_t gg_ws_edges(int64_t n, int k, double beta, uint64_t seed, int32_t* src, 
   return e;
 }
 
+// Arc count of a symmetric batch graph: kind 0 = Barabasi-Albert with
+// `param` edges per node, kind 1 = Watts-Strogatz with `param` neighbours.
+// Both generators produce no duplicate edges and no self-loops.
+int64_t gg_batch_arcs(int32_t kind, int64_t n, int param) {
+  if (n <= 0) return 0;
+  if (kind == 0) {
+    const int64_t m = param < n ? param : n;
+    return 2 * (m * (m - 1) / 2 + m * (n - m));
+  }
+  return n * (int64_t)(param / 2) * 2;
+}
+
+// Many symmetric graphs at once (OpenMP over graphs).  Graph i is written as
+// a CSR at offsets_all + off_start[i] (n_i + 1 entries) and indices_all +
+// idx_start[i] (gg_batch_arcs entries), rows sorted.  Returns 0, or the
+// 1-based index of a graph whose arc count did not match.
+int32_t gg_batch_build(int32_t k, const int32_t* kinds, const int64_t* ns, const uint64_t* seeds, int ba_m,
+                       int ws_k, double ws_beta, const int64_t* off_start, const int64_t* idx_start,
+                       int64_t* offsets_all, int32_t* indices_all) {
+  int32_t bad = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t i = 0; i < k; ++i) {
+    const int64_t n = ns[i];
+    const int param = kinds[i] == 0 ? ba_m : ws_k;
+    const int64_t edges = gg_batch_arcs(kinds[i], n, param) / 2;
+    std::vector<int32_t> src((size_t)(edges > 0 ? edges : 1)), dst((size_t)(edges > 0 ? edges : 1));
+    const int64_t got = kinds[i] == 0 ? gg_ba_edges(n, ba_m, seeds[i], src.data(), dst.data())
+                                      : gg_ws_edges(n, ws_k, ws_beta, seeds[i], src.data(), dst.data());
+    int64_t* off = offsets_all + off_start[i];
+    int32_t* idx = indices_all + idx_start[i];
+    if (got != edges) {
+#pragma omp critical
+      bad = i + 1;
+      continue;
+    }
+    std::vector<int64_t> cnt((size_t)n + 1, 0);
+    for (int64_t e = 0; e < edges; ++e) {
+      ++cnt[(size_t)src[e]];
+      ++cnt[(size_t)dst[e]];
+    }
+    off[0] = 0;
+    for (int64_t v = 0; v < n; ++v) off[v + 1] = off[v] + cnt[(size_t)v];
+    for (int64_t v = 0; v < n; ++v) cnt[(size_t)v] = off[v];
+    for (int64_t e = 0; e < edges; ++e) {
+      idx[cnt[(size_t)src[e]]++] = dst[e];
+      idx[cnt[(size_t)dst[e]]++] = src[e];
+    }
+    for (int64_t v = 0; v < n; ++v) std::sort(idx + off[v], idx + off[v + 1]);
+  }
+  return bad;
+}
+
 int gg_num_threads(void) { return omp_get_max_threads(); }
 
 }  // extern "C"

@@ -709,7 +709,9 @@ hb_status hb_centralities(hb_ctx* c, double* closeness, double* lin, double* har
   hb_status st = check_ctx(c);
   if (st != HB_OK) return st;
   if (c->n == 0) return HB_OK;
-  if (dst_on_device) {
+  // Single graphs finalise straight into device destinations; batched
+  // contexts always go through the arena-layout staging below and are packed.
+  if (dst_on_device && c->n_graphs == 0) {
     HB_HIP(hb::launch_finalize(c->n, c->S, c->H, c->E, closeness, lin, harmonic, coreach, c->stream));
     HB_HIP(hipStreamSynchronize(c->stream));
     return HB_OK;

@@ -114,3 +114,36 @@ def test_batch_against_oracle_directly():
         assert np.array_equal(regs[i], ref["regs"])
         for k in ("closeness", "lin", "harmonic", "coreach"):
             assert_fp(cen[k][i], ref[k], f"{i} {k}")
+
+
+def test_batch_device_outputs_are_packed_and_bounded():
+    # Device destinations get the packed layout (sum of n_i entries) and
+    # nothing past it: a guard region after the packed size stays untouched.
+    import torch
+
+    import paper_1308_2144_amd as hb
+
+    graphs = mixed_graphs(5, count=12)
+    seeds = np.arange(12, dtype=np.uint64) + 77
+    with hb.Batch(graphs, 6, seeds) as bt:
+        bt.run()
+        total = bt.total
+        guard = 4096
+        outs = [torch.full((total + guard,), -7.0, dtype=torch.float64, device="cuda") for _ in range(4)]
+        hb.hb_centralities(bt._ctx, *outs, True)
+        host = bt.centralities()
+        for o, key in zip(outs, ("closeness", "lin", "harmonic", "coreach")):
+            o = o.cpu().numpy()
+            assert np.array_equal(o[:total], host[key]), key
+            assert np.all(o[total:] == -7.0), key
+        S = torch.full((total + guard,), -7.0, dtype=torch.float64, device="cuda")
+        H = torch.full((total + guard,), -7.0, dtype=torch.float64, device="cuda")
+        hb.hb_get_accumulators(bt._ctx, S, H, True)
+        hS, hH = bt.accumulators()
+        assert np.array_equal(S.cpu().numpy()[:total], hS) and np.all(S.cpu().numpy()[total:] == -7.0)
+        assert np.array_equal(H.cpu().numpy()[:total], hH) and np.all(H.cpu().numpy()[total:] == -7.0)
+        R = torch.full(((total + guard) * bt.p,), 251, dtype=torch.uint8, device="cuda")
+        hb.hb_get_registers(bt._ctx, R, True)
+        R = R.cpu().numpy()
+        assert np.array_equal(R[: total * bt.p].reshape(total, bt.p), bt.registers())
+        assert np.all(R[total * bt.p:] == 251)
