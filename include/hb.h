@@ -230,6 +230,100 @@ hb_status hb_batch_graph(hb_ctx* c, int32_t g, hb_graph_info* info);
 /* Per-graph pass counts (k entries; -1 for a graph not converged yet). */
 hb_status hb_batch_passes(hb_ctx* c, int32_t* passes);
 
+/* ---- Serving form: a request loop over resident engines ----------------
+ * A server owns one multi-graph engine per log2m in [4, 8] (made on first
+ * use) and a thread that runs them.  A request is one centrality query: a
+ * host CSR, log2m and a hash seed; its result is exactly what hb_init +
+ * hb_run + hb_centralities give for the same graph alone (same registers,
+ * pass count and floating-point values, bit for bit), whatever else is
+ * resident.  Requests are admitted in submission order while the counter
+ * memory of the resident requests, sum of 2*n*2^log2m bytes, stays within
+ * budget_bytes and the engine's node/arc pools and slots have room.  An
+ * admitted request joins its engine at the next pass: its nodes start from
+ * their singleton counters and count as changed, so that pass gathers all
+ * their successors whatever the engine's pass mode, and its distances are
+ * counted from that pass.  Every engine pass runs all resident requests of
+ * its log2m at once (continuous batching); engines run on streams of their
+ * own.  A request found converged is finalized, its outputs copied into the
+ * caller's buffers, and its slot and memory are freed.
+ *
+ * Borrowing: the request's CSR arrays and output buffers must stay valid and
+ * untouched from hb_serve_submit until the request reaches a final state.
+ * Pinned host memory (hipHostMalloc) makes uploads and result copies
+ * asynchronous; pageable memory works but stalls the serving thread on the
+ * copy.  hb_serve_* calls may come from any thread. */
+typedef struct hb_server hb_server;
+
+typedef struct {
+  int64_t budget_bytes;     /* admission cap on sum of 2*n*p (<= 0: 64 GiB) */
+  int64_t max_nodes;        /* node pool per engine, padding included (<= 0: 2^25) */
+  int64_t max_arcs;         /* arc pool per engine (<= 0: 2^29) */
+  int32_t max_resident;     /* requests resident per engine (<= 0: 1024) */
+  int32_t passes_per_tick;  /* engine passes enqueued per tick (<= 0: 1) */
+  int32_t start_paused;     /* admit nothing until hb_serve_resume */
+  hb_options opt;           /* row classes, frontier and mode thresholds, validate */
+} hb_serve_config;
+
+void hb_serve_default_config(hb_serve_config* cfg);
+
+typedef struct {
+  hb_csr graph;        /* host CSR (on_device must be 0); borrowed */
+  int32_t log2m;       /* 4..8 */
+  uint64_t seed;
+  /* Host outputs, n entries each (registers: n*2^log2m bytes); any may be
+   * NULL.  Written before the request becomes HB_REQ_DONE. */
+  double* closeness;
+  double* lin;
+  double* harmonic;
+  double* coreach;
+  double* S;           /* sum_t t*(|B_t|-|B_{t-1}|) */
+  double* H;           /* sum_t (|B_t|-|B_{t-1}|)/t */
+  uint8_t* registers;
+} hb_serve_request;
+
+enum { HB_REQ_QUEUED = 0, HB_REQ_RUNNING = 1, HB_REQ_DONE = 2, HB_REQ_CANCELLED = 3, HB_REQ_FAILED = 4 };
+
+typedef struct {
+  int64_t id;
+  int32_t state;       /* HB_REQ_* */
+  int32_t passes;      /* pass count of the graph (DONE) */
+  double t_submit;     /* seconds since hb_serve_start (steady clock) */
+  double t_admit;      /* joined its engine (-1 while queued) */
+  double t_done;       /* outputs written (-1 before) */
+} hb_request_info;
+
+typedef struct {
+  int64_t submitted, admitted, completed, cancelled, failed;
+  int64_t queued, resident;
+  int64_t resident_bytes, peak_resident_bytes;  /* sum of 2*n*p */
+  int64_t ticks, engine_passes;
+  double busy_s;       /* wall time with at least one engine pass in flight */
+  double elapsed_s;    /* since hb_serve_start */
+} hb_serve_stats_t;
+
+/* Starts the serving thread on the current device (cfg NULL: defaults). */
+hb_status hb_serve_start(hb_server** out, const hb_serve_config* cfg);
+/* Lets a server started with start_paused admit requests. */
+hb_status hb_serve_resume(hb_server* s);
+/* Enqueues a request and returns its id (> 0).  HB_EINVAL for a malformed
+ * request (validated on the calling thread when opt.validate is set),
+ * HB_ENOMEM for one that could never be admitted (over the budget or an
+ * engine pool on its own), HB_ESTATE once the server failed or is stopping. */
+hb_status hb_serve_submit(hb_server* s, const hb_serve_request* rq, int64_t* id);
+/* Current state of a request, without waiting.  A final state (DONE,
+ * CANCELLED, FAILED) is reported once; the id is forgotten afterwards. */
+hb_status hb_serve_poll(hb_server* s, int64_t id, hb_request_info* info);
+/* Waits up to timeout_s seconds (< 0: no limit) for a final state; returns
+ * HB_ESTATE with info->state still QUEUED/RUNNING on a time-out and
+ * HB_EDEVICE if the request failed. */
+hb_status hb_serve_wait(hb_server* s, int64_t id, double timeout_s, hb_request_info* info);
+/* Cancels a request that is still queued (HB_ESTATE once it was admitted). */
+hb_status hb_serve_cancel(hb_server* s, int64_t id);
+hb_status hb_serve_stats(hb_server* s, hb_serve_stats_t* st);
+/* Finishes every submitted request (resuming a paused server), stops the
+ * thread and frees everything; HB_EDEVICE if the server had failed. */
+hb_status hb_serve_stop(hb_server* s);
+
 /* Releases everything the context owns (never borrowed memory).  NULL-safe. */
 void hb_free(hb_ctx* c);
 

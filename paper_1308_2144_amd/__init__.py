@@ -74,6 +74,35 @@ class hb_graph_info(ctypes.Structure):
                 ("converged", ctypes.c_int32)]
 
 
+class hb_serve_config(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("max_nodes", ctypes.c_int64), ("max_arcs", ctypes.c_int64),
+                ("max_resident", ctypes.c_int32), ("passes_per_tick", ctypes.c_int32),
+                ("start_paused", ctypes.c_int32), ("opt", hb_options)]
+
+
+class hb_serve_request(ctypes.Structure):
+    _fields_ = [("graph", hb_csr), ("log2m", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("closeness", ctypes.c_void_p), ("lin", ctypes.c_void_p), ("harmonic", ctypes.c_void_p),
+                ("coreach", ctypes.c_void_p), ("S", ctypes.c_void_p), ("H", ctypes.c_void_p),
+                ("registers", ctypes.c_void_p)]
+
+
+class hb_request_info(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("state", ctypes.c_int32), ("passes", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class hb_serve_stats_t(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "admitted", "completed", "cancelled", "failed",
+                                             "queued", "resident", "resident_bytes", "peak_resident_bytes",
+                                             "ticks", "engine_passes")] + \
+               [("busy_s", ctypes.c_double), ("elapsed_s", ctypes.c_double)]
+
+
+HB_REQ_QUEUED, HB_REQ_RUNNING, HB_REQ_DONE, HB_REQ_CANCELLED, HB_REQ_FAILED = range(5)
+REQ_STATES = ("queued", "running", "done", "cancelled", "failed")
+
+
 def _declare(L):
     vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
     P = ctypes.POINTER
@@ -95,6 +124,15 @@ def _declare(L):
         "hb_batch_reset": (ctypes.c_int, [vp, vp]),
         "hb_batch_graph": (ctypes.c_int, [vp, i32, P(hb_graph_info)]),
         "hb_batch_passes": (ctypes.c_int, [vp, vp]),
+        "hb_serve_default_config": (None, [P(hb_serve_config)]),
+        "hb_serve_start": (ctypes.c_int, [P(vp), P(hb_serve_config)]),
+        "hb_serve_resume": (ctypes.c_int, [vp]),
+        "hb_serve_submit": (ctypes.c_int, [vp, P(hb_serve_request), P(i64)]),
+        "hb_serve_poll": (ctypes.c_int, [vp, i64, P(hb_request_info)]),
+        "hb_serve_wait": (ctypes.c_int, [vp, i64, ctypes.c_double, P(hb_request_info)]),
+        "hb_serve_cancel": (ctypes.c_int, [vp, i64]),
+        "hb_serve_stats": (ctypes.c_int, [vp, P(hb_serve_stats_t)]),
+        "hb_serve_stop": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -277,6 +315,60 @@ def hb_batch_passes(ctx, k: int) -> np.ndarray:
     return out
 
 
+def hb_serve_default_config() -> hb_serve_config:
+    cfg = hb_serve_config()
+    lib().hb_serve_default_config(ctypes.byref(cfg))
+    return cfg
+
+
+def hb_serve_start(cfg: hb_serve_config | None = None):
+    srv = ctypes.c_void_p()
+    _check(lib().hb_serve_start(ctypes.byref(srv), ctypes.byref(cfg) if cfg is not None else None))
+    return srv
+
+
+def hb_serve_resume(srv):
+    _check(lib().hb_serve_resume(srv))
+
+
+def hb_serve_submit(srv, rq: hb_serve_request) -> int:
+    rid = ctypes.c_int64()
+    _check(lib().hb_serve_submit(srv, ctypes.byref(rq), ctypes.byref(rid)))
+    return rid.value
+
+
+def _info(info: hb_request_info) -> dict:
+    d = {k: getattr(info, k) for k, _ in hb_request_info._fields_}
+    d["state_name"] = REQ_STATES[d["state"]] if 0 <= d["state"] < len(REQ_STATES) else str(d["state"])
+    return d
+
+
+def hb_serve_poll(srv, rid: int) -> dict:
+    info = hb_request_info()
+    _check(lib().hb_serve_poll(srv, int(rid), ctypes.byref(info)))
+    return _info(info)
+
+
+def hb_serve_wait(srv, rid: int, timeout_s: float = -1.0) -> dict:
+    info = hb_request_info()
+    _check(lib().hb_serve_wait(srv, int(rid), float(timeout_s), ctypes.byref(info)))
+    return _info(info)
+
+
+def hb_serve_cancel(srv, rid: int):
+    _check(lib().hb_serve_cancel(srv, int(rid)))
+
+
+def hb_serve_stats(srv) -> dict:
+    st = hb_serve_stats_t()
+    _check(lib().hb_serve_stats(srv, ctypes.byref(st)))
+    return {k: getattr(st, k) for k, _ in hb_serve_stats_t._fields_}
+
+
+def hb_serve_stop(srv):
+    _check(lib().hb_serve_stop(srv))
+
+
 # --- convenience wrappers -------------------------------------------------------
 
 class HyperBall:
@@ -413,3 +505,113 @@ class Batch:
 
     def stats(self) -> dict:
         return hb_stats(self._ctx)
+
+
+class Request:
+    """A submitted serving request: its id and the host arrays the server
+    borrows until the request reaches a final state (``outputs`` holds the
+    results once ``Server.wait`` returned "done")."""
+
+    def __init__(self, rid: int, n: int, log2m: int, outputs: dict, keep):
+        self.id = rid
+        self.n = n
+        self.log2m = log2m
+        self.outputs = outputs
+        self._keep = keep
+        self.info = None
+
+
+class Server:
+    """The serving loop (see hb_serve_start in include/hb.h)."""
+
+    OUTPUTS = ("closeness", "lin", "harmonic", "coreach", "S", "H")
+
+    def __init__(self, budget_bytes: int = 0, max_nodes: int = 0, max_arcs: int = 0, max_resident: int = 0,
+                 passes_per_tick: int = 0, start_paused: bool = False, **options):
+        cfg = hb_serve_default_config()
+        for k, v in (("budget_bytes", budget_bytes), ("max_nodes", max_nodes), ("max_arcs", max_arcs),
+                     ("max_resident", max_resident), ("passes_per_tick", passes_per_tick),
+                     ("start_paused", int(start_paused))):
+            if v:
+                setattr(cfg, k, int(v))
+        cfg.opt = default_options(**options)
+        self._srv = hb_serve_start(cfg)
+        self._live = {}
+
+    def submit(self, offsets, indices, log2m: int, seed: int, *, outputs=OUTPUTS, registers: bool = False,
+               out: dict | None = None) -> Request:
+        """Host CSR in, Request out.  `out` may supply preallocated host
+        arrays (e.g. pinned) by output name; missing ones are allocated."""
+        o = np.ascontiguousarray(offsets)
+        if o.dtype not in (np.int32, np.int64):
+            o = o.astype(np.int64)
+        x = np.ascontiguousarray(indices, dtype=np.int32)
+        n = o.shape[0] - 1
+        p = 1 << int(log2m)
+        bufs = dict(out or {})
+        for k in outputs:
+            if k not in bufs:
+                bufs[k] = np.empty(max(n, 1))
+        if registers and "registers" not in bufs:
+            bufs["registers"] = np.empty((max(n, 1), p), dtype=np.uint8)
+        rq = hb_serve_request()
+        rq.graph = hb_csr(n, x.shape[0], o.ctypes.data, 64 if o.dtype == np.int64 else 32,
+                          x.ctypes.data if x.size else None, 0)
+        rq.log2m = int(log2m)
+        rq.seed = int(seed)
+        for k, a in bufs.items():
+            setattr(rq, k, _ptr(a))
+        rid = hb_serve_submit(self._srv, rq)
+        req = Request(rid, n, int(log2m), bufs, (o, x, rq))
+        self._live[rid] = req
+        return req
+
+    def _final(self, req: Request, info: dict) -> dict:
+        req.info = info
+        if info["state"] >= HB_REQ_DONE:
+            self._live.pop(req.id, None)
+            if info["state"] == HB_REQ_DONE:
+                for k, a in list(req.outputs.items()):
+                    req.outputs[k] = a[: req.n]
+        return info
+
+    def wait(self, req: Request, timeout_s: float = -1.0) -> dict:
+        try:
+            info = hb_serve_wait(self._srv, req.id, timeout_s)
+        except HBError as e:
+            if e.status == HB_EDEVICE:
+                self._live.pop(req.id, None)
+            raise
+        return self._final(req, info)
+
+    def poll(self, req: Request) -> dict:
+        return self._final(req, hb_serve_poll(self._srv, req.id))
+
+    def cancel(self, req: Request):
+        hb_serve_cancel(self._srv, req.id)
+
+    def resume(self):
+        hb_serve_resume(self._srv)
+
+    def stats(self) -> dict:
+        return hb_serve_stats(self._srv)
+
+    def stop(self):
+        if self._srv is not None:
+            srv, self._srv = self._srv, None
+            try:
+                hb_serve_stop(srv)
+            finally:
+                self._live.clear()
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.stop()

@@ -7,23 +7,15 @@
 #include <string>
 #include <vector>
 
-#include "../../include/hb.h"
-#include "hb_internal.h"
+#include "hb_ctx.h"
+
+namespace hbh {
+thread_local std::string g_err;
+}  // namespace hbh
+
+using namespace hbh;
 
 namespace {
-
-thread_local std::string g_err;
-
-hb_status fail(hb_status st, const std::string& msg) {
-  g_err = msg;
-  return st;
-}
-
-#define HB_HIP(call)                                                                  \
-  do {                                                                                \
-    hipError_t e_ = (call);                                                           \
-    if (e_ != hipSuccess) return fail(HB_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
-  } while (0)
 
 constexpr int DEFAULT_LIGHT_MAX = 64;
 constexpr int DEFAULT_HEAVY_MIN = 8192;
@@ -31,87 +23,10 @@ constexpr int DEFAULT_CHUNK = 4096;
 constexpr int DEFAULT_DENSE_PCT = 60;
 constexpr int DEFAULT_SPARSE_PCT = 20;
 
-// alpha_p of Flajolet-Fusy-Gandouet-Meunier 2007 (Algorithm 1 defers to it).
-double alpha_for(int p) {
-  if (p == 16) return 0.673;
-  if (p == 32) return 0.697;
-  if (p == 64) return 0.709;
-  return 0.7213 / (1.0 + 1.079 / (double)p);
-}
-
-template <class T>
-hipError_t dmalloc(T** p, size_t count) {
-  *p = nullptr;
-  if (count == 0) count = 1;
-  return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
-}
-
 }  // namespace
 
-struct hb_ctx {
-  int64_t n = 0, m = 0;
-  int b = 0, p = 0;
-  uint64_t seed = 0;
-  hb_options opt{};
-  hipStream_t stream = nullptr;
-  int64_t* off = nullptr;
-  bool own_off = false;
-  const int32_t* idx = nullptr;
-  int32_t* idx_owned = nullptr;
-  uint8_t* cnt[2] = {nullptr, nullptr};
-  uint64_t* mod[2] = {nullptr, nullptr};
-  uint16_t* dmask[2] = {nullptr, nullptr};
-  int64_t n_blocks = 0;
-  double* S = nullptr;
-  double* H = nullptr;
-  double* E = nullptr;
-  double* lc = nullptr;
-  double alpha_pp = 0.0;
-  hb::HeavyItem* items = nullptr;
-  int64_t n_items = 0;
-  hb::HeavyRow* hrows = nullptr;
-  int64_t n_hrows = 0;
-  int64_t n_medium = 0;
-  int32_t* light = nullptr;
-  int32_t* medium = nullptr;
-  int64_t n_light = 0;
-  int64_t n_nonempty = 0;
-  int64_t* roff = nullptr;      // reverse CSR (push activation)
-  int32_t* ridx = nullptr;
-  int32_t* act = nullptr;
-  uint2* push_items = nullptr;
-  unsigned long long* push_count = nullptr;
-  uint8_t* partial = nullptr;
-  unsigned long long* stats = nullptr;       // 2 halves of STAT_SLOTS * STAT_K
-  unsigned long long* stats_host = nullptr;  // pinned
-  double* out_tmp = nullptr;                 // 4n doubles for host-destination finalize
-  int* bad = nullptr;
-  int cur = 0;
-  int32_t t = 0;
-  bool converged = false;
-  int64_t last_nmod = -1;
-  int64_t last_slices = -1;
-  int64_t last_pairs = -1;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  // Multi-graph (batched) contexts.
-  int32_t n_graphs = 0;
-  std::vector<hb::GraphDev> graphs_host;
-  hb::GraphDev* graphs = nullptr;
-  int32_t* blk_graph = nullptr;
-  hb::PassCtl* ctl = nullptr;
-  hb::PassCtl* ctl_host = nullptr;  // pinned
-  int64_t n_packed = 0;
-  int persist_wgs = 0;
-  int graph_passes = 0;              // passes per hipGraph replay
-  hipGraphExec_t gexec = nullptr;
-  bool own_stream = false;
-  double* arena_tmp = nullptr;       // n doubles, arena layout staging for packed outputs
-  std::vector<hb_pass_info> hist;
-  double total_ms = 0.0;
-  bool failed = false;
-};
 
-namespace {
+namespace hbh {
 
 void release(hb_ctx* c) {
   if (!c) return;
@@ -152,11 +67,19 @@ void release(hb_ctx* c) {
   delete c;
 }
 
+}  // namespace hbh
+
+namespace {
+
 hb_status check_ctx(hb_ctx* c) {
   if (!c) return fail(HB_EINVAL, "NULL context");
   if (c->failed) return fail(HB_ESTATE, "context is in a failed state");
   return HB_OK;
 }
+
+}  // namespace
+
+namespace hbh {
 
 // Classify the non-empty rows by degree (empty rows never change and are
 // left out of every pass) and cut heavy rows into chunks.
@@ -189,6 +112,10 @@ void plan_rows(hb_ctx* c, const int64_t* off_host, std::vector<int32_t>& light,
     hrows.push_back(hr);
   }
 }
+
+}  // namespace hbh
+
+namespace {
 
 hb_status do_reset(hb_ctx* c, uint64_t seed) {
   c->seed = seed;
@@ -389,6 +316,10 @@ hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, co
   return HB_OK;
 }
 
+}  // namespace
+
+namespace hbh {
+
 // Arguments of a device-driven pass (buffers, mode and pass index are
 // resolved on the device from ctl).
 hb::PassArgs device_args(hb_ctx* c) {
@@ -434,6 +365,10 @@ hb_status read_ctl(hb_ctx* c) {
   c->converged = c->ctl_host->n_done >= c->n_graphs;
   return HB_OK;
 }
+
+}  // namespace hbh
+
+namespace {
 
 // Passes of a multi-graph context until every graph converged (or
 // max_passes engine passes ran): replays of a hipGraph holding graph_passes

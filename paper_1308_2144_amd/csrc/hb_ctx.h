@@ -1,0 +1,115 @@
+// Host-side context shared by the C-ABI entry points (hb_api.cpp) and the
+// serving loop (hb_serve.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/hb.h"
+#include "hb_internal.h"
+
+namespace hbh {
+
+// Message of the last failure on this thread (hb_last_error).
+extern thread_local std::string g_err;
+
+inline hb_status fail(hb_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HB_HIP(call)                                                                                   \
+  do {                                                                                                 \
+    hipError_t e_ = (call);                                                                            \
+    if (e_ != hipSuccess) return hbh::fail(HB_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+hipError_t dmalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+}
+
+// alpha_p of Flajolet-Fusy-Gandouet-Meunier 2007 (Algorithm 1 defers to it).
+inline double alpha_for(int p) {
+  if (p == 16) return 0.673;
+  if (p == 32) return 0.697;
+  if (p == 64) return 0.709;
+  return 0.7213 / (1.0 + 1.079 / (double)p);
+}
+
+}  // namespace hbh
+
+struct hb_ctx {
+  int64_t n = 0, m = 0;
+  int b = 0, p = 0;
+  uint64_t seed = 0;
+  hb_options opt{};
+  hipStream_t stream = nullptr;
+  int64_t* off = nullptr;
+  bool own_off = false;
+  const int32_t* idx = nullptr;
+  int32_t* idx_owned = nullptr;
+  uint8_t* cnt[2] = {nullptr, nullptr};
+  uint64_t* mod[2] = {nullptr, nullptr};
+  uint16_t* dmask[2] = {nullptr, nullptr};
+  int64_t n_blocks = 0;
+  double* S = nullptr;
+  double* H = nullptr;
+  double* E = nullptr;
+  double* lc = nullptr;
+  double alpha_pp = 0.0;
+  hb::HeavyItem* items = nullptr;
+  int64_t n_items = 0;
+  hb::HeavyRow* hrows = nullptr;
+  int64_t n_hrows = 0;
+  int64_t n_medium = 0;
+  int32_t* light = nullptr;
+  int32_t* medium = nullptr;
+  int64_t n_light = 0;
+  int64_t n_nonempty = 0;
+  int64_t* roff = nullptr;      // reverse CSR (push activation)
+  int32_t* ridx = nullptr;
+  int32_t* act = nullptr;
+  uint2* push_items = nullptr;
+  unsigned long long* push_count = nullptr;
+  uint8_t* partial = nullptr;
+  unsigned long long* stats = nullptr;       // 2 halves of STAT_SLOTS * STAT_K
+  unsigned long long* stats_host = nullptr;  // pinned
+  double* out_tmp = nullptr;                 // 4n doubles for host-destination finalize
+  int* bad = nullptr;
+  int cur = 0;
+  int32_t t = 0;
+  bool converged = false;
+  int64_t last_nmod = -1;
+  int64_t last_slices = -1;
+  int64_t last_pairs = -1;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // Multi-graph (batched) contexts.
+  int32_t n_graphs = 0;
+  std::vector<hb::GraphDev> graphs_host;
+  hb::GraphDev* graphs = nullptr;
+  int32_t* blk_graph = nullptr;
+  hb::PassCtl* ctl = nullptr;
+  hb::PassCtl* ctl_host = nullptr;  // pinned
+  int64_t n_packed = 0;
+  int persist_wgs = 0;
+  int graph_passes = 0;              // passes per hipGraph replay
+  hipGraphExec_t gexec = nullptr;
+  bool own_stream = false;
+  double* arena_tmp = nullptr;       // n doubles, arena layout staging for packed outputs
+  std::vector<hb_pass_info> hist;
+  double total_ms = 0.0;
+  bool failed = false;
+};
+
+namespace hbh {
+
+void release(hb_ctx* c);
+void plan_rows(hb_ctx* c, const int64_t* off_host, std::vector<int32_t>& light, std::vector<int32_t>& medium,
+               std::vector<hb::HeavyItem>& items, std::vector<hb::HeavyRow>& hrows);
+hb::PassArgs device_args(hb_ctx* c);
+hb_status read_ctl(hb_ctx* c);
+
+}  // namespace hbh

@@ -145,6 +145,15 @@ hipError_t launch_device_pass(int log2m, const PassArgs& a, int persist_wgs, uin
 // Copies arena-layout values of graph nodes into packed graph-order arrays.
 hipError_t launch_pack(const double* src, double* dst, int64_t n_arena, const int32_t* blk_graph,
                        const GraphDev* graphs, hipStream_t s);
+// Serving: CSR of one graph into its pool regions (indices already copied
+// to arc_base.. and rebased in place), slot admission at the next engine
+// pass, planning totals, and a whole slot record.
+hipError_t launch_rebase_csr(const void* off_l, int bits, int64_t n, int64_t m, int64_t node_base, int64_t arc_base,
+                             int64_t* off, int32_t* idx, hipStream_t s);
+hipError_t launch_admit(PassCtl* ctl, GraphDev* graphs, int32_t slot, const GraphDev& val, int32_t* blk_graph,
+                        uint64_t* mod0, uint64_t* mod1, int64_t b0, int64_t b1, hipStream_t s);
+hipError_t launch_set_plan(PassCtl* ctl, int64_t listed_rows, int64_t arcs, hipStream_t s);
+hipError_t launch_set_slot(GraphDev* graphs, int32_t slot, const GraphDev& val, hipStream_t s);
 hipError_t launch_pack_u8(const uint8_t* src, uint8_t* dst, int64_t n_arena, int p, const int32_t* blk_graph,
                           const GraphDev* graphs, hipStream_t s);
 // ev_mid (nullable) is recorded between the expand and merge kernels.

@@ -1148,6 +1148,59 @@ __global__ void k_pack_u8(const uint8_t* src, uint8_t* dst, int64_t n_arena, int
         *reinterpret_cast<const uint4*>(src + v * p + chunk * 16);
 }
 
+// --- serving: admission and retirement of one graph in a live engine ------
+
+// Moves a graph's CSR into its pool regions: offsets (int32 or int64, local)
+// become arc_base + offset at node_base + v; indices, already copied to
+// their arc region, get node_base added in place.
+__global__ void k_rebase_csr(const void* off_l, int bits, int64_t n, int64_t m, int64_t node_base, int64_t arc_base,
+                             int64_t* off, int32_t* idx) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t v = t0; v <= n; v += stride) {
+    const int64_t o = bits == 64 ? static_cast<const int64_t*>(off_l)[v] : (int64_t) static_cast<const int32_t*>(off_l)[v];
+    off[node_base + v] = arc_base + o;
+  }
+  for (int64_t e = t0; e < m; e += stride) idx[arc_base + e] += (int32_t)node_base;
+}
+
+// Puts a graph into slot `slot` so that the engine's next pass is its pass 0:
+// t0 is the engine pass index at that point, the region's blocks map to the
+// slot, and every node of the region counts as changed in the previous pass
+// (so any pass mode gathers all of its successors) and as unchanged so far in
+// the next one.
+__global__ void k_admit(PassCtl* ctl, GraphDev* graphs, int32_t slot, GraphDev val, int32_t* blk_graph, uint64_t* mod0,
+                        uint64_t* mod1, int64_t b0, int64_t b1) {
+  const int par = ctl->parity;
+  uint64_t* prev = par ? mod1 : mod0;
+  uint64_t* next = par ? mod0 : mod1;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t b = b0 + t0; b < b1; b += stride) {
+    blk_graph[b] = slot;
+    prev[b] = ~0ull;
+    next[b] = 0ull;
+  }
+  if (t0 == 0) {
+    val.t0 = ctl->t;
+    val.done = 0;
+    val.passes = 0;
+    val.active = 1;
+    graphs[slot] = val;
+  }
+}
+
+__global__ void k_set_plan(PassCtl* ctl, int64_t listed_rows, int64_t arcs) {
+  if (threadIdx.x == 0) {
+    ctl->listed_rows = listed_rows;
+    ctl->arcs = arcs;
+  }
+}
+
+__global__ void k_set_slot(GraphDev* graphs, int32_t slot, GraphDev val) {
+  if (threadIdx.x == 0) graphs[slot] = val;
+}
+
 int grid_for(int64_t work, int per_block, int cap) {
   int64_t g = (work + per_block - 1) / per_block;
   if (g < 1) g = 1;
@@ -1353,6 +1406,30 @@ hipError_t launch_pack_u8(const uint8_t* src, uint8_t* dst, int64_t n_arena, int
   const int64_t threads = n_arena * (p / 16);
   hipLaunchKernelGGL(k_pack_u8, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, src, dst, n_arena, p,
                      blk_graph, graphs);
+  return hipGetLastError();
+}
+
+hipError_t launch_rebase_csr(const void* off_l, int bits, int64_t n, int64_t m, int64_t node_base, int64_t arc_base,
+                             int64_t* off, int32_t* idx, hipStream_t s) {
+  hipLaunchKernelGGL(k_rebase_csr, dim3(grid_for((n > m ? n : m) + 1, 256, 16384)), dim3(256), 0, s, off_l, bits, n,
+                     m, node_base, arc_base, off, idx);
+  return hipGetLastError();
+}
+
+hipError_t launch_admit(PassCtl* ctl, GraphDev* graphs, int32_t slot, const GraphDev& val, int32_t* blk_graph,
+                        uint64_t* mod0, uint64_t* mod1, int64_t b0, int64_t b1, hipStream_t s) {
+  hipLaunchKernelGGL(k_admit, dim3(grid_for(b1 - b0 + 1, 256, 4096)), dim3(256), 0, s, ctl, graphs, slot, val,
+                     blk_graph, mod0, mod1, b0, b1);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_plan(PassCtl* ctl, int64_t listed_rows, int64_t arcs, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_plan, dim3(1), dim3(64), 0, s, ctl, listed_rows, arcs);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_slot(GraphDev* graphs, int32_t slot, const GraphDev& val, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_slot, dim3(1), dim3(64), 0, s, graphs, slot, val);
   return hipGetLastError();
 }
 
