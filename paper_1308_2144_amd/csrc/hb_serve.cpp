@@ -722,7 +722,6 @@ hb_status serve_step(hb_server* s, bool* progress) {
       r->admitting = false;
       break;
     }
-    if (!place(e, r)) break;
     st = enqueue_admit(s, e, r);
     if (st != HB_OK) return st;
     s->pending.pop_front();
