@@ -213,6 +213,182 @@ def bench_batch(args, torch, hb, plain_sample: int = 512):
             "mismatches_on_sample": mismatch}
 
 
+class PinnedArena:
+    """First-fit allocator over one pinned host buffer (result buffers of
+    served requests, so that their copies run asynchronously)."""
+
+    def __init__(self, torch, nbytes: int):
+        self.buf = torch.empty(nbytes, dtype=torch.uint8).pin_memory()
+        self.np = self.buf.numpy()
+        self.free = [(0, nbytes)]
+
+    def alloc(self, nbytes: int):
+        nbytes = (nbytes + 255) // 256 * 256
+        for k, (s, ln) in enumerate(self.free):
+            if ln >= nbytes:
+                self.free[k] = (s + nbytes, ln - nbytes)
+                if self.free[k][1] == 0:
+                    del self.free[k]
+                return s, nbytes
+        return None
+
+    def release(self, s: int, nbytes: int):
+        self.free.append((s, nbytes))
+        self.free.sort()
+        merged = []
+        for a, ln in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == a:
+                merged[-1] = (merged[-1][0], merged[-1][1] + ln)
+            else:
+                merged.append((a, ln))
+        self.free = merged
+
+
+SERVE_OUTS = ("closeness", "lin", "harmonic")
+
+
+def serve_pool(torch, count: int, seed: int = 5):
+    """Request pool of the serving workload: directed R-MAT graphs, scale
+    uniform in 10..20, edge factor uniform in 4..32, transposed, int32 CSR,
+    in pinned host memory."""
+    import graphgen
+
+    rng = np.random.default_rng(seed)
+    pool = []
+    for j in range(count):
+        sc = int(rng.integers(10, 21))
+        ef = int(rng.integers(4, 33))
+        off, idx = graphgen.rmat(sc, ef, seed=1000 + j, transpose=True)
+        o = torch.from_numpy(off.astype(np.int32)).pin_memory()
+        x = torch.from_numpy(idx).pin_memory()
+        pool.append(dict(scale=sc, ef=ef, n=len(off) - 1, m=len(idx), off=o.numpy(), idx=x.numpy(),
+                         _t=(o, x)))
+    return pool
+
+
+def bench_serve(args, torch, hb, n_requests: int = 2000, rate: float = 500.0, pool_size: int = 32):
+    """Serving form under Poisson arrivals: requests (pool graph, log2m in
+    {4, 6, 8}, hash seed) arrive at `rate` per second; latency is arrival to
+    outputs in host memory on the server's clock.  Also: throughput with all
+    requests queued at once, repeated plain per-request runs on a sample, and
+    a bit-for-bit check of served against plain outputs on a sample."""
+    import threading
+
+    t = time.time()
+    pool = serve_pool(torch, pool_size)
+    log(f"serve: pool of {pool_size} graphs, n={sum(g['n'] for g in pool)} m={sum(g['m'] for g in pool)}, "
+        f"generated in {time.time() - t:.1f}s")
+    rng = np.random.default_rng(5)
+    gaps = rng.exponential(1.0 / rate, size=n_requests)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    which = rng.integers(0, pool_size, size=n_requests)
+    classes = rng.choice([4, 6, 8], size=n_requests)
+    hseeds = rng.integers(0, 1 << 40, size=n_requests)
+    arena = PinnedArena(torch, 2 << 30)
+    check_ids = set(rng.choice(n_requests, size=24, replace=False).tolist())
+
+    def run_stream(times, tag):
+        srv = hb.Server(validate=0)
+        # engines (one per log2m) are created on first use: warm them up
+        for b in (4, 6, 8):
+            g = pool[0]
+            srv.wait(srv.submit(g["off"], g["idx"], b, 1, outputs=()))
+        st0 = srv.stats()
+        done_q = []
+        lock = threading.Lock()
+        kept = {}
+        infos = [None] * n_requests
+
+        def waiter():
+            while True:
+                with lock:
+                    item = done_q.pop(0) if done_q else None
+                if item is None:
+                    time.sleep(0.0002)
+                    continue
+                if item == "end":
+                    return
+                i, req, alloc = item
+                infos[i] = srv.wait(req)
+                if tag == "poisson" and i in check_ids:
+                    kept[i] = {k: v.copy() for k, v in req.outputs.items()}
+                with lock:
+                    arena.release(*alloc)
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        t0 = time.perf_counter()
+        for i in range(n_requests):
+            g = pool[which[i]]
+            n = g["n"]
+            while True:
+                with lock:
+                    a = arena.alloc(24 * n)
+                if a is not None:
+                    break
+                time.sleep(0.0005)
+            base = a[0]
+            outs = {k: arena.np[base + 8 * n * j: base + 8 * n * (j + 1)].view(np.float64)
+                    for j, k in enumerate(SERVE_OUTS)}
+            if times is not None:
+                dt = times[i] - (time.perf_counter() - t0)
+                if dt > 0.002:
+                    time.sleep(dt - 0.001)
+                while time.perf_counter() - t0 < times[i]:
+                    pass
+            req = srv.submit(g["off"], g["idx"], int(classes[i]), int(hseeds[i]), outputs=(), out=outs)
+            with lock:
+                done_q.append((i, req, a))
+        with lock:
+            done_q.append("end")
+        th.join()
+        st = srv.stats()
+        srv.stop()
+        lat = np.array([f["t_done"] - f["t_submit"] for f in infos]) * 1e3
+        first = min(f["t_submit"] for f in infos)
+        last = max(f["t_done"] for f in infos)
+        window = last - first
+        passes = np.array([f["passes"] for f in infos])
+        visits = float(sum(pool[which[i]]["m"] * passes[i] for i in range(n_requests)))
+        res = {"requests": n_requests, "graphs_per_s": n_requests / window, "window_s": window,
+               "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+               "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+               "edge_visits_per_s": visits / window,
+               "gpu_busy_frac": (st["busy_s"] - st0["busy_s"]) / window,
+               "engine_passes": st["engine_passes"] - st0["engine_passes"],
+               "request_passes": int(passes.sum()),
+               "peak_resident_bytes": st["peak_resident_bytes"]}
+        log(f"serve {tag}: {json.dumps(res)}")
+        return res, infos, kept
+
+    poisson, infos, kept = run_stream(arrivals, "poisson")
+    burst, _, _ = run_stream(None, "burst")
+    # Plain: the same requests one after another through hb_init / hb_run /
+    # hb_centralities / hb_free (host CSR, outputs to host), on a sample.
+    sample = sorted(set(range(0, n_requests, max(1, n_requests // 100))) | check_ids)
+    mism = 0
+    plain_t = 0.0
+    for i in sample:
+        g = pool[which[i]]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with hb.HyperBall(g["off"], g["idx"], int(classes[i]), int(hseeds[i]), validate=0) as ctx:
+            passes = ctx.run()
+            cen = ctx.centralities()
+        plain_t += time.perf_counter() - t0
+        if i in kept:
+            same = passes == infos[i]["passes"] and all(np.array_equal(cen[k], kept[i][k]) for k in SERVE_OUTS)
+            mism += int(not same)
+    plain_gps = len(sample) / plain_t
+    return {"workload": f"Poisson arrivals {rate:g}/s (seed 5), {n_requests} requests over a pool of "
+                        f"{pool_size} directed R-MAT graphs (scale U{{10..20}}, edge factor U{{4..32}}, "
+                        "transposed, int32 CSR, pinned host memory), log2m U{4,6,8}, budget 64 GiB",
+            "poisson": poisson, "burst": burst,
+            "plain_graphs_per_s": plain_gps, "plain_sample": len(sample),
+            "burst_speedup_vs_plain": burst["graphs_per_s"] / plain_gps,
+            "identical_on_sample": mism == 0, "checked": len(kept), "mismatches": mism}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +406,8 @@ def main():
     ap.add_argument("--qdense", type=int, default=0)
     ap.add_argument("--slice", type=int, default=0)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-only", action="store_true", help="only the serving measurement (its own line)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (torch) 3 times, to scale HBM counters")
     args = ap.parse_args()
@@ -241,6 +419,9 @@ def main():
 
     import paper_1308_2144_amd as hb
 
+    if args.serve_only:
+        print(json.dumps({"serving": bench_serve(args, torch, hb)}), flush=True)
+        return
     w = WORKLOADS[args.workload]
     off, idx = make_graph(w)
     n, m = len(off) - 1, len(idx)
@@ -338,6 +519,10 @@ def main():
     if not args.no_batch:
         log("batched form ...")
         out["batched"] = bench_batch(args, torch, hb)
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        log("serving form ...")
+        out["serving"] = bench_serve(args, torch, hb)
         torch.cuda.empty_cache()
     if args.copy_calib:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
