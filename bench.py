@@ -140,7 +140,11 @@ def bench_batch(args, torch, hb, plain_sample: int = 512):
     log(f"batch: {k} graphs, n={sum(len(o) - 1 for o, _ in graphs)}, m={sum(len(i) for _, i in graphs)}, "
         f"generated in {time.time() - t:.1f}s")
     t = time.time()
-    bt = hb.Batch(graphs, b, seeds)
+    opt, tune = hb.hb_batch_autotune(graphs, b, seeds, sample=256, cache_path=args.tune_cache or None)
+    tuned = hb.options_dict(opt)
+    log(f"batch: autotune {tune} -> {tuned} in {time.time() - t:.1f}s")
+    t = time.time()
+    bt = hb.Batch(graphs, b, seeds, options=opt)
     log(f"batch: context built in {time.time() - t:.1f}s; stats {bt.stats()}")
     outs = [torch.empty(max(bt.total, 1), dtype=torch.float64, device="cuda") for _ in range(4)]
 
@@ -163,6 +167,7 @@ def bench_batch(args, torch, hb, plain_sample: int = 512):
     harm = bt.split(outs[2].cpu().numpy())
     bt.close()
     del outs
+    row_opts = {k: tuned[k] for k in ("light_max", "heavy_min", "chunk", "dense_pct", "sparse_pct", "qdense")}
     # Plain runs: one context per graph (created before timing), each reset,
     # run and finalised in turn; a seeded sample of the graphs, scaled to all.
     rng = np.random.default_rng(7)
@@ -171,7 +176,7 @@ def bench_batch(args, torch, hb, plain_sample: int = 512):
     for i in sample:
         o, x = graphs[i]
         ctxs.append(hb.HyperBall(torch.from_numpy(o).cuda(), torch.from_numpy(x).cuda(), b, int(seeds[i]),
-                                 stream=torch.cuda.current_stream().cuda_stream))
+                                 stream=torch.cuda.current_stream().cuda_stream, **row_opts))
     pouts = [torch.empty(200_001, dtype=torch.float64, device="cuda") for _ in range(4)]
     plain_passes = []
     torch.cuda.synchronize()
@@ -197,7 +202,7 @@ def bench_batch(args, torch, hb, plain_sample: int = 512):
     t0 = time.perf_counter()
     for i in cold:
         o, x = graphs[i]
-        with hb.HyperBall(o, x, b, int(seeds[i])) as g:
+        with hb.HyperBall(o, x, b, int(seeds[i]), **row_opts) as g:
             g.run()
             g.centralities()
     torch.cuda.synchronize()
@@ -210,6 +215,9 @@ def bench_batch(args, torch, hb, plain_sample: int = 512):
             "plain_sample": int(len(sample)),
             "plain_cold_graphs_per_s": k / cdt, "plain_cold_sample": int(len(cold)),
             "speedup_vs_plain": pdt / bdt, "identical_on_sample": bool(identical),
+            "autotune": {"options": {k: tuned[k] for k in ("light_max", "heavy_min", "chunk", "wgs_per_cu",
+                                                            "graph_passes", "dense_pct", "sparse_pct", "qdense")},
+                         **tune},
             "mismatches_on_sample": mismatch}
 
 
@@ -407,6 +415,9 @@ def main():
     ap.add_argument("--slice", type=int, default=0)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1308_2144_amd", "tune_cache.txt"),
+                    help="autotuner cache of the batched form ('' for none: tune every run)")
+    ap.add_argument("--batch-only", action="store_true", help="only the batched measurement (its own line)")
     ap.add_argument("--serve-only", action="store_true", help="only the serving measurement (its own line)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (torch) 3 times, to scale HBM counters")
@@ -421,6 +432,9 @@ def main():
 
     if args.serve_only:
         print(json.dumps({"serving": bench_serve(args, torch, hb)}), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps({"batched": bench_batch(args, torch, hb)}), flush=True)
         return
     w = WORKLOADS[args.workload]
     off, idx = make_graph(w)

@@ -95,7 +95,11 @@ typedef struct {
  *   qdense     1: dense passes use the queued two-phase gather as well
  *              (tuning knob; results are identical).
  *   slice      1: keep a mask of changed 16-byte register slices per node
- *              (2n bytes) and let edge passes gather only changed slices. */
+ *              (2n bytes) and let edge passes gather only changed slices.
+ *   wgs_per_cu batched and served contexts: workgroups per compute unit of
+ *              their persistent pass kernels (<= 0: 5).
+ *   graph_passes batched contexts: passes per captured hipGraph replay in
+ *              hb_run (<= 0: 4; convergence is read back once per replay). */
 typedef struct {
   int32_t frontier;
   int32_t light_max;
@@ -108,6 +112,8 @@ typedef struct {
   int32_t sparse_pct;
   int32_t qdense;
   int32_t slice;
+  int32_t wgs_per_cu;
+  int32_t graph_passes;
 } hb_options;
 
 void hb_default_options(hb_options* opt);
@@ -229,6 +235,30 @@ hb_status hb_batch_reset(hb_ctx* c, const uint64_t* seeds);
 hb_status hb_batch_graph(hb_ctx* c, int32_t g, hb_graph_info* info);
 /* Per-graph pass counts (k entries; -1 for a graph not converged yet). */
 hb_status hb_batch_passes(hb_ctx* c, int32_t* passes);
+
+/* Autotuner for batched contexts.  Times complete batched runs (reset +
+ * passes to convergence) on `sample` of the k graphs (<= 0: 256; graphs
+ * sorted by size, evenly spaced) and picks, by coordinate descent from *opt:
+ * light_max (rows up to this many arcs go to one lane group, longer ones to
+ * a wavefront), heavy_min / chunk (rows from heavy_min arcs are cut into
+ * workgroup tiles of chunk arcs), wgs_per_cu, graph_passes, dense_pct,
+ * sparse_pct and qdense.  The options never change results; the tuner checks
+ * that every candidate gives the same per-graph pass counts.  *opt receives
+ * the winner.  cache_path (nullable): a text file of earlier winners keyed
+ * by a signature of the batch (log2m, sizes, degree histogram) and the
+ * device; a hit returns at once, a new winner is appended. */
+typedef struct {
+  int32_t candidates;     /* configurations timed */
+  int32_t from_cache;     /* 1: options came from the cache */
+  int32_t sample_graphs;
+  double start_ms;        /* one run over the sample with the starting options */
+  double best_ms;         /* the same with the chosen options */
+  double tune_s;          /* wall time of the call */
+} hb_tune_report;
+
+hb_status hb_batch_autotune(const hb_csr* graphs, int32_t k, int32_t log2m, const uint64_t* seeds,
+                            int32_t sample, const char* cache_path, hb_options* opt,
+                            hb_tune_report* report);
 
 /* ---- Serving form: a request loop over resident engines ----------------
  * A server owns one multi-graph engine per log2m in [4, 8] (made on first

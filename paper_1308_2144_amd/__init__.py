@@ -47,7 +47,8 @@ class hb_options(ctypes.Structure):
                 ("validate", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("dense_pct", ctypes.c_int32), ("push", ctypes.c_int32),
                 ("sparse_pct", ctypes.c_int32), ("qdense", ctypes.c_int32),
-                ("slice", ctypes.c_int32)]
+                ("slice", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
+                ("graph_passes", ctypes.c_int32)]
 
 
 class hb_stats_t(ctypes.Structure):
@@ -99,6 +100,11 @@ class hb_serve_stats_t(ctypes.Structure):
                [("busy_s", ctypes.c_double), ("elapsed_s", ctypes.c_double)]
 
 
+class hb_tune_report(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("sample_graphs", ctypes.c_int32),
+                ("start_ms", ctypes.c_double), ("best_ms", ctypes.c_double), ("tune_s", ctypes.c_double)]
+
+
 HB_REQ_QUEUED, HB_REQ_RUNNING, HB_REQ_DONE, HB_REQ_CANCELLED, HB_REQ_FAILED = range(5)
 REQ_STATES = ("queued", "running", "done", "cancelled", "failed")
 
@@ -124,6 +130,8 @@ def _declare(L):
         "hb_batch_reset": (ctypes.c_int, [vp, vp]),
         "hb_batch_graph": (ctypes.c_int, [vp, i32, P(hb_graph_info)]),
         "hb_batch_passes": (ctypes.c_int, [vp, vp]),
+        "hb_batch_autotune": (ctypes.c_int, [vp, i32, i32, vp, i32, ctypes.c_char_p, P(hb_options),
+                                             P(hb_tune_report)]),
         "hb_serve_default_config": (None, [P(hb_serve_config)]),
         "hb_serve_start": (ctypes.c_int, [P(vp), P(hb_serve_config)]),
         "hb_serve_resume": (ctypes.c_int, [vp]),
@@ -315,6 +323,40 @@ def hb_batch_passes(ctx, k: int) -> np.ndarray:
     return out
 
 
+def _csr_array(graphs):
+    k = len(graphs)
+    arr = (hb_csr * k)()
+    keep = []
+    for i, (o, x) in enumerate(graphs):
+        o = np.ascontiguousarray(o)
+        if o.dtype not in (np.int32, np.int64):
+            o = o.astype(np.int64)
+        x = np.ascontiguousarray(x, dtype=np.int32)
+        keep.append((o, x))
+        arr[i] = hb_csr(o.shape[0] - 1, x.shape[0], o.ctypes.data, 64 if o.dtype == np.int64 else 32,
+                        x.ctypes.data if x.size else None, 0)
+    return arr, keep
+
+
+def hb_batch_autotune(graphs, log2m: int, seeds, sample: int = 0, cache_path: str | None = None,
+                      options: hb_options | None = None):
+    """Returns (tuned hb_options, report dict)."""
+    arr, keep = _csr_array(graphs)
+    sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+    if sd.shape[0] != len(graphs):
+        raise ValueError("need one seed per graph")
+    opt = options if options is not None else default_options()
+    rep = hb_tune_report()
+    _check(lib().hb_batch_autotune(ctypes.cast(arr, ctypes.c_void_p), len(graphs), int(log2m), sd.ctypes.data,
+                                   int(sample), cache_path.encode() if cache_path else None, ctypes.byref(opt),
+                                   ctypes.byref(rep)))
+    return opt, {k: getattr(rep, k) for k, _ in hb_tune_report._fields_}
+
+
+def options_dict(o: hb_options) -> dict:
+    return {k: getattr(o, k) for k, _ in hb_options._fields_}
+
+
 def hb_serve_default_config() -> hb_serve_config:
     cfg = hb_serve_config()
     lib().hb_serve_default_config(ctypes.byref(cfg))
@@ -442,14 +484,14 @@ class Batch:
     """Many graphs in one batched context (see hb_batch_init in include/hb.h).
     Packed outputs are split per graph with split()."""
 
-    def __init__(self, graphs, log2m: int, seeds, *, stream=None, **options):
+    def __init__(self, graphs, log2m: int, seeds, *, stream=None, options: hb_options | None = None, **kw):
         self.log2m = int(log2m)
         self.p = 1 << self.log2m
         self.k = len(graphs)
         self.sizes = np.array([len(o) - 1 for o, _ in graphs], dtype=np.int64)
         self.bounds = np.concatenate([[0], np.cumsum(self.sizes)])
         self.total = int(self.bounds[-1])
-        opt = default_options(**options)
+        opt = options if options is not None else default_options(**kw)
         self._ctx, self._keep = hb_batch_init(graphs, log2m, seeds, opt, stream)
 
     def close(self):

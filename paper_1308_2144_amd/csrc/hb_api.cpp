@@ -307,8 +307,8 @@ hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, co
     HB_HIP(hipGetDevice(&dev));
     hipDeviceProp_t prop;
     HB_HIP(hipGetDeviceProperties(&prop, dev));
-    c->persist_wgs = prop.multiProcessorCount * 5;
-    c->graph_passes = 4;
+    c->persist_wgs = prop.multiProcessorCount * (c->opt.wgs_per_cu > 0 ? c->opt.wgs_per_cu : 5);
+    c->graph_passes = c->opt.graph_passes > 0 ? c->opt.graph_passes : 4;
   }
   hb_status st = do_reset(c, seed);
   if (st != HB_OK) return st;
@@ -435,6 +435,8 @@ void hb_default_options(hb_options* opt) {
   opt->sparse_pct = DEFAULT_SPARSE_PCT;
   opt->qdense = 0;
   opt->slice = 0;
+  opt->wgs_per_cu = 5;
+  opt->graph_passes = 4;
 }
 
 hb_status hb_init(hb_ctx** out, const hb_csr* g, int32_t log2m, uint64_t seed, const hb_options* opt,

@@ -389,7 +389,7 @@ hb_status make_engine(hb_server* s, int b, Engine** out) {
   ENG_HIP(hipGetDevice(&dev));
   hipDeviceProp_t prop;
   ENG_HIP(hipGetDeviceProperties(&prop, dev));
-  c->persist_wgs = prop.multiProcessorCount * 5;
+  c->persist_wgs = prop.multiProcessorCount * (cfg.opt.wgs_per_cu > 0 ? cfg.opt.wgs_per_cu : 5);
   for (int i = 0; i < TICK_DEPTH; ++i) {
     Tick t;
     ENG_HIP(hipEventCreateWithFlags(&t.ev, hipEventDisableTiming));

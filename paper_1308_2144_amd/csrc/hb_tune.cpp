@@ -1,0 +1,299 @@
+// Autotuner of batched contexts: picks the row classes (how many arcs a row
+// may have to be handled by one lane group, or a whole wavefront, before it
+// is cut into workgroup tiles of `chunk` arcs), the persistent launch shape,
+// the passes per hipGraph replay and the pass-mode thresholds by timing
+// complete batched runs on a sample of the graphs.  Every candidate computes
+// the same registers (the options only change how the work is scheduled), so
+// the tuner compares per-graph pass counts across candidates as a check.
+//
+// Search: coordinate descent, first over the knobs that change the row
+// lists (each candidate builds its own context on the sample), then over the
+// run-time knobs on one context.  The winner is stored in a text cache keyed
+// by a signature of the workload (log2m, sizes, degree histogram) and the
+// device, so a later call with a similar batch reuses it without timing.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "hb_ctx.h"
+
+using namespace hbh;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+uint64_t fnv1a(const std::string& s) {
+  uint64_t h = 1469598103934665603ull;
+  for (unsigned char ch : s) {
+    h ^= ch;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+template <class T>
+void degree_histogram(const T* off, int64_t n, std::vector<double>& hist) {
+  for (int64_t v = 0; v < n; ++v) {
+    const int64_t d = (int64_t)off[v + 1] - (int64_t)off[v];
+    int bucket = 0;
+    while (bucket < 24 && (1ll << bucket) <= d) ++bucket;  // 0: d = 0, j: 2^(j-1) <= d < 2^j
+    hist[(size_t)bucket] += 1.0;
+  }
+}
+
+// Signature of a batch for the cache: coarse enough that batches drawn from
+// the same distribution share it.
+std::string signature(const hb_csr* graphs, int32_t k, int32_t log2m, const hb_options& start) {
+  std::vector<double> deg(25, 0.0), size(32, 0.0);
+  double nodes = 0.0, arcs = 0.0;
+  for (int32_t i = 0; i < k; ++i) {
+    const hb_csr& g = graphs[i];
+    if (g.offsets_bits == 64)
+      degree_histogram(static_cast<const int64_t*>(g.offsets), g.n, deg);
+    else
+      degree_histogram(static_cast<const int32_t*>(g.offsets), g.n, deg);
+    int b = 0;
+    while (b < 31 && (1ll << b) <= g.n) ++b;
+    size[(size_t)b] += 1.0;
+    nodes += (double)g.n;
+    arcs += (double)g.m;
+  }
+  std::ostringstream o;
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    o << prop.gcnArchName << "/" << prop.multiProcessorCount;
+  o << " v" << hb_version() << " b" << log2m << " f" << start.frontier << " k" << std::lround(std::log2((double)k));
+  o << " a" << std::lround(4.0 * std::log2(arcs + 1.0)) << " d";
+  for (double x : deg) o << "," << std::lround(20.0 * x / std::max(nodes, 1.0));
+  o << " s";
+  for (double x : size) o << "," << std::lround(10.0 * x / k);
+  char key[32];
+  std::snprintf(key, sizeof(key), "%016llx", (unsigned long long)fnv1a(o.str()));
+  return key;
+}
+
+const char* CACHE_TAG = "hbtune1";
+
+bool cache_lookup(const char* path, const std::string& key, hb_options* opt, double* ms) {
+  if (!path || !*path) return false;
+  std::ifstream in(path);
+  std::string line;
+  bool found = false;
+  while (std::getline(in, line)) {
+    std::istringstream ls(line);
+    std::string tag, k;
+    hb_options o = *opt;
+    double t = 0.0;
+    if (!(ls >> tag >> k) || tag != CACHE_TAG || k != key) continue;
+    if (ls >> o.light_max >> o.heavy_min >> o.chunk >> o.wgs_per_cu >> o.graph_passes >> o.dense_pct >> o.sparse_pct >>
+        o.qdense >> t) {
+      *opt = o;  // the last matching line wins
+      *ms = t;
+      found = true;
+    }
+  }
+  return found;
+}
+
+void cache_store(const char* path, const std::string& key, const hb_options& o, double ms) {
+  if (!path || !*path) return;
+  std::ofstream out(path, std::ios::app);
+  out << CACHE_TAG << " " << key << " " << o.light_max << " " << o.heavy_min << " " << o.chunk << " " << o.wgs_per_cu
+      << " " << o.graph_passes << " " << o.dense_pct << " " << o.sparse_pct << " " << o.qdense << " " << ms << "\n";
+}
+
+struct Sample {
+  std::vector<hb_csr> graphs;
+  std::vector<uint64_t> seeds;
+  int32_t log2m = 0;
+};
+
+// Applies the knobs that do not change the row lists to a batched context.
+hb_status apply_runtime(hb_ctx* c, const hb_options& o) {
+  int dev = 0;
+  HB_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HB_HIP(hipGetDeviceProperties(&prop, dev));
+  c->opt.wgs_per_cu = o.wgs_per_cu;
+  c->opt.graph_passes = o.graph_passes;
+  c->opt.dense_pct = o.dense_pct;
+  c->opt.sparse_pct = o.sparse_pct;
+  c->opt.qdense = o.qdense;
+  c->persist_wgs = prop.multiProcessorCount * std::max(o.wgs_per_cu, 1);
+  c->graph_passes = std::max(o.graph_passes, 1);
+  c->ctl_host->dense_pct = o.dense_pct;
+  c->ctl_host->sparse_pct = o.sparse_pct;
+  if (c->gexec) {
+    (void)hipGraphExecDestroy(c->gexec);  // captured with the old launch arguments
+    c->gexec = nullptr;
+  }
+  return HB_OK;
+}
+
+// Best of `reps` timed runs (reset + passes to convergence) after one
+// untimed run; checks the per-graph pass counts against `ref` (filled by
+// the first call).
+hb_status time_runs(hb_ctx* c, int reps, std::vector<int32_t>& ref, double* best_ms) {
+  std::vector<int32_t> passes((size_t)c->n_graphs);
+  *best_ms = 1e300;
+  for (int r = 0; r <= reps; ++r) {
+    const auto t0 = Clock::now();
+    hb_status st = hb_batch_reset(c, nullptr);
+    if (st == HB_OK) st = hb_run(c, 0, nullptr);
+    if (st != HB_OK) return st;
+    const double ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+    if (r > 0) *best_ms = std::min(*best_ms, ms);
+  }
+  hb_status st = hb_batch_passes(c, passes.data());
+  if (st != HB_OK) return st;
+  if (ref.empty())
+    ref = passes;
+  else if (ref != passes)
+    return fail(HB_EDEVICE, "autotune: candidates disagree on per-graph pass counts");
+  return HB_OK;
+}
+
+hb_status time_structural(const Sample& s, const hb_options& o, int reps, std::vector<int32_t>& ref, double* ms,
+                          hipStream_t stream) {
+  hb_ctx* c = nullptr;
+  hb_status st = hb_batch_init(&c, s.graphs.data(), (int32_t)s.graphs.size(), s.log2m, s.seeds.data(), &o, stream);
+  if (st != HB_OK) return st;
+  st = time_runs(c, reps, ref, ms);
+  hb_free(c);
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+hb_status hb_batch_autotune(const hb_csr* graphs, int32_t k, int32_t log2m, const uint64_t* seeds, int32_t sample,
+                            const char* cache_path, hb_options* opt, hb_tune_report* report) {
+  if (!graphs || !seeds || !opt || k <= 0) return fail(HB_EINVAL, "need graphs, seeds and options");
+  if (log2m < 4 || log2m > 8) return fail(HB_EINVAL, "batched contexts need log2m in [4, 8]");
+  const auto t_start = Clock::now();
+  hb_tune_report rep{};
+  const hb_options start = *opt;
+  const std::string key = signature(graphs, k, log2m, start);
+  double cached_ms = 0.0;
+  if (cache_lookup(cache_path, key, opt, &cached_ms)) {
+    rep.from_cache = 1;
+    rep.best_ms = cached_ms;
+    rep.tune_s = std::chrono::duration<double>(Clock::now() - t_start).count();
+    if (report) *report = rep;
+    return HB_OK;
+  }
+  // Sample: graphs sorted by size, every k/sample-th, so that all sizes occur.
+  Sample s;
+  s.log2m = log2m;
+  std::vector<int32_t> order((size_t)k);
+  for (int32_t i = 0; i < k; ++i) order[(size_t)i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return graphs[a].n < graphs[b].n; });
+  const int32_t want = sample > 0 ? std::min(sample, k) : std::min(k, 256);
+  for (int32_t j = 0; j < want; ++j) {
+    const int32_t i = order[(size_t)(((int64_t)j * k + k / 2) / want)];
+    s.graphs.push_back(graphs[i]);
+    s.seeds.push_back(seeds[i]);
+  }
+  hipStream_t stream = nullptr;
+  HB_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+  struct StreamGuard {
+    hipStream_t s;
+    ~StreamGuard() { (void)hipStreamDestroy(s); }
+  } guard{stream};
+  const int reps = 2;
+  std::vector<int32_t> ref;
+  hb_options best = start;
+  double best_ms = 0.0;
+  hb_status st = time_structural(s, best, reps, ref, &best_ms, stream);
+  if (st != HB_OK) return st;
+  rep.start_ms = best_ms;
+  rep.candidates = 1;
+  // Structural knobs: row classes and heavy-row tiles.
+  best.validate = 0;  // validated by the first build
+  for (int lm : {16, 32, 64, 128, 256}) {
+    if (lm == best.light_max) continue;
+    hb_options o = best;
+    o.light_max = lm;
+    if (o.heavy_min <= lm) o.heavy_min = lm + 1;
+    double ms = 0.0;
+    st = time_structural(s, o, reps, ref, &ms, stream);
+    if (st != HB_OK) return st;
+    rep.candidates++;
+    if (ms < best_ms) best_ms = ms, best = o;
+  }
+  const int tiles[][2] = {{2048, 1024}, {4096, 2048}, {8192, 4096}, {16384, 4096}, {16384, 8192}, {65536, 16384}};
+  for (const auto& t : tiles) {
+    if (t[0] == best.heavy_min && t[1] == best.chunk) continue;
+    if (t[0] <= best.light_max) continue;
+    hb_options o = best;
+    o.heavy_min = t[0];
+    o.chunk = t[1];
+    double ms = 0.0;
+    st = time_structural(s, o, reps, ref, &ms, stream);
+    if (st != HB_OK) return st;
+    rep.candidates++;
+    if (ms < best_ms) best_ms = ms, best = o;
+  }
+  // Run-time knobs on one context with the chosen row classes.
+  hb_ctx* c = nullptr;
+  st = hb_batch_init(&c, s.graphs.data(), (int32_t)s.graphs.size(), s.log2m, s.seeds.data(), &best, stream);
+  if (st != HB_OK) return st;
+  auto try_runtime = [&](hb_options o) -> hb_status {
+    hb_status e = apply_runtime(c, o);
+    double ms = 0.0;
+    if (e == HB_OK) e = time_runs(c, reps, ref, &ms);
+    if (e != HB_OK) return e;
+    rep.candidates++;
+    if (ms < best_ms) best_ms = ms, best = o;
+    return HB_OK;
+  };
+  for (int w : {2, 3, 4, 6, 8}) {
+    hb_options o = best;
+    o.wgs_per_cu = w;
+    if (w != best.wgs_per_cu && (st = try_runtime(o)) != HB_OK) break;
+  }
+  for (int gp : {1, 2, 8, 16}) {
+    if (st != HB_OK) break;
+    hb_options o = best;
+    o.graph_passes = gp;
+    if (gp != best.graph_passes) st = try_runtime(o);
+  }
+  for (int dp : {30, 45, 75, 90}) {
+    if (st != HB_OK) break;
+    hb_options o = best;
+    o.dense_pct = dp;
+    if (dp != best.dense_pct) st = try_runtime(o);
+  }
+  for (int sp : {5, 10, 40}) {
+    if (st != HB_OK) break;
+    hb_options o = best;
+    o.sparse_pct = sp;
+    if (sp != best.sparse_pct) st = try_runtime(o);
+  }
+  if (st == HB_OK) {
+    hb_options o = best;
+    o.qdense = best.qdense ? 0 : 1;
+    st = try_runtime(o);
+  }
+  hb_free(c);
+  if (st != HB_OK) return st;
+  best.validate = start.validate;
+  *opt = best;
+  cache_store(cache_path, key, best, best_ms);
+  rep.best_ms = best_ms;
+  rep.sample_graphs = (int32_t)s.graphs.size();
+  rep.tune_s = std::chrono::duration<double>(Clock::now() - t_start).count();
+  if (report) *report = rep;
+  return HB_OK;
+}
+
+}  // extern "C"

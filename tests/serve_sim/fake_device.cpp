@@ -105,6 +105,8 @@ void hb_default_options(hb_options* opt) {
   opt->sparse_pct = 20;
   opt->qdense = 0;
   opt->slice = 0;
+  opt->wgs_per_cu = 5;
+  opt->graph_passes = 4;
 }
 }
 

@@ -84,3 +84,17 @@ def test_binding_refuses_mixed_inputs():
 
     with pytest.raises(TypeError):
         hb.hb_init(torch.zeros(2, dtype=torch.int64), np.zeros(1, dtype=np.int32), 4, 1)
+
+
+def test_autotune_argument_errors():
+    import paper_1308_2144_amd as hb
+
+    g = [(np.array([0, 1, 2], dtype=np.int64), np.array([1, 0], dtype=np.int32))]
+    with pytest.raises(hb.HBError) as e:
+        hb.hb_batch_autotune(g, 3, [1])
+    assert e.value.status == hb.HB_EINVAL
+    with pytest.raises(hb.HBError) as e:
+        hb.hb_batch_autotune(g, 9, [1])
+    assert e.value.status == hb.HB_EINVAL
+    L = hb.lib()
+    assert L.hb_batch_autotune(None, 0, 5, None, 0, None, None, None) == hb.HB_EINVAL

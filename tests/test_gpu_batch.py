@@ -147,3 +147,25 @@ def test_batch_device_outputs_are_packed_and_bounded():
         R = R.cpu().numpy()
         assert np.array_equal(R[: total * bt.p].reshape(total, bt.p), bt.registers())
         assert np.all(R[total * bt.p:] == 251)
+
+
+def test_autotune_picks_candidates_and_caches(tmp_path):
+    """The tuner returns options from its candidate sets, a second call with
+    the same batch is served from the cache, and a batch built with the tuned
+    options still equals solo runs."""
+    import paper_1308_2144_amd as hb
+
+    graphs = mixed_graphs(seed=5, count=40)
+    seeds = np.arange(len(graphs), dtype=np.uint64) + 3
+    cache = str(tmp_path / "tune.txt")
+    opt, rep = hb.hb_batch_autotune(graphs, 5, seeds, sample=16, cache_path=cache)
+    _log("autotune:", rep, hb.options_dict(opt))
+    assert rep["from_cache"] == 0 and rep["candidates"] > 10 and rep["sample_graphs"] == 16
+    assert rep["best_ms"] <= rep["start_ms"]
+    assert opt.light_max in (16, 32, 64, 128, 256) and opt.heavy_min > opt.light_max
+    assert opt.wgs_per_cu in (2, 3, 4, 5, 6, 8) and opt.graph_passes in (1, 2, 4, 8, 16)
+    opt2, rep2 = hb.hb_batch_autotune(graphs, 5, seeds, sample=16, cache_path=cache)
+    assert rep2["from_cache"] == 1 and hb.options_dict(opt2) == hb.options_dict(opt)
+    tuned = hb.options_dict(opt)
+    compare_batch(graphs, 5, seeds, **{k: tuned[k] for k in ("light_max", "heavy_min", "chunk", "wgs_per_cu",
+                                                            "graph_passes", "dense_pct", "sparse_pct", "qdense")})
