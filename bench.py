@@ -167,7 +167,7 @@ def bench_batch(args, torch, hb, plain_sample: int = 512):
     harm = bt.split(outs[2].cpu().numpy())
     bt.close()
     del outs
-    row_opts = {k: tuned[k] for k in ("light_max", "heavy_min", "chunk", "dense_pct", "sparse_pct", "qdense")}
+    row_opts = {}  # plain contexts keep the single-graph defaults (faster for them than the batch's tuning)
     # Plain runs: one context per graph (created before timing), each reset,
     # run and finalised in turn; a seeded sample of the graphs, scaled to all.
     rng = np.random.default_rng(7)
