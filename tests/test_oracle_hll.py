@@ -6,22 +6,26 @@ conversion, closed forms of the estimator, and the statistical behaviour the
 paper states for HyperLogLog counters.
 """
 import math
+import os
 
 import numpy as np
 import pytest
 
-# Outputs of the SplitMix64 generator (Steele, Lea, Flood 2014), as printed by
-# its public reference implementation: the first outputs from state 0, and the
-# first five from state 1234567.  The k-th output from state x is
-# mix(x + k*0x9E3779B97F4A7C15), i.e. our h(x, seed = k-1).
-SPLITMIX_FROM_0 = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F, 0xF88BB8A8724C81EC]
-SPLITMIX_FROM_1234567 = [6457827717110365317, 3203168211198807973, 9817491932198370423,
-                         4593380528125082431, 16408922859458223821]
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name):
+    """Data lines of a fixture under tests/golden (each file cites its source)."""
+    with open(os.path.join(GOLDEN, name)) as f:
+        return [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
 
 
 def test_hash_matches_published_splitmix64(orc):
-    assert [orc.hash64(0, s) for s in range(4)] == SPLITMIX_FROM_0
-    assert [orc.hash64(1234567, s) for s in range(5)] == SPLITMIX_FROM_1234567
+    rows = golden("splitmix64.txt")
+    assert len(rows) >= 2
+    for state, *outs in rows:
+        want = [int(x, 0) for x in outs]
+        assert [orc.hash64(int(state, 0), s) for s in range(len(want))] == want
 
 
 def test_hash_is_injective_on_ids(orc):
@@ -30,11 +34,13 @@ def test_hash_is_injective_on_ids(orc):
 
 
 def test_rho_paper_example(orc):
-    # Sec. 4.1: rho+(00101) = 3.  Put 00101 right after the leftmost b bits.
-    for b in (4, 7, 16):
-        for idx in (0, 1, (1 << b) - 1):
-            h = (idx << (64 - b)) | (0b00101 << (64 - b - 5)) | 0x1F
-            assert orc.rho(h, b) == 3
+    # Sec. 4.1 example; the bit string is put right after the leftmost b bits.
+    for bits, want in golden("paper_rho.txt"):
+        k = len(bits)
+        for b in (4, 7, 16):
+            for idx in (0, 1, (1 << b) - 1):
+                h = (idx << (64 - b)) | (int(bits, 2) << (64 - b - k)) | 0x1F
+                assert orc.rho(h, b) == int(want)
 
 
 def test_rho_extremes(orc):
@@ -111,9 +117,10 @@ def test_register_sum_is_exact_sum_rounded_once(orc, b):
 
 
 def test_alpha_constants(orc):
-    # Flajolet et al. 2007 give alpha_16, alpha_32, alpha_64 as tabulated
-    # values and 0.7213/(1+1.079/p) beyond; all lie in (0.67, 0.7213).
-    assert orc.alpha(4) == 0.673 and orc.alpha(5) == 0.697 and orc.alpha(6) == 0.709
+    # Tabulated values of Flajolet et al. 2007, and 0.7213/(1+1.079/p) beyond;
+    # all lie in (0.67, 0.7213).
+    for m, a in golden("hll_alpha.txt"):
+        assert orc.alpha(int(m).bit_length() - 1) == float(a)
     for b in range(7, 17):
         a = orc.alpha(b)
         assert 0.709 < a < 0.7213
