@@ -221,6 +221,67 @@ def bench_batch(args, torch, hb, plain_sample: int = 512):
             "mismatches_on_sample": mismatch}
 
 
+def bench_ensemble(args, torch, hb, K: int = 8, b: int = 4, steps: int = 3):
+    """Multi-seed ensemble: K hash seeds on R-MAT scale 20 (edge factor 16,
+    transposed, gen seed 2) in one context against K plain runs one after
+    another; inputs resident, each step = reset + passes to convergence +
+    centralities and the ensemble summary into device memory."""
+    w = WORKLOADS["rmat-s20"]
+    off, idx = make_graph(w)
+    n, m = len(off) - 1, len(idx)
+    dev = torch.device("cuda:0")
+    o = torch.from_numpy(off.astype(np.int32)).to(dev)
+    x = torch.from_numpy(idx).to(dev)
+    seeds = [42 + k for k in range(K)]
+    stream = torch.cuda.current_stream().cuda_stream
+    ens = hb.Ensemble(o, x, b, seeds, stream=stream)
+    outs = [torch.empty(n * K, dtype=torch.float64, device=dev) for _ in range(4)]
+    summ = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(2)]
+
+    def estep():
+        ens.reset(seeds)
+        total = ens.run()
+        hb.hb_centralities(ens._ctx, *outs, True)
+        hb.hb_ensemble_summary(ens._ctx, "harmonic", *summ, True)
+        return total
+
+    estep()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        estep()
+    torch.cuda.synchronize()
+    edt = (time.perf_counter() - t0) / steps
+    passes = ens.passes()
+    eregs = ens.registers()
+    ens.close()
+    plain = hb.HyperBall(o, x, b, seeds[0], stream=stream)
+    pouts = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(4)]
+    ppasses = []
+    same = True
+    for k in range(K):  # warm-up and check
+        plain.reset(seeds[k])
+        ppasses.append(plain.run())
+        same &= bool(np.array_equal(plain.registers(), eregs[:, k]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for k in range(K):
+            plain.reset(seeds[k])
+            plain.run()
+            hb.hb_centralities(plain._ctx, *pouts, True)
+    torch.cuda.synchronize()
+    pdt = (time.perf_counter() - t0) / steps
+    plain.close()
+    same &= [int(v) for v in passes] == ppasses
+    visits = m * int(np.sum(passes))
+    return {"workload": f"R-MAT scale 20, edge factor 16, transposed, int32 CSR, log2m={b}, {K} seeds 42..{41 + K}",
+            "n": n, "m": m, "seeds": K, "passes": [int(v) for v in passes],
+            "ensemble_ms": edt * 1e3, "plain_ms": pdt * 1e3, "speedup_vs_plain": pdt / edt,
+            "ensemble_edge_visits_per_s": visits / edt, "plain_edge_visits_per_s": visits / pdt,
+            "identical": bool(same)}
+
+
 class PinnedArena:
     """First-fit allocator over one pinned host buffer (result buffers of
     served requests, so that their copies run asynchronously)."""
@@ -415,6 +476,8 @@ def main():
     ap.add_argument("--slice", type=int, default=0)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the multi-seed ensemble measurement")
+    ap.add_argument("--ensemble-only", action="store_true", help="only the ensemble measurement (its own line)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1308_2144_amd", "tune_cache.txt"),
                     help="autotuner cache of the batched form ('' for none: tune every run)")
     ap.add_argument("--batch-only", action="store_true", help="only the batched measurement (its own line)")
@@ -435,6 +498,9 @@ def main():
         return
     if args.batch_only:
         print(json.dumps({"batched": bench_batch(args, torch, hb)}), flush=True)
+        return
+    if args.ensemble_only:
+        print(json.dumps({"ensemble": bench_ensemble(args, torch, hb)}), flush=True)
         return
     w = WORKLOADS[args.workload]
     off, idx = make_graph(w)
@@ -533,6 +599,10 @@ def main():
     if not args.no_batch:
         log("batched form ...")
         out["batched"] = bench_batch(args, torch, hb)
+        torch.cuda.empty_cache()
+    if not args.no_ensemble:
+        log("multi-seed ensemble ...")
+        out["ensemble"] = bench_ensemble(args, torch, hb)
         torch.cuda.empty_cache()
     if not args.no_serve:
         log("serving form ...")

@@ -260,6 +260,31 @@ hb_status hb_batch_autotune(const hb_csr* graphs, int32_t k, int32_t log2m, cons
                             int32_t sample, const char* cache_path, hb_options* opt,
                             hb_tune_report* report);
 
+/* ---- Multi-seed ensembles ---------------------------------------------
+ * Sec. 5 recommends running HyperBall several times and reporting the
+ * empirical standard deviation of the results.  An ensemble context runs k
+ * independent runs on one graph at once, run i with hash seed seeds[i]: the
+ * row of node v holds the k counters (k * 2^log2m bytes; register j of run i
+ * at byte (v*k + i) * 2^log2m + j), so each arc's successor id is read once
+ * for all k runs, and every run gets its own estimator and accumulators.
+ * Run i's registers, pass count and floating-point results equal those of
+ * hb_init(seed = seeds[i]) + hb_run bit for bit.  k in {2, 4, 8, 16} and
+ * k * 2^log2m <= 256.  On an ensemble context hb_iterate / hb_run run until
+ * every seed converged (a row counts as changed if any of its counters did);
+ * hb_centralities and hb_get_accumulators give n*k values, entry v*k + i;
+ * hb_get_registers gives n*k*2^log2m bytes; hb_reset is refused. */
+hb_status hb_ensemble_init(hb_ctx** out, const hb_csr* g, int32_t log2m, const uint64_t* seeds, int32_t k,
+                           const hb_options* opt, void* stream);
+/* Restart from pass 0 with new seeds (k entries; NULL keeps them). */
+hb_status hb_ensemble_reset(hb_ctx* c, const uint64_t* seeds);
+/* Pass count of each run (k entries; -1 for a run not converged yet). */
+hb_status hb_ensemble_passes(hb_ctx* c, int32_t* passes);
+/* Per node, over the k runs: mean and empirical standard deviation
+ * (sqrt(sum_i (x_i - mean)^2 / (k - 1)), summed in run order) of one
+ * centrality, which = 0 closeness, 1 Lin, 2 harmonic, 3 coreachable size.
+ * mean and sd hold n doubles (either may be NULL). */
+hb_status hb_ensemble_summary(hb_ctx* c, int32_t which, double* mean, double* sd, int32_t dst_on_device);
+
 /* ---- Serving form: a request loop over resident engines ----------------
  * A server owns one multi-graph engine per log2m in [4, 8] (made on first
  * use) and a thread that runs them.  A request is one centrality query: a

@@ -17,6 +17,10 @@ Parity status of every function (pins live in ``tests/test_oracle_*.py``):
   accumulators on cycles, paths, stars, complete graphs in the exact regime.
 * ``node``                   - pinned: agrees with ``run`` and with closed forms.
 * ``finalize``               - pinned: closed forms on the same graphs.
+* ``ensemble``               - K independent runs (Sec. 5: several runs of
+  HyperBall), one ``run`` + ``finalize`` per seed; pinned through ``run``.
+* ``ensemble_summary``       - pinned: numpy's mean and std (ddof=1), and
+  closed forms (equal values, two values, arithmetic progressions).
 """
 from __future__ import annotations
 
@@ -173,3 +177,34 @@ def node(offsets, indices, b: int, seed: int, x: int, radius: int = -1):
     if rc != 0:
         raise RuntimeError("oracle node evaluation failed")
     return dict(regs=regs, S=S.value, H=H.value, last_change=last.value, ecc=ecc.value)
+
+
+def ensemble(offsets, indices, b: int, seeds, max_passes: int = 0):
+    """K independent runs, one per hash seed (Sec. 5 suggests repeating the
+    computation and reporting the spread).  Returns a list of run dicts with
+    the finalize() outputs merged in."""
+    out = []
+    for sd in seeds:
+        r = run(offsets, indices, b, int(sd), max_passes=max_passes)
+        r.update(finalize(r["regs"], b, r["S"], r["H"]))
+        out.append(r)
+    return out
+
+
+def ensemble_summary(values):
+    """Mean and empirical standard deviation over runs of per-node values
+    (array (n, K)): mean = (x_0 + x_1 + ... + x_{K-1}) / K summed in run
+    order, sd = sqrt(sum_k (x_k - mean)^2 / (K - 1)), the squares also summed
+    in run order."""
+    x = np.asarray(values, dtype=np.float64)
+    K = x.shape[1]
+    m = x[:, 0].copy()
+    for k in range(1, K):
+        m = m + x[:, k]
+    m = m / float(K)
+    q = np.zeros_like(m)
+    for k in range(K):
+        d = x[:, k] - m
+        q = q + d * d
+    sd = np.sqrt(q / float(K - 1)) if K > 1 else np.zeros_like(m)
+    return m, sd

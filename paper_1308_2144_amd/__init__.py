@@ -130,6 +130,10 @@ def _declare(L):
         "hb_batch_reset": (ctypes.c_int, [vp, vp]),
         "hb_batch_graph": (ctypes.c_int, [vp, i32, P(hb_graph_info)]),
         "hb_batch_passes": (ctypes.c_int, [vp, vp]),
+        "hb_ensemble_init": (ctypes.c_int, [P(vp), P(hb_csr), i32, vp, i32, P(hb_options), vp]),
+        "hb_ensemble_reset": (ctypes.c_int, [vp, vp]),
+        "hb_ensemble_passes": (ctypes.c_int, [vp, vp]),
+        "hb_ensemble_summary": (ctypes.c_int, [vp, i32, vp, vp, i32]),
         "hb_batch_autotune": (ctypes.c_int, [vp, i32, i32, vp, i32, ctypes.c_char_p, P(hb_options),
                                              P(hb_tune_report)]),
         "hb_serve_default_config": (None, [P(hb_serve_config)]),
@@ -193,11 +197,9 @@ def default_options(**kw) -> hb_options:
 
 # --- one-to-one wrappers of the C ABI ------------------------------------------
 
-def hb_init(offsets, indices, log2m: int, seed: int, options: hb_options | None = None,
-            stream=None):
-    """Returns (ctx handle, keepalive tuple).  offsets: int32/int64; indices int32.
-
-    numpy inputs are host memory (copied); torch CUDA tensors are borrowed."""
+def _csr(offsets, indices):
+    """hb_csr for numpy (host, copied by the library) or torch CUDA (device,
+    borrowed) arrays, and the arrays to keep alive."""
     dev = _is_torch(offsets)
     if dev != _is_torch(indices):
         raise TypeError("offsets and indices must both be numpy arrays or both torch tensors")
@@ -221,11 +223,49 @@ def hb_init(offsets, indices, log2m: int, seed: int, options: hb_options | None 
         bits = 64 if offsets.dtype == np.int64 else 32
         g = hb_csr(n, indices.shape[0], offsets.ctypes.data, bits,
                    indices.ctypes.data if indices.size else None, 0)
+    return g, (offsets, indices)
+
+
+def hb_init(offsets, indices, log2m: int, seed: int, options: hb_options | None = None,
+            stream=None):
+    """Returns (ctx handle, keepalive tuple).  offsets: int32/int64; indices int32.
+
+    numpy inputs are host memory (copied); torch CUDA tensors are borrowed."""
+    g, keep = _csr(offsets, indices)
     ctx = ctypes.c_void_p()
     opt = ctypes.byref(options) if options is not None else None
     _check(lib().hb_init(ctypes.byref(ctx), ctypes.byref(g), int(log2m), int(seed), opt,
                          ctypes.c_void_p(stream) if stream else None))
-    return ctx, (offsets, indices)
+    return ctx, keep
+
+
+def hb_ensemble_init(offsets, indices, log2m: int, seeds, options: hb_options | None = None, stream=None):
+    g, keep = _csr(offsets, indices)
+    sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+    ctx = ctypes.c_void_p()
+    opt = ctypes.byref(options) if options is not None else None
+    _check(lib().hb_ensemble_init(ctypes.byref(ctx), ctypes.byref(g), int(log2m), sd.ctypes.data, sd.shape[0], opt,
+                                  ctypes.c_void_p(stream) if stream else None))
+    return ctx, keep + (sd,)
+
+
+def hb_ensemble_reset(ctx, seeds=None):
+    sd = None if seeds is None else np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+    _check(lib().hb_ensemble_reset(ctx, None if sd is None else sd.ctypes.data))
+
+
+def hb_ensemble_passes(ctx, k: int) -> np.ndarray:
+    out = np.empty(k, dtype=np.int32)
+    _check(lib().hb_ensemble_passes(ctx, out.ctypes.data))
+    return out
+
+
+CENTRALITY_INDEX = {"closeness": 0, "lin": 1, "harmonic": 2, "coreach": 3}
+
+
+def hb_ensemble_summary(ctx, which, mean, sd, dst_on_device: bool):
+    w = CENTRALITY_INDEX[which] if isinstance(which, str) else int(which)
+    _check(lib().hb_ensemble_summary(ctx, w, _ptr(mean), _ptr(sd), int(bool(dst_on_device))))
 
 
 def hb_reset(ctx, seed: int):
@@ -657,3 +697,73 @@ class Server:
 
     def __exit__(self, *exc):
         self.stop()
+
+
+class Ensemble:
+    """k HyperBall runs with different hash seeds on one graph in one context
+    (see hb_ensemble_init in include/hb.h).  Per-run outputs have shape
+    (n, k); summary() gives the per-node mean and empirical standard
+    deviation over the runs."""
+
+    def __init__(self, offsets, indices, log2m: int, seeds, *, stream=None, **options):
+        self.log2m = int(log2m)
+        self.p = 1 << self.log2m
+        self.k = len(seeds)
+        opt = default_options(**options)
+        self._ctx, self._keep = hb_ensemble_init(offsets, indices, log2m, seeds, opt, stream)
+        self.n = (offsets.numel() if _is_torch(offsets) else len(offsets)) - 1
+
+    def close(self):
+        if self._ctx is not None:
+            hb_free(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def run(self, max_passes: int = 0) -> int:
+        return hb_run(self._ctx, max_passes)
+
+    def iterate(self) -> int:
+        return hb_iterate(self._ctx)
+
+    def reset(self, seeds=None):
+        hb_ensemble_reset(self._ctx, seeds)
+
+    def passes(self) -> np.ndarray:
+        return hb_ensemble_passes(self._ctx, self.k)
+
+    def registers(self) -> np.ndarray:
+        """(n, k, p) bytes: run i's counter of node v at [v, i]."""
+        out = np.empty((max(self.n, 1), self.k, self.p), dtype=np.uint8)
+        hb_get_registers(self._ctx, out, False)
+        return out[: self.n]
+
+    def accumulators(self):
+        S = np.empty((max(self.n, 1), self.k))
+        H = np.empty((max(self.n, 1), self.k))
+        hb_get_accumulators(self._ctx, S, H, False)
+        return S[: self.n], H[: self.n]
+
+    def centralities(self):
+        outs = [np.empty((max(self.n, 1), self.k)) for _ in range(4)]
+        hb_centralities(self._ctx, *outs, False)
+        return dict(zip(("closeness", "lin", "harmonic", "coreach"), (o[: self.n] for o in outs)))
+
+    def summary(self, which="harmonic"):
+        mean = np.empty(max(self.n, 1))
+        sd = np.empty(max(self.n, 1))
+        hb_ensemble_summary(self._ctx, which, mean, sd, False)
+        return mean[: self.n], sd[: self.n]
+
+    def stats(self) -> dict:
+        return hb_stats(self._ctx)

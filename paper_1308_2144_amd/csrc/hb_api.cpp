@@ -58,6 +58,7 @@ void release(hb_ctx* c) {
   (void)hipFree(c->blk_graph);
   (void)hipFree(c->ctl);
   (void)hipFree(c->arena_tmp);
+  (void)hipFree(c->seeds_dev);
   if (c->ctl_host) (void)hipHostFree(c->ctl_host);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -152,6 +153,15 @@ hb_status do_reset(hb_ctx* c, uint64_t seed) {
     HB_HIP(hipStreamSynchronize(c->stream));  // ctl_host is reused by the next readback
     return HB_OK;
   }
+  if (c->n_seeds > 1) {
+    std::fill(c->seed_passes.begin(), c->seed_passes.end(), -1);
+    HB_HIP(hipMemcpyAsync(c->seeds_dev, c->seeds.data(), sizeof(uint64_t) * c->seeds.size(), hipMemcpyHostToDevice,
+                          c->stream));
+    HB_HIP(hb::launch_init_ensemble(c->b_seed, c->seg_log, c->n, c->seeds_dev, c->cnt[0], c->cnt[1], c->S, c->H,
+                                    c->E, c->lc, c->alpha_pp, c->stream));
+    HB_HIP(hipStreamSynchronize(c->stream));  // the seed upload reads host memory
+    return HB_OK;
+  }
   HB_HIP(hb::launch_init_nodes(c->b, c->n, seed, c->cnt[0], c->cnt[1], c->S, c->H, c->E, c->lc,
                                c->alpha_pp, c->stream));
   return HB_OK;
@@ -161,8 +171,9 @@ hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, co
                     void* stream, const std::vector<int32_t>* blk_graph = nullptr) {
   c->n = g->n;
   c->m = g->m;
-  c->b = log2m;
-  c->p = 1 << log2m;
+  c->b = log2m + c->seg_log;  // row width (one counter, or an ensemble's K counters)
+  c->p = 1 << c->b;
+  c->b_seed = log2m;
   c->stream = reinterpret_cast<hipStream_t>(stream);
   if (opt)
     c->opt = *opt;
@@ -269,10 +280,12 @@ hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, co
     if (c->opt.slice && c->p <= 256 && dmalloc(&c->dmask[i], (size_t)n) != hipSuccess)
       return fail(HB_ENOMEM, "cannot allocate slice masks");
   }
-  if (dmalloc(&c->S, (size_t)n) != hipSuccess || dmalloc(&c->H, (size_t)n) != hipSuccess ||
-      dmalloc(&c->E, (size_t)n) != hipSuccess)
+  const size_t nk = (size_t)n * (size_t)c->n_seeds;
+  if (dmalloc(&c->S, nk) != hipSuccess || dmalloc(&c->H, nk) != hipSuccess || dmalloc(&c->E, nk) != hipSuccess)
     return fail(HB_ENOMEM, "cannot allocate accumulators");
-  HB_HIP(dmalloc(&c->lc, (size_t)c->p + 1));
+  const int ps = 1 << c->b_seed;  // registers per counter
+  HB_HIP(dmalloc(&c->lc, (size_t)ps + 1));
+  if (c->n_seeds > 1) HB_HIP(dmalloc(&c->seeds_dev, (size_t)c->n_seeds));
   HB_HIP(dmalloc(&c->partial, (size_t)c->n_items * (size_t)c->p));
   HB_HIP(dmalloc(&c->stats, (size_t)2 * hb::STAT_SLOTS * hb::STAT_K));
   HB_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->stats_host),
@@ -280,9 +293,9 @@ hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, co
   for (int i = 0; i < 4; ++i) HB_HIP(hipEventCreate(&c->ev[i]));
 
   // Estimator constants: alpha_p p^2 and the linear-counting table p ln(p/V).
-  c->alpha_pp = (alpha_for(c->p) * (double)c->p) * (double)c->p;
-  std::vector<double> lc((size_t)c->p + 1, 0.0);
-  for (int V = 1; V <= c->p; ++V) lc[(size_t)V] = (double)c->p * std::log((double)c->p / (double)V);
+  c->alpha_pp = (alpha_for(ps) * (double)ps) * (double)ps;
+  std::vector<double> lc((size_t)ps + 1, 0.0);
+  for (int V = 1; V <= ps; ++V) lc[(size_t)V] = (double)ps * std::log((double)ps / (double)V);
   HB_HIP(hipMemcpyAsync(c->lc, lc.data(), sizeof(double) * lc.size(), hipMemcpyHostToDevice, c->stream));
   if (blk_graph) {
     // Multi-graph context: per-graph state, block map and device pass control.
@@ -478,6 +491,7 @@ hb_status hb_init(hb_ctx** out, const hb_csr* g, int32_t log2m, uint64_t seed, c
 hb_status hb_reset(hb_ctx* c, uint64_t seed) {
   hb_status st = check_ctx(c);
   if (st != HB_OK) return st;
+  if (c->n_seeds > 1) return fail(HB_EINVAL, "ensemble contexts restart with hb_ensemble_reset");
   st = do_reset(c, seed);
   if (st != HB_OK) c->failed = true;
   return st;
@@ -508,6 +522,8 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
   hb_pass_info info{};
   if (c->n == 0) {
     c->hist.push_back(info);
+    for (auto& sp : c->seed_passes)
+      if (sp < 0) sp = c->t + 1;
     c->t += 1;
     c->converged = true;
     c->last_nmod = 0;
@@ -568,6 +584,7 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
   a.epoch = c->t + 1;
   a.mode = mode;
   a.qdense = c->opt.qdense ? 1 : 0;
+  a.seg_lanes = (1 << c->b_seed) / 16;
   const bool timing = c->opt.timing != 0;
   hipError_t e = hipSuccess;
   if (timing) e = hipEventRecord(c->ev[0], c->stream);
@@ -589,8 +606,14 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
     return fail(HB_EDEVICE, std::string("pass ") + std::to_string(c->t) + ": " + hipGetErrorString(e));
   }
   unsigned long long sum[hb::STAT_K] = {};
-  for (int s = 0; s < hb::STAT_SLOTS; ++s)
-    for (int k = 0; k < hb::STAT_K; ++k) sum[k] += c->stats_host[s * hb::STAT_K + k];
+  unsigned long long seeds_changed = 0;
+  for (int s = 0; s < hb::STAT_SLOTS; ++s) {
+    for (int k = 0; k < hb::STAT_SEEDS; ++k) sum[k] += c->stats_host[s * hb::STAT_K + k];
+    seeds_changed |= c->stats_host[s * hb::STAT_K + hb::STAT_SEEDS];
+  }
+  // A seed's run ends with its first pass that changes none of its counters.
+  for (int k = 0; k < c->n_seeds && c->n_seeds > 1; ++k)
+    if (c->seed_passes[(size_t)k] < 0 && !((seeds_changed >> k) & 1ull)) c->seed_passes[(size_t)k] = c->t + 1;
   info.counters_gathered = (int64_t)sum[0];
   info.rows_loaded = (int64_t)sum[1];
   info.rows_written = (int64_t)sum[2];
@@ -648,12 +671,13 @@ hb_status hb_centralities(hb_ctx* c, double* closeness, double* lin, double* har
   if (c->n == 0) return HB_OK;
   // Single graphs finalise straight into device destinations; batched
   // contexts always go through the arena-layout staging below and are packed.
+  const int64_t nk = c->n * c->n_seeds;  // values per output (ensembles: K per node)
   if (dst_on_device && c->n_graphs == 0) {
-    HB_HIP(hb::launch_finalize(c->n, c->S, c->H, c->E, closeness, lin, harmonic, coreach, c->stream));
+    HB_HIP(hb::launch_finalize(nk, c->S, c->H, c->E, closeness, lin, harmonic, coreach, c->stream));
     HB_HIP(hipStreamSynchronize(c->stream));
     return HB_OK;
   }
-  const size_t n = (size_t)c->n;
+  const size_t n = (size_t)nk;
   if (!c->out_tmp) {
     if (dmalloc(&c->out_tmp, 4 * n) != hipSuccess) return fail(HB_ENOMEM, "cannot allocate output staging");
   }
@@ -676,7 +700,7 @@ hb_status hb_centralities(hb_ctx* c, double* closeness, double* lin, double* har
     HB_HIP(hipStreamSynchronize(c->stream));
     return HB_OK;
   }
-  HB_HIP(hb::launch_finalize(c->n, c->S, c->H, c->E, h[0] ? d[0] : nullptr, h[1] ? d[1] : nullptr,
+  HB_HIP(hb::launch_finalize(nk, c->S, c->H, c->E, h[0] ? d[0] : nullptr, h[1] ? d[1] : nullptr,
                              h[2] ? d[2] : nullptr, h[3] ? d[3] : nullptr, c->stream));
   for (int i = 0; i < 4; ++i)
     if (h[i]) HB_HIP(hipMemcpyAsync(h[i], d[i], sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
@@ -717,7 +741,7 @@ hb_status hb_get_registers(hb_ctx* c, uint8_t* dst, int32_t dst_on_device) {
 hb_status hb_get_accumulators(hb_ctx* c, double* S, double* H, int32_t dst_on_device) {
   hb_status st = check_ctx(c);
   if (st != HB_OK) return st;
-  const size_t bytes = sizeof(double) * (size_t)c->n;
+  const size_t bytes = sizeof(double) * (size_t)c->n * (size_t)c->n_seeds;
   if (bytes == 0) return HB_OK;
   if (c->n_graphs > 0) {
     if (S) {
@@ -743,7 +767,7 @@ hb_status hb_stats(hb_ctx* c, hb_stats_t* s) {
   if (!c || !s) return fail(HB_EINVAL, "NULL argument");
   s->n = c->n;
   s->m = c->m;
-  s->log2m = c->b;
+  s->log2m = c->b_seed;
   s->passes = c->t;
   s->converged = c->converged ? 1 : 0;
   s->last_modified = c->last_nmod;
@@ -885,6 +909,90 @@ hb_status hb_batch_passes(hb_ctx* c, int32_t* passes) {
   HB_HIP(hipMemcpyAsync(gh.data(), c->graphs, sizeof(hb::GraphDev) * gh.size(), hipMemcpyDeviceToHost, c->stream));
   HB_HIP(hipStreamSynchronize(c->stream));
   for (size_t i = 0; i < gh.size(); ++i) passes[i] = gh[i].done ? gh[i].passes : -1;
+  return HB_OK;
+}
+
+hb_status hb_ensemble_init(hb_ctx** out, const hb_csr* g, int32_t log2m, const uint64_t* seeds, int32_t k,
+                           const hb_options* opt, void* stream) {
+  if (!out) return fail(HB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!seeds) return fail(HB_EINVAL, "seeds is NULL");
+  if (k < 2 || k > 16 || (k & (k - 1)) != 0) return fail(HB_EINVAL, "ensembles need k in {2, 4, 8, 16}");
+  int seg_log = 0;
+  while ((1 << seg_log) < k) ++seg_log;
+  if (log2m < 4 || log2m + seg_log > 8) return fail(HB_EINVAL, "ensembles need log2m >= 4 and k * 2^log2m <= 256");
+  if (!g) return fail(HB_EINVAL, "graph is NULL");
+  if (g->n < 0 || g->m < 0) return fail(HB_EINVAL, "negative n or m");
+  if (g->n > 0x7fffffffLL) return fail(HB_EINVAL, "n must fit int32 node ids");
+  if (g->offsets_bits != 32 && g->offsets_bits != 64) return fail(HB_EINVAL, "offsets_bits must be 32 or 64");
+  if (g->offsets_bits == 32 && g->m > 0x7fffffffLL) return fail(HB_EINVAL, "m too large for int32 offsets");
+  if (!g->offsets) return fail(HB_EINVAL, "offsets is NULL");
+  if (g->m > 0 && !g->indices) return fail(HB_EINVAL, "indices is NULL");
+  if (!g->on_device) {
+    const bool o64 = g->offsets_bits == 64;
+    const int64_t first = o64 ? static_cast<const int64_t*>(g->offsets)[0] : static_cast<const int32_t*>(g->offsets)[0];
+    const int64_t last =
+        o64 ? static_cast<const int64_t*>(g->offsets)[g->n] : static_cast<const int32_t*>(g->offsets)[g->n];
+    if (first != 0 || last != g->m) return fail(HB_EINVAL, "offsets must start at 0 and end at m");
+  }
+  hb_ctx* c = new (std::nothrow) hb_ctx();
+  if (!c) return fail(HB_ENOMEM, "cannot allocate context");
+  c->n_seeds = k;
+  c->seg_log = seg_log;
+  c->seeds.assign(seeds, seeds + k);
+  c->seed_passes.assign((size_t)k, -1);
+  const hb_status st = init_impl(c, g, log2m, 0, opt, stream);
+  if (st != HB_OK) {
+    const std::string msg = g_err;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    release(c);
+    g_err = msg;
+    return st;
+  }
+  *out = c;
+  return HB_OK;
+}
+
+hb_status hb_ensemble_reset(hb_ctx* c, const uint64_t* seeds) {
+  hb_status st = check_ctx(c);
+  if (st != HB_OK) return st;
+  if (c->n_seeds < 2) return fail(HB_EINVAL, "not an ensemble context");
+  if (seeds) c->seeds.assign(seeds, seeds + c->n_seeds);
+  st = do_reset(c, 0);
+  if (st != HB_OK) c->failed = true;
+  return st;
+}
+
+hb_status hb_ensemble_passes(hb_ctx* c, int32_t* passes) {
+  hb_status st = check_ctx(c);
+  if (st != HB_OK) return st;
+  if (!passes) return fail(HB_EINVAL, "passes is NULL");
+  if (c->n_seeds < 2) return fail(HB_EINVAL, "not an ensemble context");
+  for (int k = 0; k < c->n_seeds; ++k) passes[k] = c->seed_passes[(size_t)k];
+  return HB_OK;
+}
+
+hb_status hb_ensemble_summary(hb_ctx* c, int32_t which, double* mean, double* sd, int32_t dst_on_device) {
+  hb_status st = check_ctx(c);
+  if (st != HB_OK) return st;
+  if (c->n_seeds < 2) return fail(HB_EINVAL, "not an ensemble context");
+  if (which < 0 || which > 3) return fail(HB_EINVAL, "which must be 0 (closeness), 1 (Lin), 2 (harmonic) or 3 (coreachable size)");
+  if (c->n == 0 || (!mean && !sd)) return HB_OK;
+  if (dst_on_device) {
+    HB_HIP(hb::launch_ensemble_summary(c->n, c->n_seeds, which, c->S, c->H, c->E, mean, sd, c->stream));
+    HB_HIP(hipStreamSynchronize(c->stream));
+    return HB_OK;
+  }
+  const size_t n = (size_t)c->n;
+  if (!c->out_tmp) {
+    if (dmalloc(&c->out_tmp, 4 * n * (size_t)c->n_seeds) != hipSuccess)
+      return fail(HB_ENOMEM, "cannot allocate output staging");
+  }
+  HB_HIP(hb::launch_ensemble_summary(c->n, c->n_seeds, which, c->S, c->H, c->E, mean ? c->out_tmp : nullptr,
+                                     sd ? c->out_tmp + n : nullptr, c->stream));
+  if (mean) HB_HIP(hipMemcpyAsync(mean, c->out_tmp, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  if (sd) HB_HIP(hipMemcpyAsync(sd, c->out_tmp + n, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  HB_HIP(hipStreamSynchronize(c->stream));
   return HB_OK;
 }
 

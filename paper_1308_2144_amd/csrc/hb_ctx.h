@@ -43,7 +43,15 @@ inline double alpha_for(int p) {
 
 struct hb_ctx {
   int64_t n = 0, m = 0;
-  int b = 0, p = 0;
+  int b = 0, p = 0;              // row width: p = 2^b bytes
+  // Multi-seed ensembles: a row holds n_seeds = 2^seg_log counters of
+  // 2^b_seed registers each (otherwise n_seeds = 1 and b_seed = b).
+  int32_t n_seeds = 1;
+  int seg_log = 0;
+  int b_seed = 0;
+  std::vector<uint64_t> seeds;
+  uint64_t* seeds_dev = nullptr;
+  std::vector<int32_t> seed_passes;  // pass count of each seed once converged, else -1
   uint64_t seed = 0;
   hb_options opt{};
   hipStream_t stream = nullptr;

@@ -28,8 +28,10 @@ struct HeavyItem {
 constexpr int STAT_SLOTS = 256;
 // gathered successors, rows run, rows written, rows changed, arcs scanned,
 // 16-byte slices gathered, 16-byte slices changed, arcs into changed rows
-// (the number of successors the next pass would gather with edge skipping)
-constexpr int STAT_K = 8;
+// (the number of successors the next pass would gather with edge skipping),
+// and (OR, not a sum) the mask of ensemble seeds with a changed counter
+constexpr int STAT_K = 9;
+constexpr int STAT_SEEDS = 8;
 
 // Reverse-CSR entries handled by one push item.
 constexpr int PUSH_CHUNK = 2048;
@@ -114,6 +116,10 @@ struct PassArgs {
   int32_t epoch;
   int32_t mode;                      // PassMode
   int32_t qdense;                    // dense passes use the queued gather too
+  // Multi-seed ensembles: a row holds K = G / seg_lanes independent counters
+  // (one per seed, seg_lanes * 16 bytes each) and E, S, H hold K values per
+  // node.  0 means one counter per row.
+  int32_t seg_lanes;
   // Multi-graph contexts (null otherwise): graph of each 64-node block, the
   // per-graph state, and the device pass control; with ctl set, cur/nxt,
   // mod_prev/mod_cur, mode, epoch and the stats halves are taken from ctl
@@ -132,6 +138,14 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_init_nodes(int log2m, int64_t n, uint64_t seed, uint8_t* cur, uint8_t* nxt,
                              double* S, double* H, double* E, const double* lc, double alpha_pp,
                              hipStream_t s);
+// Ensemble initialisation: rows of K = 2^seg_log counters of p = 2^log2m
+// registers, counter k of node v hashing v with seeds[k] (device array).
+hipError_t launch_init_ensemble(int log2m, int seg_log, int64_t n, const uint64_t* seeds, uint8_t* cur, uint8_t* nxt,
+                                double* S, double* H, double* E, const double* lc, double alpha_pp, hipStream_t s);
+// Per node, the mean and empirical standard deviation over the K seeds of one
+// centrality (0 closeness, 1 Lin, 2 harmonic, 3 coreachable size).
+hipError_t launch_ensemble_summary(int64_t n, int k, int which, const double* S, const double* H, const double* E,
+                                   double* mean, double* sd, hipStream_t s);
 // Multi-graph initialisation of arena nodes [v0, v1): node v hashes its
 // graph-local id with its graph's seed; padding rows get empty counters.
 hipError_t launch_init_arena(int log2m, int64_t v0, int64_t v1, const int32_t* blk_graph,

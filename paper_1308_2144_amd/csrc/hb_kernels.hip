@@ -240,6 +240,7 @@ __device__ __forceinline__ bool bit_of(const uint64_t* bm, int64_t v) {
 // Per-wavefront work counters (summed over lanes before the atomics).
 struct Counts {
   uint32_t gath, load, write, chg, arcs, slices, sch, pairs;
+  uint32_t seeds;  // ensembles: OR of the seeds whose counter changed
 };
 
 // own_mod: the row's counter changed in the previous pass (so the next buffer
@@ -440,13 +441,23 @@ struct RowPre {
   double e, s, h;
 };
 
-template <int B>
+template <int B, bool ENS = false>
 __device__ __forceinline__ RowPre preload(const PassArgs& A, int64_t row, int gl) {
   constexpr int P = 1 << B;
+  constexpr int G = P / 16;
   RowPre r;
   r.own = ld_stream(reinterpret_cast<const uint4*>(A.cur + (size_t)row * P + (size_t)gl * 16));
   r.e = r.s = r.h = 0.0;
-  if (gl == 0) {
+  if constexpr (ENS) {
+    // first lane of each seed's counter: its cached estimate and accumulators
+    const int gs = A.seg_lanes;
+    if ((gl & (gs - 1)) == 0) {
+      const int64_t i = row * (G / gs) + gl / gs;
+      r.e = ld_stream(A.E + i);
+      r.s = ld_stream(A.S + i);
+      r.h = ld_stream(A.H + i);
+    }
+  } else if (gl == 0) {
     r.e = ld_stream(A.E + row);
     r.s = ld_stream(A.S + row);
     r.h = ld_stream(A.H + row);
@@ -456,8 +467,10 @@ __device__ __forceinline__ RowPre preload(const PassArgs& A, int64_t row, int gl
 
 // Completes row `row` for a group of G lanes: a = own U gathered, write-back
 // rule, change detection, the fused estimator/accumulator, the change bit
-// and the mask of changed slices.  Returns whether the counter changed.
-template <int B, bool MG>
+// and the mask of changed slices.  In an ensemble row (ENS) every seed's
+// counter gets its own estimator and accumulators, and the row's change bit
+// is set if any of them changed.  Returns whether the row changed.
+template <int B, bool MG, bool ENS = false>
 __device__ __forceinline__ bool finish_row(const PassArgs& A, int64_t row, uint4 acc, bool got,
                                            const RowPre& pre, bool own_mod, int gl, int grp,
                                            Counts& c) {
@@ -477,7 +490,39 @@ __device__ __forceinline__ bool finish_row(const PassArgs& A, int64_t row, uint4
     c.sch += (uint32_t)__popc(msk);
     if (changed && A.roff) c.pairs += (uint32_t)(A.roff[row + 1] - A.roff[row]);
   }
-  if (changed) {
+  if constexpr (ENS) {
+    const int gs = A.seg_lanes;  // lanes per seed's counter
+    const int seg = gl / gs;
+    if (gl == 0 && changed)
+      for (int k = 0; k < G / gs; ++k)
+        if ((msk >> (k * gs)) & ((1u << gs) - 1u)) c.seeds |= 1u << k;
+    if ((msk >> (seg * gs)) & ((1u << gs) - 1u)) {  // uniform over the lanes of one counter
+      const Parts pr = reg_parts(a);
+      double big = pr.big, small = pr.small;
+      int V = pr.zeros;
+#pragma unroll
+      for (int o = 1; o < G; o <<= 1) {
+        if (o < gs) {
+          big += __shfl_xor(big, o);
+          small += __shfl_xor(small, o);
+          V += __shfl_xor(V, o);
+        }
+      }
+      if ((gl & (gs - 1)) == 0) {
+        const double En = estimate(big, small, V, A.alpha_pp, (double)(16 * gs), A.lc);
+        const double delta = En - pre.e;
+        const double d = row_d<MG>(A, row);
+        const int64_t i = row * (G / gs) + seg;
+        st_stream(A.S + i, pre.s + d * delta);
+        st_stream(A.H + i, pre.h + delta / d);
+        st_stream(A.E + i, En);
+      }
+    }
+    if (changed && gl == 0) {
+      if (A.dmask_cur) A.dmask_cur[row] = (uint16_t)msk;
+      atomicOr(A.mod_cur + (row >> 6), 1ull << (row & 63));
+    }
+  } else if (changed) {
     const Parts pr = reg_parts(a);
     double big = pr.big, small = pr.small;
     int V = pr.zeros;
@@ -501,13 +546,16 @@ __device__ __forceinline__ bool finish_row(const PassArgs& A, int64_t row, uint4
   return changed;
 }
 
+template <bool ENS = false>
 __device__ __forceinline__ void add_stats(unsigned long long* st, const Counts& c) {
-  const unsigned long long v[STAT_K] = {c.gath, c.load, c.write, c.chg, c.arcs, c.slices, c.sch, c.pairs};
+  const unsigned long long v[STAT_SEEDS] = {c.gath, c.load, c.write, c.chg, c.arcs, c.slices, c.sch, c.pairs};
 #pragma unroll
-  for (int k = 0; k < STAT_K; ++k)
+  for (int k = 0; k < STAT_SEEDS; ++k)
     if (v[k]) atomicAdd(st + k, v[k]);
+  if (ENS && c.seeds) atomicOr(st + STAT_SEEDS, (unsigned long long)c.seeds);
 }
 
+template <bool ENS = false>
 __device__ __forceinline__ void flush_counts(const PassArgs& A, Counts c, int64_t slot, int lane) {
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -519,15 +567,16 @@ __device__ __forceinline__ void flush_counts(const PassArgs& A, Counts c, int64_
     c.slices += __shfl_xor(c.slices, o);
     c.sch += __shfl_xor(c.sch, o);
     c.pairs += __shfl_xor(c.pairs, o);
+    if (ENS) c.seeds |= __shfl_xor(c.seeds, o);
   }
-  if (lane == 0) add_stats(A.stats + (slot & (STAT_SLOTS - 1)) * STAT_K, c);
+  if (lane == 0) add_stats<ENS>(A.stats + (slot & (STAT_SLOTS - 1)) * STAT_K, c);
 }
 
 __device__ __forceinline__ uint64_t lanes_below(int lane) { return (1ull << lane) - 1ull; }
 
 // 64 consecutive entries of the light-row list per wavefront; entry
 // q*W + grp goes to lane group grp in round q.
-template <int B, bool Q, bool MG>
+template <int B, bool Q, bool MG, bool ENS = false>
 __device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, int64_t lw, int lane) {
   constexpr int P = 1 << B;
   constexpr int G = P / 16;
@@ -556,7 +605,7 @@ __device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, int64_t 
       const int64_t rd = __shfl(deg, rl);
       if ((needs >> rl) & 1ull) {
         const bool rmod = ((mods >> rl) & 1ull) != 0ull;
-        const RowPre pre = preload<B>(A, rrow, gl);
+        const RowPre pre = preload<B, ENS>(A, rrow, gl);
         bool got = false;
         uint4 acc;
         if constexpr (Q)
@@ -564,16 +613,16 @@ __device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, int64_t 
         else
           acc = gather<B>(A, rs, rs + rd, 1, gl, got, c);
         if (gl == 0) c.arcs += (uint32_t)rd;
-        finish_row<B, MG>(A, rrow, acc, got, pre, rmod, gl, grp, c);
+        finish_row<B, MG, ENS>(A, rrow, acc, got, pre, rmod, gl, grp, c);
       }
     }
   }
-  flush_counts(A, c, lw, lane);
+  flush_counts<ENS>(A, c, lw, lane);
 }
 
 // One medium row per wavefront: the groups share its arcs and reduce their
 // partial maxima by shuffles.
-template <int B, bool Q, bool MG>
+template <int B, bool Q, bool MG, bool ENS = false>
 __device__ __forceinline__ void medium_wave(const PassArgs& A, QEnt* qw, int64_t mi, int lane) {
   constexpr int P = 1 << B;
   constexpr int G = P / 16;
@@ -588,7 +637,7 @@ __device__ __forceinline__ void medium_wave(const PassArgs& A, QEnt* qw, int64_t
   Counts c{};
   if (need) {
     RowPre pre;
-    if (grp == 0) pre = preload<B>(A, row, gl);
+    if (grp == 0) pre = preload<B, ENS>(A, row, gl);
     bool got = false;
     uint4 acc;
     if constexpr (Q)
@@ -599,9 +648,9 @@ __device__ __forceinline__ void medium_wave(const PassArgs& A, QEnt* qw, int64_t
 #pragma unroll
     for (int o = G; o < 64; o <<= 1) acc = bmax(acc, shfl_xor4(acc, o));
     got = __ballot(got) != 0ull;
-    if (grp == 0) finish_row<B, MG>(A, row, acc, got, pre, own_mod, gl, 0, c);
+    if (grp == 0) finish_row<B, MG, ENS>(A, row, acc, got, pre, own_mod, gl, 0, c);
   }
-  flush_counts(A, c, mi, lane);
+  flush_counts<ENS>(A, c, mi, lane);
 }
 
 // One chunk of a heavy row per workgroup (4 wavefronts): writes the chunk's
@@ -648,7 +697,7 @@ __device__ __forceinline__ void heavy_chunk(const PassArgs& A, QEnt* qw, int64_t
 // per workgroup][light rows, 256 per workgroup].  Q selects the queued
 // gather (slice, edge and sparse passes, or dense passes on request) over
 // the direct one.
-template <int B, bool Q, bool MG>
+template <int B, bool Q, bool MG, bool ENS = false>
 __device__ __forceinline__ void expand_item(const PassArgs& A, QEnt* qw, int64_t b) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -662,12 +711,12 @@ __device__ __forceinline__ void expand_item(const PassArgs& A, QEnt* qw, int64_t
   const int64_t med_wgs = (A.n_medium + 3) / 4;
   if (b < med_wgs) {
     const int64_t mi = b * 4 + wave;
-    if (mi < A.n_medium) medium_wave<B, Q, MG>(A, qw, mi, lane);
+    if (mi < A.n_medium) medium_wave<B, Q, MG, ENS>(A, qw, mi, lane);
     return;
   }
   b -= med_wgs;
   const int64_t lw = b * 4 + wave;
-  if (lw * 64 < A.n_light) light_wave<B, Q, MG>(A, qw, lw, lane);
+  if (lw * 64 < A.n_light) light_wave<B, Q, MG, ENS>(A, qw, lw, lane);
 }
 
 __device__ __forceinline__ int64_t pass_items(const PassArgs& A) {
@@ -684,15 +733,15 @@ __device__ __forceinline__ bool queued_mode(const PassArgs& A) {
 #define HB_EXPAND_ATTR __launch_bounds__(256)
 #endif
 
-template <int B>
+template <int B, bool ENS = false>
 __global__ HB_EXPAND_ATTR void k_expand(PassArgs A) {
-  expand_item<B, false, false>(A, nullptr, blockIdx.x);
+  expand_item<B, false, false, ENS>(A, nullptr, blockIdx.x);
 }
 
-template <int B>
+template <int B, bool ENS = false>
 __global__ HB_EXPAND_ATTR void k_expand_q(PassArgs A) {
   __shared__ QEnt qbuf[4][QCAP];
-  expand_item<B, true, false>(A, qbuf[threadIdx.x >> 6], blockIdx.x);
+  expand_item<B, true, false, ENS>(A, qbuf[threadIdx.x >> 6], blockIdx.x);
 }
 
 // Persistent form for device-driven passes: a fixed grid whose workgroups
@@ -718,7 +767,7 @@ __global__ HB_EXPAND_ATTR void k_expand_p(PassArgs A0) {
 
 // Folds the partial counters of every heavy row into the row (one wavefront
 // per heavy row) and finishes it like any other row.
-template <int B, bool MG>
+template <int B, bool MG, bool ENS = false>
 __global__ __launch_bounds__(256) void k_merge(PassArgs A0) {
   const PassArgs A = resolve(A0);
   constexpr int P = 1 << B;
@@ -735,7 +784,7 @@ __global__ __launch_bounds__(256) void k_merge(PassArgs A0) {
   row_flags<MG>(A, hr.row, own_mod, need);
   if (!need) return;
   RowPre pre;
-  if (grp == 0) pre = preload<B>(A, hr.row, gl);
+  if (grp == 0) pre = preload<B, ENS>(A, hr.row, gl);
   uint4 acc = zero4();
   for (int64_t j = grp; j < hr.nitems; j += W)
     acc = bmax(acc, *reinterpret_cast<const uint4*>(A.partial + (size_t)(hr.item0 + j) * P +
@@ -743,8 +792,8 @@ __global__ __launch_bounds__(256) void k_merge(PassArgs A0) {
 #pragma unroll
   for (int o = G; o < 64; o <<= 1) acc = bmax(acc, shfl_xor4(acc, o));
   Counts c{};
-  if (grp == 0) finish_row<B, MG>(A, hr.row, acc, true, pre, own_mod, gl, 0, c);
-  flush_counts(A, c, h, lane);
+  if (grp == 0) finish_row<B, MG, ENS>(A, hr.row, acc, true, pre, own_mod, gl, 0, c);
+  flush_counts<ENS>(A, c, h, lane);
 }
 
 // Counters wider than 256 bytes: one workgroup per 64-row block, rows in
@@ -899,6 +948,71 @@ __global__ void k_finalize(int64_t n, const double* S, const double* H, const do
   if (clo) clo[v] = (s == 0.0) ? 0.0 : 1.0 / s;
   if (lin) lin[v] = (s == 0.0) ? 1.0 : (size * size) / s;
   if (harm) harm[v] = H[v];
+}
+
+// Ensemble initialisation: as k_init_nodes, with K = 2^seg_log counters per
+// row; thread i writes 16-byte chunk i of the rows, counter k of node v
+// hashes v with seeds[k], and E, S, H hold K values per node.
+__global__ void k_init_ensemble(int log2m, int seg_log, int64_t n, const uint64_t* seeds, uint8_t* cur, uint8_t* nxt,
+                                double* S, double* H, double* E, const double* lc, double alpha_pp) {
+  const int64_t P = (int64_t)1 << log2m;
+  const int64_t C = P / 16;                 // chunks per counter
+  const int64_t K = (int64_t)1 << seg_log;  // counters per row
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * C * K) return;
+  const int64_t v = i / (C * K);
+  const int64_t chunk = i - v * C * K;
+  const int64_t k = chunk / C;
+  const int64_t ck = chunk - k * C;
+  const uint64_t h = node_hash((uint64_t)v, seeds[k]);
+  const uint32_t j = (uint32_t)(h >> (64 - log2m));
+  const uint64_t rest = h << log2m;
+  const uint32_t r = rest == 0ull ? (uint32_t)(65 - log2m) : (uint32_t)__clzll((long long)rest) + 1u;
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
+  if ((int64_t)(j >> 4) == ck) w[(j >> 2) & 3u] = r << (8u * (j & 3u));
+  const uint4 val = make_uint4(w[0], w[1], w[2], w[3]);
+  *reinterpret_cast<uint4*>(cur + (v * K) * P + chunk * 16) = val;
+  *reinterpret_cast<uint4*>(nxt + (v * K) * P + chunk * 16) = val;
+  if (ck == 0) {
+    S[v * K + k] = 0.0;
+    H[v * K + k] = 0.0;
+    double big = (double)(P - 1), small = 0.0;
+    if (r <= 26u)
+      big += pow2neg(r);
+    else
+      small += pow2neg(r);
+    E[v * K + k] = estimate(big, small, (int)(P - 1), alpha_pp, (double)P, lc);
+  }
+}
+
+// One run's centrality `which` of entry i (0 closeness, 1 Lin, 2 harmonic,
+// 3 coreachable size), as k_finalize computes it.
+__device__ __forceinline__ double centrality_of(int which, const double* S, const double* H, const double* E,
+                                                int64_t i) {
+  const double s = S[i];
+  const double size = E[i];
+  if (which == 0) return (s == 0.0) ? 0.0 : 1.0 / s;
+  if (which == 1) return (s == 0.0) ? 1.0 : (size * size) / s;
+  if (which == 2) return H[i];
+  return size;
+}
+
+// Mean and empirical standard deviation (K - 1 in the denominator) over the
+// K seeds of a node, summing in seed order.
+__global__ void k_ensemble_summary(int64_t n, int K, int which, const double* S, const double* H, const double* E,
+                                   double* mean, double* sd) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  double m = centrality_of(which, S, H, E, v * K);
+  for (int k = 1; k < K; ++k) m = m + centrality_of(which, S, H, E, v * K + k);
+  m = m / (double)K;
+  double q = 0.0;
+  for (int k = 0; k < K; ++k) {
+    const double d = centrality_of(which, S, H, E, v * K + k) - m;
+    q = q + d * d;
+  }
+  if (mean) mean[v] = m;
+  if (sd) sd[v] = K > 1 ? sqrt(q / (double)(K - 1)) : 0.0;
 }
 
 __global__ void k_widen(const int32_t* in, int64_t* out, int64_t count) {
@@ -1229,8 +1343,63 @@ hipError_t launch_init_nodes(int log2m, int64_t n, uint64_t seed, uint8_t* cur, 
   return hipGetLastError();
 }
 
+hipError_t launch_init_ensemble(int log2m, int seg_log, int64_t n, const uint64_t* seeds, uint8_t* cur, uint8_t* nxt,
+                                double* S, double* H, double* E, const double* lc, double alpha_pp, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t threads = n * ((((int64_t)1 << log2m) / 16) << seg_log);
+  hipLaunchKernelGGL(k_init_ensemble, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, log2m, seg_log, n,
+                     seeds, cur, nxt, S, H, E, lc, alpha_pp);
+  return hipGetLastError();
+}
+
+hipError_t launch_ensemble_summary(int64_t n, int k, int which, const double* S, const double* H, const double* E,
+                                   double* mean, double* sd, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (k < 1 || k > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ensemble_summary, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, k, which, S, H, E,
+                     mean, sd);
+  return hipGetLastError();
+}
+
+// Ensemble rows (seg_lanes below the lanes of a row): expand and merge.
+hipError_t launch_pass_ens(int log2m, const PassArgs& a, hipStream_t s, hipEvent_t ev_mid) {
+  const int64_t grid = a.n_items + (a.n_medium + 3) / 4 + (a.n_light + 255) / 256;
+  const bool q = !(a.mode == MODE_FIRST || a.mode == MODE_DENSE) || a.qdense;
+  if (grid > 0) {
+    const dim3 g((unsigned)grid), t(256);
+    switch (log2m * 2 + (q ? 1 : 0)) {
+      case 10: hipLaunchKernelGGL((k_expand<5, true>), g, t, 0, s, a); break;
+      case 11: hipLaunchKernelGGL((k_expand_q<5, true>), g, t, 0, s, a); break;
+      case 12: hipLaunchKernelGGL((k_expand<6, true>), g, t, 0, s, a); break;
+      case 13: hipLaunchKernelGGL((k_expand_q<6, true>), g, t, 0, s, a); break;
+      case 14: hipLaunchKernelGGL((k_expand<7, true>), g, t, 0, s, a); break;
+      case 15: hipLaunchKernelGGL((k_expand_q<7, true>), g, t, 0, s, a); break;
+      case 16: hipLaunchKernelGGL((k_expand<8, true>), g, t, 0, s, a); break;
+      case 17: hipLaunchKernelGGL((k_expand_q<8, true>), g, t, 0, s, a); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (ev_mid) {
+    e = hipEventRecord(ev_mid, s);
+    if (e != hipSuccess) return e;
+  }
+  if (a.n_hrows > 0) {
+    const unsigned mg = (unsigned)((a.n_hrows + 3) / 4);
+    switch (log2m) {
+      case 5: hipLaunchKernelGGL((k_merge<5, false, true>), dim3(mg), dim3(256), 0, s, a); break;
+      case 6: hipLaunchKernelGGL((k_merge<6, false, true>), dim3(mg), dim3(256), 0, s, a); break;
+      case 7: hipLaunchKernelGGL((k_merge<7, false, true>), dim3(mg), dim3(256), 0, s, a); break;
+      default: hipLaunchKernelGGL((k_merge<8, false, true>), dim3(mg), dim3(256), 0, s, a); break;
+    }
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_pass(int log2m, const PassArgs& a, hipStream_t s, hipEvent_t ev_mid) {
   if (a.n_blocks == 0) return hipSuccess;
+  if (log2m <= 8 && a.seg_lanes > 0 && a.seg_lanes < (1 << log2m) / 16) return launch_pass_ens(log2m, a, s, ev_mid);
   if (log2m <= 8) {
     const int64_t grid = a.n_items + (a.n_medium + 3) / 4 + (a.n_light + 255) / 256;
     const bool q = !(a.mode == MODE_FIRST || a.mode == MODE_DENSE) || a.qdense;

@@ -98,3 +98,19 @@ def test_autotune_argument_errors():
     assert e.value.status == hb.HB_EINVAL
     L = hb.lib()
     assert L.hb_batch_autotune(None, 0, 5, None, 0, None, None, None) == hb.HB_EINVAL
+
+
+def test_ensemble_argument_errors():
+    """Refused on the host before any device work."""
+    import paper_1308_2144_amd as hb
+
+    off = np.array([0, 1, 2], dtype=np.int64)
+    idx = np.array([1, 0], dtype=np.int32)
+    for b, seeds in ((4, [1, 2, 3]), (4, list(range(32))), (6, list(range(8))), (3, [1, 2]), (9, [1, 2]),
+                     (4, [1])):
+        with pytest.raises(hb.HBError) as e:
+            hb.Ensemble(off, idx, b, seeds)
+        assert e.value.status == hb.HB_EINVAL
+    with pytest.raises(hb.HBError) as e:
+        hb.Ensemble(np.array([0, 1, 3], dtype=np.int64), idx, 4, [1, 2])    # offsets[n] != m
+    assert e.value.status == hb.HB_EINVAL

@@ -193,3 +193,36 @@ def test_invariants_on_rmat(orc, gg):
         else:
             assert nchg == 0
         prev = cur
+
+
+def test_ensemble_summary_against_numpy_and_closed_forms(orc):
+    rng = np.random.default_rng(3)
+    for K in (2, 4, 8, 16):
+        x = rng.lognormal(2.0, 1.0, size=(500, K))
+        m, sd = orc.ensemble_summary(x)
+        assert np.allclose(m, x.mean(axis=1), rtol=1e-14, atol=0)
+        assert np.allclose(sd, x.std(axis=1, ddof=1), rtol=1e-12, atol=1e-300)
+    # equal integer values (every partial sum exact): mean exact, spread exactly zero
+    x = np.repeat(rng.integers(1, 1 << 20, size=(50, 1)).astype(np.float64), 8, axis=1)
+    m, sd = orc.ensemble_summary(x)
+    assert np.array_equal(m, x[:, 0]) and np.all(sd == 0.0)
+    # two values a, b: sd = |a - b| / sqrt(2)
+    a, b = rng.lognormal(size=200), rng.lognormal(size=200)
+    m, sd = orc.ensemble_summary(np.stack([a, b], axis=1))
+    assert np.allclose(sd, np.abs(a - b) / np.sqrt(2.0), rtol=1e-14)
+    # arithmetic progression c, c+h, ..., c+(K-1)h: sd = h * sqrt(K (K+1) / 12)
+    for K in (4, 16):
+        c, h = 10.0, 0.5
+        x = (c + h * np.arange(K))[None, :].repeat(3, axis=0)
+        m, sd = orc.ensemble_summary(x)
+        assert np.allclose(m, c + h * (K - 1) / 2, rtol=1e-15)
+        assert np.allclose(sd, h * np.sqrt(K * (K + 1) / 12.0), rtol=1e-14)
+
+
+def test_ensemble_is_independent_runs(orc, gg):
+    off, idx = gg.rmat(7, 8, seed=5, transpose=True)
+    runs = orc.ensemble(off, idx, 4, [3, 9])
+    for sd, r in zip([3, 9], runs):
+        ref = orc.run(off, idx, 4, sd)
+        assert r["passes"] == ref["passes"] and np.array_equal(r["regs"], ref["regs"])
+    assert not np.array_equal(runs[0]["regs"], runs[1]["regs"])   # different seeds differ
