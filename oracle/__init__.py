@@ -17,6 +17,17 @@ Parity status of every function (pins live in ``tests/test_oracle_*.py``):
   accumulators on cycles, paths, stars, complete graphs in the exact regime.
 * ``node``                   - pinned: agrees with ``run`` and with closed forms.
 * ``finalize``               - pinned: closed forms on the same graphs.
+* ``run_ext``                - ``run`` with Sec. 6 node weights (replicas),
+  a Sec. 7 discount accumulator and the per-pass estimate trace; pinned:
+  unit weights and no discount reproduce ``run`` bit for bit, f(d) = d
+  reproduces S bit for bit, weighted distance sums and discounted sums
+  against breadth-first distances in the exact regime, the replica counter
+  against ``counter_of``.
+* ``neighbourhood``          - N(t) = correctly rounded sum over nodes of the
+  estimates after t passes (``math.fsum`` of the trace); pinned: exact-regime
+  ball sizes from breadth-first search.
+* ``distance_stats``         - average distance and interpolated effective
+  diameter from N(t); pinned: closed forms on paths and cycles.
 * ``ensemble``               - K independent runs (Sec. 5: several runs of
   HyperBall), one ``run`` + ``finalize`` per seed; pinned through ``run``.
 * ``ensemble_summary``       - pinned: numpy's mean and std (ddof=1), and
@@ -67,6 +78,8 @@ def _load():
         L.hbo_size.restype = ctypes.c_double
         L.hbo_run.argtypes = [i64, vp, vp, ci, u64, ci, vp, vp, vp, vp, vp]
         L.hbo_run.restype = ci
+        L.hbo_run_ext.argtypes = [i64, vp, vp, ci, u64, ci, vp, vp, ci, vp, vp, vp, vp, vp, i64, vp, vp]
+        L.hbo_run_ext.restype = ci
         L.hbo_finalize.argtypes = [i64, vp, ci, vp, vp, vp, vp, vp, vp]
         L.hbo_finalize.restype = None
         L.hbo_node.argtypes = [i64, vp, vp, ci, u64, i64, ci, vp, vp, vp, vp, vp]
@@ -145,6 +158,80 @@ def run(offsets, indices, b: int, seed: int, max_passes: int = 0):
         raise RuntimeError("oracle run failed")
     t = passes.value
     return dict(regs=regs[:n], S=S[:n], H=H[:n], nmod=nmod[:t].copy(), passes=t)
+
+
+def replica_item(x: int, j: int) -> int:
+    """Item of replica j of node x (Sec. 6): x for j = 0, x + j * 2^32 after."""
+    return x + (j << 32)
+
+
+def run_ext(offsets, indices, b: int, seed: int, max_passes: int = 0, weights=None, discount=None,
+            trace: bool = False):
+    """``run`` with node weights w(x) >= 1 (counter x starts as the
+    HyperLogLog of the w(x) replicas of x, Sec. 6), a discount table
+    f(1..L) (D[v] += f(t+1) * delta in pass t, f(d) = f(L) for d > L,
+    Sec. 7), and the trace of every counter's estimate after each pass.
+
+    Returns run()'s dict plus D (if discount) and etrace ((passes+1, n), if
+    trace)."""
+    o, i = _csr(offsets, indices)
+    n = o.shape[0] - 1
+    p = 1 << b
+    regs = np.zeros((max(n, 1), p), dtype=np.uint8)
+    S = np.zeros(max(n, 1))
+    H = np.zeros(max(n, 1))
+    D = np.zeros(max(n, 1))
+    cap = max_passes if max_passes > 0 else n + 2
+    nmod = np.zeros(cap + 1, dtype=np.int64)
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.int32)
+    if w is not None and (w.shape[0] != n or (n and w.min() < 1)):
+        raise ValueError("need one weight >= 1 per node")
+    f = None if discount is None else np.ascontiguousarray(discount, dtype=np.float64)
+    rows = cap + 1 if trace else 0
+    et = np.zeros((max(rows, 1), max(n, 1))) if trace else None
+    passes = ctypes.c_int(0)
+    rc = _load().hbo_run_ext(n, _p(o), _p(i), b, seed, max_passes, None if w is None else _p(w),
+                             None if f is None else _p(f), 0 if f is None else f.shape[0], _p(regs), _p(S), _p(H),
+                             _p(D), None if et is None else _p(et), rows, _p(nmod), ctypes.byref(passes))
+    if rc != 0:
+        raise RuntimeError("oracle run failed")
+    t = passes.value
+    out = dict(regs=regs[:n], S=S[:n], H=H[:n], nmod=nmod[:t].copy(), passes=t)
+    if f is not None:
+        out["D"] = D[:n]
+    if trace:
+        out["etrace"] = et[: t + 1, :n].copy()
+    return out
+
+
+def neighbourhood(etrace) -> np.ndarray:
+    """N(t) for t = 0..passes: the sum over nodes of the size estimates after
+    t passes (an estimate of the number of pairs (x, y) with y in B(x, t)),
+    correctly rounded (math.fsum)."""
+    import math
+
+    return np.array([math.fsum(row.tolist()) for row in np.asarray(etrace)])
+
+
+def distance_stats(N, alpha: float = 0.9):
+    """From the neighbourhood function N(0..T): reachable pairs at distance
+    >= 1 (N(T) - N(0)), the average distance sum_{t>=1} t (N(t) - N(t-1)) /
+    (N(T) - N(0)), and the effective diameter: the smallest t with N(t) >=
+    alpha N(T), interpolated linearly between t-1 and t.  Sums in t order."""
+    N = [float(x) for x in N]
+    T = len(N) - 1
+    pairs = N[T] - N[0]
+    num = 0.0
+    for t in range(1, T + 1):
+        num = num + float(t) * (N[t] - N[t - 1])
+    avg = num / pairs if pairs > 0 else 0.0
+    target = alpha * N[T]
+    eff = 0.0
+    for t in range(0, T + 1):
+        if N[t] >= target:
+            eff = float(t) if t == 0 else float(t - 1) + (target - N[t - 1]) / (N[t] - N[t - 1])
+            break
+    return dict(pairs=pairs, average_distance=avg, effective_diameter=eff)
 
 
 def finalize(regs: np.ndarray, b: int, S: np.ndarray, H: np.ndarray):

@@ -119,25 +119,52 @@ static void hbo_union(uint8_t* M, const uint8_t* N, int p) {
  * uncapped).  *passes receives the number of passes run, the last unchanged
  * one included.  Returns 0, or -1 on bad arguments / allocation failure.
  */
-int hbo_run(int64_t n, const int64_t* offsets, const int32_t* indices, int b, uint64_t seed,
-            int max_passes, uint8_t* regs, double* S, double* H, int64_t* nmod, int* passes) {
+/* Item of replica j of node x (Sec. 6 simulates an integer weight w(x) by
+ * w(x) distinct replicas): x itself for j = 0, x + j * 2^32 for j > 0, which
+ * no node id (< 2^31) and no other replica can equal. */
+static uint64_t replica_item(int64_t x, int64_t j) { return (uint64_t)x + ((uint64_t)j << 32); }
+
+/* Algorithm 2 to stabilisation (or max_passes passes), with the Sec. 5
+ * accumulators and, optionally:
+ *   weights  (nullable) w(x) >= 1: counter x starts as the HyperLogLog of the
+ *            w(x) replicas of x (Sec. 6), so the sizes and accumulators
+ *            count weighted nodes;
+ *   disc     (nullable) a discount table f(1..disc_len): D[v] accumulates
+ *            f(t+1) * delta in pass t (Sec. 7), f(d) = f(disc_len) beyond
+ *            the table;
+ *   etrace   (nullable) (trace_rows * n) doubles: row t receives the size
+ *            estimate of every counter after t passes (row 0: before pass 0),
+ *            for the rows the run reaches. */
+int hbo_run_ext(int64_t n, const int64_t* offsets, const int32_t* indices, int b, uint64_t seed, int max_passes,
+                const int32_t* weights, const double* disc, int disc_len, uint8_t* regs, double* S, double* H,
+                double* D, double* etrace, int64_t trace_rows, int64_t* nmod, int* passes) {
   if (n < 0 || b < 4 || b > 16) return -1;
+  if (disc && disc_len < 1) return -1;
   int p = 1 << b;
-  size_t bytes = (size_t)(n > 0 ? n : 1) * (size_t)p;
+  size_t nn = (size_t)(n > 0 ? n : 1);
+  size_t bytes = nn * (size_t)p;
   uint8_t* c = (uint8_t*)calloc(bytes, 1);
   uint8_t* next = (uint8_t*)calloc(bytes, 1);
-  double* s = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
-  double* h = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
-  if (!c || !next || !s || !h) {
-    free(c); free(next); free(s); free(h);
+  double* s = (double*)calloc(nn, sizeof(double));
+  double* h = (double*)calloc(nn, sizeof(double));
+  double* dsum = (double*)calloc(nn, sizeof(double));
+  if (!c || !next || !s || !h || !dsum) {
+    free(c); free(next); free(s); free(h); free(dsum);
     return -1;
   }
-  /* Algorithm 2: every counter starts empty and is fed its own node. */
-  for (int64_t v = 0; v < n; ++v) hbo_add(c + (size_t)v * p, b, (uint64_t)v, seed);
+  /* Algorithm 2: every counter starts empty and is fed its own node (or the
+   * node's replicas). */
+  for (int64_t v = 0; v < n; ++v) {
+    const int64_t w = weights ? weights[v] : 1;
+    for (int64_t j = 0; j < w; ++j) hbo_add(c + (size_t)v * p, b, replica_item(v, j), seed);
+  }
+  if (etrace && trace_rows > 0)
+    for (int64_t v = 0; v < n; ++v) etrace[v] = hbo_size(c + (size_t)v * p, b);
   int t = 0;
   int64_t changed;
   do {
     changed = 0;
+    const double f = disc ? disc[t + 1 <= disc_len ? t : disc_len - 1] : 0.0;
     for (int64_t v = 0; v < n; ++v) {
       uint8_t* a = next + (size_t)v * p;
       const uint8_t* cv = c + (size_t)v * p;
@@ -149,25 +176,31 @@ int hbo_run(int64_t n, const int64_t* offsets, const int32_t* indices, int b, ui
       double d = (double)(t + 1);
       s[v] = s[v] + d * delta;
       h[v] = h[v] + delta / d;
+      if (disc) dsum[v] = dsum[v] + f * delta;
       if (memcmp(a, cv, (size_t)p) != 0) ++changed;
     }
     /* Apply all pairs <v,a> at once (synchronous update). */
     uint8_t* tmp = c; c = next; next = tmp;
     if (nmod) nmod[t] = changed;
     ++t;
+    if (etrace && t < trace_rows)
+      for (int64_t v = 0; v < n; ++v) etrace[(size_t)t * nn + v] = hbo_size(c + (size_t)v * p, b);
   } while (changed != 0 && (max_passes <= 0 || t < max_passes));
   if (regs && n > 0) memcpy(regs, c, (size_t)n * p);
   if (S && n > 0) memcpy(S, s, (size_t)n * sizeof(double));
   if (H && n > 0) memcpy(H, h, (size_t)n * sizeof(double));
+  if (D && n > 0) memcpy(D, dsum, (size_t)n * sizeof(double));
   if (passes) *passes = t;
-  free(c); free(next); free(s); free(h);
+  free(c); free(next); free(s); free(h); free(dsum);
   return 0;
 }
 
-/* Sec. 3 and Sec. 5: the coreachable-set size is the final counter's size;
- * closeness = 1/sum of distances (0 with no distance mass); Lin =
- * |coreachable|^2 / sum of distances (1 with no distance mass); harmonic =
- * sum of reciprocal distances. */
+int hbo_run(int64_t n, const int64_t* offsets, const int32_t* indices, int b, uint64_t seed,
+            int max_passes, uint8_t* regs, double* S, double* H, int64_t* nmod, int* passes) {
+  return hbo_run_ext(n, offsets, indices, b, seed, max_passes, NULL, NULL, 0, regs, S, H, NULL, NULL, 0, nmod,
+                     passes);
+}
+
 void hbo_finalize(int64_t n, const uint8_t* regs, int b, const double* S, const double* H,
                   double* closeness, double* lin, double* harmonic, double* coreach) {
   int p = 1 << b;

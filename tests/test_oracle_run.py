@@ -226,3 +226,100 @@ def test_ensemble_is_independent_runs(orc, gg):
         ref = orc.run(off, idx, 4, sd)
         assert r["passes"] == ref["passes"] and np.array_equal(r["regs"], ref["regs"])
     assert not np.array_equal(runs[0]["regs"], runs[1]["regs"])   # different seeds differ
+
+
+def exact_replica_seed(orc, weights, b=16):
+    # a seed for which all replicas of all nodes fill distinct registers
+    items = [orc.replica_item(x, j) for x in range(len(weights)) for j in range(int(weights[x]))]
+    for seed in range(2000):
+        if np.count_nonzero(orc.counter_of(items, b, seed)) == len(items):
+            return seed
+    raise AssertionError("no collision-free seed")
+
+
+def test_run_ext_reduces_to_run(orc, gg):
+    off, idx = gg.rmat(8, 8, seed=31, transpose=True)
+    n = len(off) - 1
+    a = orc.run(off, idx, 6, 5)
+    table = [float(d) for d in range(1, 40)]
+    b = orc.run_ext(off, idx, 6, 5, weights=np.ones(n, dtype=np.int32), discount=table, trace=True)
+    assert a["passes"] == b["passes"] and np.array_equal(a["regs"], b["regs"])
+    assert np.array_equal(a["S"], b["S"]) and np.array_equal(a["H"], b["H"])
+    assert np.array_equal(b["D"], b["S"])          # f(d) = d is S's own weighting, same arithmetic
+    # the trace's last row is the size of the final counters
+    fin = orc.finalize(a["regs"], 6, a["S"], a["H"])
+    assert np.array_equal(b["etrace"][-1], fin["coreach"])
+    assert b["etrace"].shape == (a["passes"] + 1, n)
+
+
+def test_weighted_counter_is_hll_of_replicas(orc, gg):
+    n = 9
+    o, i = gg.empty(n)
+    w = np.array([1, 2, 3, 5, 8, 1, 1, 4, 2], dtype=np.int32)
+    r = orc.run_ext(o, i, 7, 13, weights=w)
+    for x in range(n):
+        items = [orc.replica_item(x, j) for j in range(w[x])]
+        assert np.array_equal(r["regs"][x], orc.counter_of(items, 7, 13))
+
+
+def test_weights_and_discounts_match_exact_distances(orc, gg):
+    # Sec. 6 and Sec. 7 in the exact-counting regime: S ~ sum_y w(y) d(x,y),
+    # H ~ sum_y w(y)/d(x,y), D ~ sum_y w(y) f(d(x,y)), coreach ~ sum of the
+    # weights of the reachable set (x included).
+    b = 16
+    rng = np.random.default_rng(17)
+    tables = {"quadratic": [1.0 / d ** 2 for d in range(1, 65)],
+              "logarithmic": [1.0 / math.log2(d + 1) for d in range(1, 65)],
+              "short": [1.0, 0.5, 0.25]}                     # f(d) = 1/4 beyond d = 3
+    for name, (o, i) in small_graphs(gg):
+        n = o.shape[0] - 1
+        w = rng.integers(1, 4, size=n).astype(np.int32)
+        seed = exact_replica_seed(orc, w)
+        Dist = bfs_dist(o, i)
+        for tname, table in tables.items():
+            r = orc.run_ext(o, i, b, seed, weights=w, discount=table)
+            core = orc.finalize(r["regs"], b, r["S"], r["H"])["coreach"]
+            for x in range(n):
+                mask = np.isfinite(Dist[x]) & (Dist[x] > 0)
+                d, wy = Dist[x][mask], w[mask]
+                fd = np.array([table[min(int(k), len(table)) - 1] for k in d])
+                S, H, Dd, R = (wy * d).sum(), (wy / d).sum(), (wy * fd).sum(), w[x] + wy.sum()
+                assert abs(r["S"][x] - S) < 3e-3 * max(1.0, S), (name, tname, x)
+                assert abs(r["H"][x] - H) < 3e-3 * max(1.0, H), (name, tname, x)
+                assert abs(r["D"][x] - Dd) < 3e-3 * max(1.0, Dd), (name, tname, x)
+                assert abs(core[x] - R) < 3e-3 * R, (name, tname, x)
+
+
+def test_neighbourhood_function_matches_ball_sizes(orc, gg):
+    # N(t) ~ sum over x of the weight of B(x, t), exact regime
+    b = 16
+    rng = np.random.default_rng(19)
+    for name, (o, i) in small_graphs(gg):
+        n = o.shape[0] - 1
+        w = rng.integers(1, 3, size=n).astype(np.int32)
+        seed = exact_replica_seed(orc, w)
+        Dist = bfs_dist(o, i)
+        r = orc.run_ext(o, i, b, seed, weights=w, trace=True)
+        N = orc.neighbourhood(r["etrace"])
+        assert len(N) == r["passes"] + 1
+        for t in range(len(N)):
+            exact = sum(w[(Dist[x] <= t)].sum() for x in range(n))
+            assert abs(N[t] - exact) < 3e-3 * exact, (name, t)
+        assert np.all(np.diff(N) >= -1e-9 * N[-1])          # balls only grow
+
+
+def test_distance_stats_closed_forms(orc):
+    # directed path on n nodes: n - d pairs at distance d, average (n+1)/3
+    n = 40
+    N = [n + sum(n - d for d in range(1, t + 1)) for t in range(n)]
+    st = orc.distance_stats(N)
+    assert st["pairs"] == n * (n - 1) / 2
+    assert abs(st["average_distance"] - (n + 1) / 3) < 1e-12
+    # directed cycle: n pairs at each distance 1..n-1, N(t) = n (t+1) linear,
+    # average n/2, effective diameter 0.9 n - 1 exactly by interpolation
+    n = 50
+    N = [n * (t + 1) for t in range(n)]
+    st = orc.distance_stats(N)
+    assert abs(st["average_distance"] - n / 2) < 1e-12
+    assert abs(st["effective_diameter"] - (0.9 * n - 1)) < 1e-12
+    assert orc.distance_stats([7.0])["effective_diameter"] == 0.0     # no arcs
