@@ -99,7 +99,9 @@ typedef struct {
  *   wgs_per_cu batched and served contexts: workgroups per compute unit of
  *              their persistent pass kernels (<= 0: 5).
  *   graph_passes batched contexts: passes per captured hipGraph replay in
- *              hb_run (<= 0: 4; convergence is read back once per replay). */
+ *              hb_run (<= 0: 4; convergence is read back once per replay).
+ *   neighbourhood  single-graph contexts: 1 records the neighbourhood
+ *              function N(t) at every pass (hb_neighbourhood). */
 typedef struct {
   int32_t frontier;
   int32_t light_max;
@@ -114,6 +116,7 @@ typedef struct {
   int32_t slice;
   int32_t wgs_per_cu;
   int32_t graph_passes;
+  int32_t neighbourhood;
 } hb_options;
 
 void hb_default_options(hb_options* opt);
@@ -378,6 +381,42 @@ hb_status hb_serve_stats(hb_server* s, hb_serve_stats_t* st);
 /* Finishes every submitted request (resuming a paused server), stops the
  * thread and frees everything; HB_EDEVICE if the server had failed. */
 hb_status hb_serve_stop(hb_server* s);
+
+/* ---- Weights, discounts and the neighbourhood function (single graphs) ----
+ * Sec. 6: integer node weights w(x) >= 1 are simulated by w(x) replicas per
+ * node: counter x starts as the HyperLogLog of the items x + j * 2^32,
+ * j < w(x) (x itself for j = 0, so unit weights change nothing).  Sizes,
+ * accumulators and centralities then count weighted nodes: S = sum_y w(y)
+ * d(y,x), H = sum_y w(y)/d(y,x), coreachable size = sum of reachable
+ * weights.  weights: n int32 (host or device, copied); NULL removes them.
+ * The computation restarts from pass 0 with the current seed. */
+hb_status hb_set_weights(hb_ctx* c, const int32_t* weights, int32_t on_device);
+
+/* Sec. 7 discounted-gain centrality sum_{y != x, d(y,x) finite} w(y)
+ * f(d(y,x)) for a discount table f(1..len) (host, copied; f(d) = f(len) for
+ * d > len): pass t adds f(t+1) * delta to D[v].  NULL or len 0 turns it off.
+ * Needs 2^log2m <= 256 and a single-graph, single-seed context.  The
+ * computation restarts from pass 0. */
+hb_status hb_set_discount(hb_ctx* c, const double* f, int32_t len);
+/* The discounted sums (n doubles). */
+hb_status hb_get_discounted(hb_ctx* c, double* D, int32_t dst_on_device);
+
+/* Neighbourhood function (opt.neighbourhood = 1): N(t) = sum over nodes of
+ * the size estimate after t passes, an estimate of the number of pairs
+ * (x, y) with y in B(x, t) (weighted: sum of w(y)), for t = 0..passes.  Each
+ * N(t) is the exact sum of the node estimates rounded once to double.
+ * Copies min(cap, passes + 1) values; *len receives passes + 1. */
+hb_status hb_neighbourhood(hb_ctx* c, double* N, int32_t cap, int32_t* len);
+
+typedef struct {
+  double pairs;              /* N(T) - N(0): pairs at distance >= 1 */
+  double average_distance;   /* sum_{t>=1} t (N(t) - N(t-1)) / pairs */
+  double effective_diameter; /* smallest t with N(t) >= alpha N(T), linearly interpolated */
+} hb_distance_stats_t;
+
+/* Distance statistics of a neighbourhood function N(0..len-1) (host
+ * arithmetic, sums in t order; no context needed). */
+hb_status hb_distance_stats(const double* N, int32_t len, double alpha, hb_distance_stats_t* out);
 
 /* Releases everything the context owns (never borrowed memory).  NULL-safe. */
 void hb_free(hb_ctx* c);

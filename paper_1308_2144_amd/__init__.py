@@ -48,7 +48,7 @@ class hb_options(ctypes.Structure):
                 ("dense_pct", ctypes.c_int32), ("push", ctypes.c_int32),
                 ("sparse_pct", ctypes.c_int32), ("qdense", ctypes.c_int32),
                 ("slice", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
-                ("graph_passes", ctypes.c_int32)]
+                ("graph_passes", ctypes.c_int32), ("neighbourhood", ctypes.c_int32)]
 
 
 class hb_stats_t(ctypes.Structure):
@@ -105,6 +105,11 @@ class hb_tune_report(ctypes.Structure):
                 ("start_ms", ctypes.c_double), ("best_ms", ctypes.c_double), ("tune_s", ctypes.c_double)]
 
 
+class hb_distance_stats_t(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.c_double), ("average_distance", ctypes.c_double),
+                ("effective_diameter", ctypes.c_double)]
+
+
 HB_REQ_QUEUED, HB_REQ_RUNNING, HB_REQ_DONE, HB_REQ_CANCELLED, HB_REQ_FAILED = range(5)
 REQ_STATES = ("queued", "running", "done", "cancelled", "failed")
 
@@ -130,6 +135,11 @@ def _declare(L):
         "hb_batch_reset": (ctypes.c_int, [vp, vp]),
         "hb_batch_graph": (ctypes.c_int, [vp, i32, P(hb_graph_info)]),
         "hb_batch_passes": (ctypes.c_int, [vp, vp]),
+        "hb_set_weights": (ctypes.c_int, [vp, vp, i32]),
+        "hb_set_discount": (ctypes.c_int, [vp, vp, i32]),
+        "hb_get_discounted": (ctypes.c_int, [vp, vp, i32]),
+        "hb_neighbourhood": (ctypes.c_int, [vp, vp, i32, P(i32)]),
+        "hb_distance_stats": (ctypes.c_int, [vp, i32, ctypes.c_double, P(hb_distance_stats_t)]),
         "hb_ensemble_init": (ctypes.c_int, [P(vp), P(hb_csr), i32, vp, i32, P(hb_options), vp]),
         "hb_ensemble_reset": (ctypes.c_int, [vp, vp]),
         "hb_ensemble_passes": (ctypes.c_int, [vp, vp]),
@@ -237,6 +247,61 @@ def hb_init(offsets, indices, log2m: int, seed: int, options: hb_options | None 
     _check(lib().hb_init(ctypes.byref(ctx), ctypes.byref(g), int(log2m), int(seed), opt,
                          ctypes.c_void_p(stream) if stream else None))
     return ctx, keep
+
+
+def hb_set_weights(ctx, weights):
+    """weights: n int32 >= 1 (numpy host array or torch CUDA tensor), or None."""
+    if weights is None:
+        _check(lib().hb_set_weights(ctx, None, 0))
+        return None
+    if _is_torch(weights):
+        _check(lib().hb_set_weights(ctx, weights.data_ptr(), 1))
+        return weights
+    w = np.ascontiguousarray(weights, dtype=np.int32)
+    _check(lib().hb_set_weights(ctx, w.ctypes.data, 0))
+    return w
+
+
+def hb_set_discount(ctx, table):
+    if table is None or len(table) == 0:
+        _check(lib().hb_set_discount(ctx, None, 0))
+        return
+    f = np.ascontiguousarray(table, dtype=np.float64)
+    _check(lib().hb_set_discount(ctx, f.ctypes.data, f.shape[0]))
+
+
+def hb_get_discounted(ctx, D, dst_on_device: bool):
+    _check(lib().hb_get_discounted(ctx, _ptr(D), int(bool(dst_on_device))))
+
+
+def hb_neighbourhood(ctx) -> np.ndarray:
+    ln = ctypes.c_int32(0)
+    _check(lib().hb_neighbourhood(ctx, None, 0, ctypes.byref(ln)))
+    out = np.empty(max(ln.value, 1))
+    _check(lib().hb_neighbourhood(ctx, out.ctypes.data, ln.value, ctypes.byref(ln)))
+    return out[: ln.value]
+
+
+def hb_distance_stats(N, alpha: float = 0.9) -> dict:
+    a = np.ascontiguousarray(N, dtype=np.float64)
+    st = hb_distance_stats_t()
+    _check(lib().hb_distance_stats(a.ctypes.data, a.shape[0], float(alpha), ctypes.byref(st)))
+    return {k: getattr(st, k) for k, _ in hb_distance_stats_t._fields_}
+
+
+def discount_table(kind: str, length: int = 64) -> np.ndarray:
+    """f(1..length) for the discounts Sec. 7 names: "harmonic" 1/d,
+    "quadratic" 1/d^2, "logarithmic" 1/log2(d+1), "constant" 1."""
+    d = np.arange(1, length + 1, dtype=np.float64)
+    if kind == "harmonic":
+        return 1.0 / d
+    if kind == "quadratic":
+        return 1.0 / (d * d)
+    if kind == "logarithmic":
+        return 1.0 / np.log2(d + 1.0)
+    if kind == "constant":
+        return np.ones_like(d)
+    raise ValueError(f"unknown discount {kind}")
 
 
 def hb_ensemble_init(offsets, indices, log2m: int, seeds, options: hb_options | None = None, stream=None):
@@ -518,6 +583,20 @@ class HyperBall:
 
     def pass_stats(self, t: int) -> dict:
         return hb_pass_stats(self._ctx, t)
+
+    def set_weights(self, weights):
+        self._weights = hb_set_weights(self._ctx, weights)
+
+    def set_discount(self, table):
+        hb_set_discount(self._ctx, table)
+
+    def discounted(self) -> np.ndarray:
+        D = np.empty(max(self.n, 1))
+        hb_get_discounted(self._ctx, D, False)
+        return D[: self.n]
+
+    def neighbourhood(self) -> np.ndarray:
+        return hb_neighbourhood(self._ctx)
 
 
 class Batch:

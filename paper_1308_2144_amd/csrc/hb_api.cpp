@@ -59,6 +59,11 @@ void release(hb_ctx* c) {
   (void)hipFree(c->ctl);
   (void)hipFree(c->arena_tmp);
   (void)hipFree(c->seeds_dev);
+  (void)hipFree(c->weights);
+  (void)hipFree(c->D);
+  (void)hipFree(c->esum_part);
+  (void)hipFree(c->esum_out);
+  if (c->esum_host) (void)hipHostFree(c->esum_host);
   if (c->ctl_host) (void)hipHostFree(c->ctl_host);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -118,6 +123,50 @@ void plan_rows(hb_ctx* c, const int64_t* off_host, std::vector<int32_t>& light,
 
 namespace {
 
+constexpr int ESUM_BLOCKS = 1024;
+
+// X * 2^-52 rounded to the nearest double (ties to even), X the 192-bit
+// integer w[0] + w[1] 2^64 + w[2] 2^128 of an exact sum of estimates.
+double fix_to_double(const uint64_t* w) {
+  int top = -1;
+  for (int i = 2; i >= 0 && top < 0; --i)
+    if (w[i]) top = 64 * i + 63 - __builtin_clzll(w[i]);
+  if (top < 0) return 0.0;
+  if (top <= 52) return std::ldexp((double)w[0], -52);  // below 2^53: exact
+  auto bit = [&](int k) -> uint64_t { return (w[k >> 6] >> (k & 63)) & 1ull; };
+  const int shift = top - 52;
+  uint64_t mant = 0;
+  for (int k = 52; k >= 0; --k) mant = (mant << 1) | bit(shift + k);
+  const uint64_t guard = bit(shift - 1);
+  bool sticky = false;
+  for (int k = 0; k < shift - 1 && !sticky; ++k) sticky = bit(k) != 0;
+  int e = shift - 52;
+  if (guard && (sticky || (mant & 1ull))) ++mant;
+  if (mant == (1ull << 53)) {
+    mant >>= 1;
+    ++e;
+  }
+  return std::ldexp((double)mant, e);
+}
+
+// Enqueues the exact sum of the current estimates and its readback.
+hipError_t enqueue_esum(hb_ctx* c) {
+  hipError_t e = hb::launch_fill_zero(c->esum_out + 3, sizeof(uint64_t), c->stream);
+  if (e == hipSuccess)
+    e = hb::launch_esum(c->E, c->n, c->esum_part, ESUM_BLOCKS, c->esum_out, reinterpret_cast<int*>(c->esum_out + 3),
+                        c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->esum_host, c->esum_out, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream);
+  return e;
+}
+
+// After the stream synchronised: appends N(t).
+hb_status take_esum(hb_ctx* c) {
+  if ((uint32_t)c->esum_host[3] != 0u) return fail(HB_EDEVICE, "neighbourhood sum: an estimate is not a multiple of 2^-52");
+  c->nf.push_back(fix_to_double(c->esum_host));
+  return HB_OK;
+}
+
 hb_status do_reset(hb_ctx* c, uint64_t seed) {
   c->seed = seed;
   c->t = 0;
@@ -162,8 +211,20 @@ hb_status do_reset(hb_ctx* c, uint64_t seed) {
     HB_HIP(hipStreamSynchronize(c->stream));  // the seed upload reads host memory
     return HB_OK;
   }
-  HB_HIP(hb::launch_init_nodes(c->b, c->n, seed, c->cnt[0], c->cnt[1], c->S, c->H, c->E, c->lc,
-                               c->alpha_pp, c->stream));
+  if (c->weights) {
+    HB_HIP(hb::launch_init_weighted(c->b, c->n, seed, c->weights, c->cnt[0], c->cnt[1], c->S, c->H, c->D, c->E, c->lc,
+                                    c->alpha_pp, c->stream));
+  } else {
+    HB_HIP(hb::launch_init_nodes(c->b, c->n, seed, c->cnt[0], c->cnt[1], c->S, c->H, c->E, c->lc,
+                                 c->alpha_pp, c->stream));
+    if (c->D) HB_HIP(hb::launch_fill_zero(c->D, sizeof(double) * (size_t)c->n, c->stream));
+  }
+  c->nf.clear();
+  if (c->esum_out) {
+    HB_HIP(enqueue_esum(c));
+    HB_HIP(hipStreamSynchronize(c->stream));
+    return take_esum(c);
+  }
   return HB_OK;
 }
 
@@ -286,6 +347,11 @@ hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, co
   const int ps = 1 << c->b_seed;  // registers per counter
   HB_HIP(dmalloc(&c->lc, (size_t)ps + 1));
   if (c->n_seeds > 1) HB_HIP(dmalloc(&c->seeds_dev, (size_t)c->n_seeds));
+  if (c->opt.neighbourhood && !blk_graph && c->n_seeds == 1) {
+    HB_HIP(dmalloc(&c->esum_part, (size_t)3 * ESUM_BLOCKS));
+    HB_HIP(dmalloc(&c->esum_out, 4));
+    HB_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->esum_host), 4 * sizeof(uint64_t), hipHostMallocDefault));
+  }
   HB_HIP(dmalloc(&c->partial, (size_t)c->n_items * (size_t)c->p));
   HB_HIP(dmalloc(&c->stats, (size_t)2 * hb::STAT_SLOTS * hb::STAT_K));
   HB_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->stats_host),
@@ -450,6 +516,7 @@ void hb_default_options(hb_options* opt) {
   opt->slice = 0;
   opt->wgs_per_cu = 5;
   opt->graph_passes = 4;
+  opt->neighbourhood = 0;
 }
 
 hb_status hb_init(hb_ctx** out, const hb_csr* g, int32_t log2m, uint64_t seed, const hb_options* opt,
@@ -522,6 +589,7 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
   hb_pass_info info{};
   if (c->n == 0) {
     c->hist.push_back(info);
+    if (c->esum_out) c->nf.push_back(0.0);
     for (auto& sp : c->seed_passes)
       if (sp < 0) sp = c->t + 1;
     c->t += 1;
@@ -585,6 +653,8 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
   a.mode = mode;
   a.qdense = c->opt.qdense ? 1 : 0;
   a.seg_lanes = (1 << c->b_seed) / 16;
+  a.D = c->D;
+  a.disc_f = c->disc.empty() ? 0.0 : c->disc[(size_t)std::min<int64_t>(c->t, (int64_t)c->disc.size() - 1)];
   const bool timing = c->opt.timing != 0;
   hipError_t e = hipSuccess;
   if (timing) e = hipEventRecord(c->ev[0], c->stream);
@@ -597,6 +667,7 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
   if (e == hipSuccess && timing) e = hipEventRecord(c->ev[1], c->stream);
   if (e == hipSuccess) e = hb::launch_pass(c->b, a, c->stream, timing ? c->ev[2] : nullptr);
   if (e == hipSuccess && timing) e = hipEventRecord(c->ev[3], c->stream);
+  if (e == hipSuccess && c->esum_out) e = enqueue_esum(c);
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->stats_host, a.stats, sizeof(unsigned long long) * half, hipMemcpyDeviceToHost,
                        c->stream);
@@ -632,6 +703,13 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
     info.expand_ms = ms1;
     info.merge_ms = ms2;
     c->total_ms += (double)ms0 + (double)ms1 + (double)ms2;
+  }
+  if (c->esum_out) {
+    const hb_status es = take_esum(c);
+    if (es != HB_OK) {
+      c->failed = true;
+      return es;
+    }
   }
   c->hist.push_back(info);
   c->cur ^= 1;
@@ -909,6 +987,105 @@ hb_status hb_batch_passes(hb_ctx* c, int32_t* passes) {
   HB_HIP(hipMemcpyAsync(gh.data(), c->graphs, sizeof(hb::GraphDev) * gh.size(), hipMemcpyDeviceToHost, c->stream));
   HB_HIP(hipStreamSynchronize(c->stream));
   for (size_t i = 0; i < gh.size(); ++i) passes[i] = gh[i].done ? gh[i].passes : -1;
+  return HB_OK;
+}
+
+hb_status hb_set_weights(hb_ctx* c, const int32_t* weights, int32_t on_device) {
+  hb_status st = check_ctx(c);
+  if (st != HB_OK) return st;
+  if (c->n_graphs > 0 || c->n_seeds > 1) return fail(HB_EINVAL, "node weights need a single-graph, single-seed context");
+  if (!weights) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->weights);
+    c->weights = nullptr;
+  } else if (c->n > 0) {
+    if (!on_device)
+      for (int64_t v = 0; v < c->n; ++v)
+        if (weights[v] < 1) return fail(HB_EINVAL, "node weights must be >= 1");
+    if (!c->weights) HB_HIP(dmalloc(&c->weights, (size_t)c->n));
+    HB_HIP(hipMemcpyAsync(c->weights, weights, sizeof(int32_t) * (size_t)c->n,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+    if (on_device) {
+      if (!c->bad) HB_HIP(dmalloc(&c->bad, 1));
+      HB_HIP(hb::launch_fill_zero(c->bad, sizeof(int), c->stream));
+      HB_HIP(hb::launch_check_weights(c->weights, c->n, c->bad, c->stream));
+      int bad = 0;
+      HB_HIP(hipMemcpyAsync(&bad, c->bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      HB_HIP(hipStreamSynchronize(c->stream));
+      if (bad) {
+        (void)hipFree(c->weights);
+        c->weights = nullptr;
+        return fail(HB_EINVAL, "node weights must be >= 1");
+      }
+    }
+    HB_HIP(hipStreamSynchronize(c->stream));  // host weights are read before returning
+  }
+  st = do_reset(c, c->seed);
+  if (st != HB_OK) c->failed = true;
+  return st;
+}
+
+hb_status hb_set_discount(hb_ctx* c, const double* f, int32_t len) {
+  hb_status st = check_ctx(c);
+  if (st != HB_OK) return st;
+  if (c->n_graphs > 0 || c->n_seeds > 1) return fail(HB_EINVAL, "discounts need a single-graph, single-seed context");
+  if (c->p > 256) return fail(HB_EINVAL, "discounts need 2^log2m <= 256");
+  if (!f || len <= 0) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->D);
+    c->D = nullptr;
+    c->disc.clear();
+  } else {
+    for (int32_t i = 0; i < len; ++i)
+      if (!std::isfinite(f[i])) return fail(HB_EINVAL, "discount values must be finite");
+    c->disc.assign(f, f + len);
+    if (!c->D) HB_HIP(dmalloc(&c->D, (size_t)(c->n > 0 ? c->n : 1)));
+  }
+  st = do_reset(c, c->seed);
+  if (st != HB_OK) c->failed = true;
+  return st;
+}
+
+hb_status hb_get_discounted(hb_ctx* c, double* D, int32_t dst_on_device) {
+  hb_status st = check_ctx(c);
+  if (st != HB_OK) return st;
+  if (!D) return fail(HB_EINVAL, "D is NULL");
+  if (!c->D) return fail(HB_EINVAL, "no discount set (hb_set_discount)");
+  if (c->n == 0) return HB_OK;
+  HB_HIP(hipMemcpyAsync(D, c->D, sizeof(double) * (size_t)c->n,
+                        dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+  HB_HIP(hipStreamSynchronize(c->stream));
+  return HB_OK;
+}
+
+hb_status hb_neighbourhood(hb_ctx* c, double* N, int32_t cap, int32_t* len) {
+  hb_status st = check_ctx(c);
+  if (st != HB_OK) return st;
+  if (!c->esum_out) return fail(HB_EINVAL, "the context was not made with opt.neighbourhood = 1");
+  const int32_t have = (int32_t)c->nf.size();
+  if (len) *len = have;
+  if (N)
+    for (int32_t t = 0; t < have && t < cap; ++t) N[t] = c->nf[(size_t)t];
+  return HB_OK;
+}
+
+hb_status hb_distance_stats(const double* N, int32_t len, double alpha, hb_distance_stats_t* out) {
+  if (!N || !out || len < 1) return fail(HB_EINVAL, "need N with at least one entry and an output");
+  const int32_t T = len - 1;
+  const double pairs = N[T] - N[0];
+  double num = 0.0;
+  for (int32_t t = 1; t <= T; ++t) num = num + (double)t * (N[t] - N[t - 1]);
+  out->pairs = pairs;
+  out->average_distance = pairs > 0.0 ? num / pairs : 0.0;
+  const double target = alpha * N[T];
+  double eff = 0.0;
+  for (int32_t t = 0; t <= T; ++t) {
+    if (N[t] >= target) {
+      eff = t == 0 ? 0.0 : (double)(t - 1) + (target - N[t - 1]) / (N[t] - N[t - 1]);
+      break;
+    }
+  }
+  out->effective_diameter = eff;
   return HB_OK;
 }
 

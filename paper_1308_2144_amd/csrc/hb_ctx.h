@@ -52,6 +52,16 @@ struct hb_ctx {
   std::vector<uint64_t> seeds;
   uint64_t* seeds_dev = nullptr;
   std::vector<int32_t> seed_passes;  // pass count of each seed once converged, else -1
+  // Sec. 6 node weights (device, n entries; null: every weight 1).
+  int32_t* weights = nullptr;
+  // Sec. 7 discounted-gain accumulator and its table f(1..L) (empty: off).
+  double* D = nullptr;
+  std::vector<double> disc;
+  // Neighbourhood function N(0..t) (opt.neighbourhood) and its exact-sum scratch.
+  std::vector<double> nf;
+  uint64_t* esum_part = nullptr;
+  uint64_t* esum_out = nullptr;  // 3 words + the inexact flag word
+  uint64_t* esum_host = nullptr; // pinned copy of esum_out
   uint64_t seed = 0;
   hb_options opt{};
   hipStream_t stream = nullptr;

@@ -120,6 +120,10 @@ struct PassArgs {
   // (one per seed, seg_lanes * 16 bytes each) and E, S, H hold K values per
   // node.  0 means one counter per row.
   int32_t seg_lanes;
+  // Discounted-gain accumulator (Sec. 7, nullable): D += disc_f * delta,
+  // disc_f = f(t+1) for this pass.
+  double* D;
+  double disc_f;
   // Multi-graph contexts (null otherwise): graph of each 64-node block, the
   // per-graph state, and the device pass control; with ctl set, cur/nxt,
   // mod_prev/mod_cur, mode, epoch and the stats halves are taken from ctl
@@ -138,6 +142,19 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_init_nodes(int log2m, int64_t n, uint64_t seed, uint8_t* cur, uint8_t* nxt,
                              double* S, double* H, double* E, const double* lc, double alpha_pp,
                              hipStream_t s);
+// Weighted initialisation (Sec. 6 replicas): counter v holds the HyperLogLog
+// of items v + j * 2^32, j < w[v]; then E from the counters, S = H = 0, and
+// D = 0 if D is set.
+hipError_t launch_init_weighted(int log2m, int64_t n, uint64_t seed, const int32_t* w, uint8_t* cur, uint8_t* nxt,
+                                double* S, double* H, double* D, double* E, const double* lc, double alpha_pp,
+                                hipStream_t s);
+// Sets *bad to 1 if some w[v] < 1.
+hipError_t launch_check_weights(const int32_t* w, int64_t n, int* bad, hipStream_t s);
+// Exact sum of E[0..n) as a 192-bit integer E * 2^52 (three words, low
+// first) into out; partial holds 3 * max_blocks words of scratch; *inexact
+// becomes 1 if an E is not a multiple of 2^-52 (never for counter estimates).
+hipError_t launch_esum(const double* E, int64_t n, uint64_t* partial, int max_blocks, uint64_t* out, int* inexact,
+                       hipStream_t s);
 // Ensemble initialisation: rows of K = 2^seg_log counters of p = 2^log2m
 // registers, counter k of node v hashing v with seeds[k] (device array).
 hipError_t launch_init_ensemble(int log2m, int seg_log, int64_t n, const uint64_t* seeds, uint8_t* cur, uint8_t* nxt,

@@ -53,6 +53,13 @@ namespace {
 #endif
 constexpr int U = HB_U;
 
+// Kernel flavours of the fused estimator/accumulator step: one counter per
+// row; an ensemble row of several seeds' counters; one counter per row plus
+// the discounted-gain accumulator.
+constexpr int FL_PLAIN = 0;
+constexpr int FL_ENS = 1;
+constexpr int FL_DISC = 2;
+
 template <class T>
 __device__ __forceinline__ T ld_stream(const T* p) {
 #if HB_NT
@@ -439,16 +446,17 @@ __device__ __forceinline__ uint4 gather_wave_q(const PassArgs& A, QEnt* q, int64
 struct RowPre {
   uint4 own;
   double e, s, h;
+  double dd;  // discounted sum (FL_DISC)
 };
 
-template <int B, bool ENS = false>
+template <int B, int FL = FL_PLAIN>
 __device__ __forceinline__ RowPre preload(const PassArgs& A, int64_t row, int gl) {
   constexpr int P = 1 << B;
   constexpr int G = P / 16;
   RowPre r;
   r.own = ld_stream(reinterpret_cast<const uint4*>(A.cur + (size_t)row * P + (size_t)gl * 16));
-  r.e = r.s = r.h = 0.0;
-  if constexpr (ENS) {
+  r.e = r.s = r.h = r.dd = 0.0;
+  if constexpr (FL == FL_ENS) {
     // first lane of each seed's counter: its cached estimate and accumulators
     const int gs = A.seg_lanes;
     if ((gl & (gs - 1)) == 0) {
@@ -461,16 +469,18 @@ __device__ __forceinline__ RowPre preload(const PassArgs& A, int64_t row, int gl
     r.e = ld_stream(A.E + row);
     r.s = ld_stream(A.S + row);
     r.h = ld_stream(A.H + row);
+    if constexpr (FL == FL_DISC) r.dd = ld_stream(A.D + row);
   }
   return r;
 }
 
 // Completes row `row` for a group of G lanes: a = own U gathered, write-back
 // rule, change detection, the fused estimator/accumulator, the change bit
-// and the mask of changed slices.  In an ensemble row (ENS) every seed's
+// and the mask of changed slices.  In an ensemble row (FL_ENS) every seed's
 // counter gets its own estimator and accumulators, and the row's change bit
-// is set if any of them changed.  Returns whether the row changed.
-template <int B, bool MG, bool ENS = false>
+// is set if any of them changed; FL_DISC also accumulates the discounted sum
+// D += f(t+1) * delta.  Returns whether the row changed.
+template <int B, bool MG, int FL = FL_PLAIN>
 __device__ __forceinline__ bool finish_row(const PassArgs& A, int64_t row, uint4 acc, bool got,
                                            const RowPre& pre, bool own_mod, int gl, int grp,
                                            Counts& c) {
@@ -490,7 +500,7 @@ __device__ __forceinline__ bool finish_row(const PassArgs& A, int64_t row, uint4
     c.sch += (uint32_t)__popc(msk);
     if (changed && A.roff) c.pairs += (uint32_t)(A.roff[row + 1] - A.roff[row]);
   }
-  if constexpr (ENS) {
+  if constexpr (FL == FL_ENS) {
     const int gs = A.seg_lanes;  // lanes per seed's counter
     const int seg = gl / gs;
     if (gl == 0 && changed)
@@ -538,6 +548,7 @@ __device__ __forceinline__ bool finish_row(const PassArgs& A, int64_t row, uint4
       const double d = row_d<MG>(A, row);
       st_stream(A.S + row, pre.s + d * delta);
       st_stream(A.H + row, pre.h + delta / d);
+      if constexpr (FL == FL_DISC) st_stream(A.D + row, pre.dd + A.disc_f * delta);
       st_stream(A.E + row, En);
       if (A.dmask_cur) A.dmask_cur[row] = (uint16_t)msk;
       atomicOr(A.mod_cur + (row >> 6), 1ull << (row & 63));
@@ -546,16 +557,16 @@ __device__ __forceinline__ bool finish_row(const PassArgs& A, int64_t row, uint4
   return changed;
 }
 
-template <bool ENS = false>
+template <int FL = FL_PLAIN>
 __device__ __forceinline__ void add_stats(unsigned long long* st, const Counts& c) {
   const unsigned long long v[STAT_SEEDS] = {c.gath, c.load, c.write, c.chg, c.arcs, c.slices, c.sch, c.pairs};
 #pragma unroll
   for (int k = 0; k < STAT_SEEDS; ++k)
     if (v[k]) atomicAdd(st + k, v[k]);
-  if (ENS && c.seeds) atomicOr(st + STAT_SEEDS, (unsigned long long)c.seeds);
+  if (FL == FL_ENS && c.seeds) atomicOr(st + STAT_SEEDS, (unsigned long long)c.seeds);
 }
 
-template <bool ENS = false>
+template <int FL = FL_PLAIN>
 __device__ __forceinline__ void flush_counts(const PassArgs& A, Counts c, int64_t slot, int lane) {
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -567,16 +578,16 @@ __device__ __forceinline__ void flush_counts(const PassArgs& A, Counts c, int64_
     c.slices += __shfl_xor(c.slices, o);
     c.sch += __shfl_xor(c.sch, o);
     c.pairs += __shfl_xor(c.pairs, o);
-    if (ENS) c.seeds |= __shfl_xor(c.seeds, o);
+    if (FL == FL_ENS) c.seeds |= __shfl_xor(c.seeds, o);
   }
-  if (lane == 0) add_stats<ENS>(A.stats + (slot & (STAT_SLOTS - 1)) * STAT_K, c);
+  if (lane == 0) add_stats<FL>(A.stats + (slot & (STAT_SLOTS - 1)) * STAT_K, c);
 }
 
 __device__ __forceinline__ uint64_t lanes_below(int lane) { return (1ull << lane) - 1ull; }
 
 // 64 consecutive entries of the light-row list per wavefront; entry
 // q*W + grp goes to lane group grp in round q.
-template <int B, bool Q, bool MG, bool ENS = false>
+template <int B, bool Q, bool MG, int FL = FL_PLAIN>
 __device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, int64_t lw, int lane) {
   constexpr int P = 1 << B;
   constexpr int G = P / 16;
@@ -605,7 +616,7 @@ __device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, int64_t 
       const int64_t rd = __shfl(deg, rl);
       if ((needs >> rl) & 1ull) {
         const bool rmod = ((mods >> rl) & 1ull) != 0ull;
-        const RowPre pre = preload<B, ENS>(A, rrow, gl);
+        const RowPre pre = preload<B, FL>(A, rrow, gl);
         bool got = false;
         uint4 acc;
         if constexpr (Q)
@@ -613,16 +624,16 @@ __device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, int64_t 
         else
           acc = gather<B>(A, rs, rs + rd, 1, gl, got, c);
         if (gl == 0) c.arcs += (uint32_t)rd;
-        finish_row<B, MG, ENS>(A, rrow, acc, got, pre, rmod, gl, grp, c);
+        finish_row<B, MG, FL>(A, rrow, acc, got, pre, rmod, gl, grp, c);
       }
     }
   }
-  flush_counts<ENS>(A, c, lw, lane);
+  flush_counts<FL>(A, c, lw, lane);
 }
 
 // One medium row per wavefront: the groups share its arcs and reduce their
 // partial maxima by shuffles.
-template <int B, bool Q, bool MG, bool ENS = false>
+template <int B, bool Q, bool MG, int FL = FL_PLAIN>
 __device__ __forceinline__ void medium_wave(const PassArgs& A, QEnt* qw, int64_t mi, int lane) {
   constexpr int P = 1 << B;
   constexpr int G = P / 16;
@@ -637,7 +648,7 @@ __device__ __forceinline__ void medium_wave(const PassArgs& A, QEnt* qw, int64_t
   Counts c{};
   if (need) {
     RowPre pre;
-    if (grp == 0) pre = preload<B, ENS>(A, row, gl);
+    if (grp == 0) pre = preload<B, FL>(A, row, gl);
     bool got = false;
     uint4 acc;
     if constexpr (Q)
@@ -648,9 +659,9 @@ __device__ __forceinline__ void medium_wave(const PassArgs& A, QEnt* qw, int64_t
 #pragma unroll
     for (int o = G; o < 64; o <<= 1) acc = bmax(acc, shfl_xor4(acc, o));
     got = __ballot(got) != 0ull;
-    if (grp == 0) finish_row<B, MG, ENS>(A, row, acc, got, pre, own_mod, gl, 0, c);
+    if (grp == 0) finish_row<B, MG, FL>(A, row, acc, got, pre, own_mod, gl, 0, c);
   }
-  flush_counts<ENS>(A, c, mi, lane);
+  flush_counts<FL>(A, c, mi, lane);
 }
 
 // One chunk of a heavy row per workgroup (4 wavefronts): writes the chunk's
@@ -697,7 +708,7 @@ __device__ __forceinline__ void heavy_chunk(const PassArgs& A, QEnt* qw, int64_t
 // per workgroup][light rows, 256 per workgroup].  Q selects the queued
 // gather (slice, edge and sparse passes, or dense passes on request) over
 // the direct one.
-template <int B, bool Q, bool MG, bool ENS = false>
+template <int B, bool Q, bool MG, int FL = FL_PLAIN>
 __device__ __forceinline__ void expand_item(const PassArgs& A, QEnt* qw, int64_t b) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -711,12 +722,12 @@ __device__ __forceinline__ void expand_item(const PassArgs& A, QEnt* qw, int64_t
   const int64_t med_wgs = (A.n_medium + 3) / 4;
   if (b < med_wgs) {
     const int64_t mi = b * 4 + wave;
-    if (mi < A.n_medium) medium_wave<B, Q, MG, ENS>(A, qw, mi, lane);
+    if (mi < A.n_medium) medium_wave<B, Q, MG, FL>(A, qw, mi, lane);
     return;
   }
   b -= med_wgs;
   const int64_t lw = b * 4 + wave;
-  if (lw * 64 < A.n_light) light_wave<B, Q, MG, ENS>(A, qw, lw, lane);
+  if (lw * 64 < A.n_light) light_wave<B, Q, MG, FL>(A, qw, lw, lane);
 }
 
 __device__ __forceinline__ int64_t pass_items(const PassArgs& A) {
@@ -733,15 +744,15 @@ __device__ __forceinline__ bool queued_mode(const PassArgs& A) {
 #define HB_EXPAND_ATTR __launch_bounds__(256)
 #endif
 
-template <int B, bool ENS = false>
+template <int B, int FL = FL_PLAIN>
 __global__ HB_EXPAND_ATTR void k_expand(PassArgs A) {
-  expand_item<B, false, false, ENS>(A, nullptr, blockIdx.x);
+  expand_item<B, false, false, FL>(A, nullptr, blockIdx.x);
 }
 
-template <int B, bool ENS = false>
+template <int B, int FL = FL_PLAIN>
 __global__ HB_EXPAND_ATTR void k_expand_q(PassArgs A) {
   __shared__ QEnt qbuf[4][QCAP];
-  expand_item<B, true, false, ENS>(A, qbuf[threadIdx.x >> 6], blockIdx.x);
+  expand_item<B, true, false, FL>(A, qbuf[threadIdx.x >> 6], blockIdx.x);
 }
 
 // Persistent form for device-driven passes: a fixed grid whose workgroups
@@ -767,7 +778,7 @@ __global__ HB_EXPAND_ATTR void k_expand_p(PassArgs A0) {
 
 // Folds the partial counters of every heavy row into the row (one wavefront
 // per heavy row) and finishes it like any other row.
-template <int B, bool MG, bool ENS = false>
+template <int B, bool MG, int FL = FL_PLAIN>
 __global__ __launch_bounds__(256) void k_merge(PassArgs A0) {
   const PassArgs A = resolve(A0);
   constexpr int P = 1 << B;
@@ -784,7 +795,7 @@ __global__ __launch_bounds__(256) void k_merge(PassArgs A0) {
   row_flags<MG>(A, hr.row, own_mod, need);
   if (!need) return;
   RowPre pre;
-  if (grp == 0) pre = preload<B, ENS>(A, hr.row, gl);
+  if (grp == 0) pre = preload<B, FL>(A, hr.row, gl);
   uint4 acc = zero4();
   for (int64_t j = grp; j < hr.nitems; j += W)
     acc = bmax(acc, *reinterpret_cast<const uint4*>(A.partial + (size_t)(hr.item0 + j) * P +
@@ -792,8 +803,8 @@ __global__ __launch_bounds__(256) void k_merge(PassArgs A0) {
 #pragma unroll
   for (int o = G; o < 64; o <<= 1) acc = bmax(acc, shfl_xor4(acc, o));
   Counts c{};
-  if (grp == 0) finish_row<B, MG, ENS>(A, hr.row, acc, true, pre, own_mod, gl, 0, c);
-  flush_counts<ENS>(A, c, h, lane);
+  if (grp == 0) finish_row<B, MG, FL>(A, hr.row, acc, true, pre, own_mod, gl, 0, c);
+  flush_counts<FL>(A, c, h, lane);
 }
 
 // Counters wider than 256 bytes: one workgroup per 64-row block, rows in
@@ -948,6 +959,142 @@ __global__ void k_finalize(int64_t n, const double* S, const double* H, const do
   if (clo) clo[v] = (s == 0.0) ? 0.0 : 1.0 / s;
   if (lin) lin[v] = (s == 0.0) ? 1.0 : (size * size) / s;
   if (harm) harm[v] = H[v];
+}
+
+// Weighted initialisation (Sec. 6): counter v is the HyperLogLog of the w[v]
+// replicas of v, replica j hashing as item v + j * 2^32 (v itself for j = 0);
+// thread i writes 16-byte chunk i of the counters into both buffers.  The
+// estimates are computed afterwards by k_row_estimate.
+__global__ void k_init_weighted(int log2m, int64_t n, uint64_t seed, const int32_t* w, uint8_t* cur, uint8_t* nxt) {
+  const int64_t P = (int64_t)1 << log2m;
+  const int64_t C = P / 16;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * C) return;
+  const int64_t v = i / C;
+  const int64_t chunk = i - v * C;
+  uint8_t reg[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) reg[k] = 0;
+  const int64_t reps = w[v];
+  for (int64_t j = 0; j < reps; ++j) {
+    const uint64_t h = node_hash((uint64_t)v + ((uint64_t)j << 32), seed);
+    const uint32_t idx = (uint32_t)(h >> (64 - log2m));
+    if ((int64_t)(idx >> 4) != chunk) continue;
+    const uint64_t rest = h << log2m;
+    const uint32_t r = rest == 0ull ? (uint32_t)(65 - log2m) : (uint32_t)__clzll((long long)rest) + 1u;
+    const uint32_t k = idx & 15u;
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if ((uint32_t)q == k && r > reg[q]) reg[q] = (uint8_t)r;
+  }
+  uint32_t wd[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    wd[q] = (uint32_t)reg[4 * q] | ((uint32_t)reg[4 * q + 1] << 8) | ((uint32_t)reg[4 * q + 2] << 16) |
+            ((uint32_t)reg[4 * q + 3] << 24);
+  const uint4 val = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+  *reinterpret_cast<uint4*>(cur + v * P + chunk * 16) = val;
+  *reinterpret_cast<uint4*>(nxt + v * P + chunk * 16) = val;
+}
+
+// E[v] = size(counter v) (Algorithm 1), S = H = 0 and, if D is set, D = 0;
+// one thread per counter, the register sum accumulated exactly as in the
+// pass kernels (terms above and below 2^-26 summed apart, rounded once).
+__global__ void k_row_estimate(int log2m, int64_t n, const uint8_t* cnt, double* S, double* H, double* D, double* E,
+                               const double* lc, double alpha_pp) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int64_t P = (int64_t)1 << log2m;
+  const uint4* row = reinterpret_cast<const uint4*>(cnt + v * P);
+  double big = 0.0, small = 0.0;
+  int V = 0;
+  for (int64_t c = 0; c < P / 16; ++c) {
+    const Parts pr = reg_parts(row[c]);
+    big += pr.big;
+    small += pr.small;
+    V += pr.zeros;
+  }
+  E[v] = estimate(big, small, V, alpha_pp, (double)P, lc);
+  S[v] = 0.0;
+  H[v] = 0.0;
+  if (D) D[v] = 0.0;
+}
+
+// --- exact sum of the estimates (neighbourhood function) ------------------
+// Every estimate is 0 or at least 1, hence a multiple of 2^-52 below 2^66:
+// E * 2^52 is an integer below 2^118, and the sum of up to 2^31 of them fits
+// 192 bits.  Integer addition is associative, so the sum does not depend on
+// the reduction order; it is rounded to double once, on the host.
+struct Fix192 {
+  unsigned long long w0, w1, w2;
+};
+
+__device__ __forceinline__ void fix_add(Fix192& a, const Fix192& b) {
+  const unsigned long long s0 = a.w0 + b.w0;
+  const unsigned long long c0 = s0 < a.w0 ? 1ull : 0ull;
+  const unsigned long long s1a = a.w1 + b.w1;
+  const unsigned long long c1a = s1a < a.w1 ? 1ull : 0ull;
+  const unsigned long long s1 = s1a + c0;
+  const unsigned long long c1b = s1 < s1a ? 1ull : 0ull;
+  a.w0 = s0;
+  a.w1 = s1;
+  a.w2 = a.w2 + b.w2 + c1a + c1b;
+}
+
+// E * 2^52 as a 192-bit integer; sets *inexact if E is not a multiple of 2^-52.
+__device__ __forceinline__ Fix192 fix_of(double e, int* inexact) {
+  Fix192 f{0ull, 0ull, 0ull};
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(e);
+  const int ex = (int)((bits >> 52) & 0x7FFull);
+  if (ex == 0) {
+    if (bits != 0ull) *inexact = 1;  // subnormal
+    return f;
+  }
+  const unsigned long long mant = (bits & ((1ull << 52) - 1ull)) | (1ull << 52);
+  const int sh = ex - 1023;  // E * 2^52 = mant * 2^sh
+  if (sh < 0) {
+    if (sh <= -53 || (mant & ((1ull << (-sh)) - 1ull))) *inexact = 1;
+    f.w0 = sh <= -53 ? 0ull : mant >> (-sh);
+  } else if (sh < 64) {
+    f.w0 = mant << sh;
+    f.w1 = sh == 0 ? 0ull : mant >> (64 - sh);
+  } else if (sh < 128) {
+    f.w1 = mant << (sh - 64);
+    f.w2 = sh == 64 ? 0ull : mant >> (128 - sh);
+  } else {
+    *inexact = 1;  // beyond 2^75: not an estimate of any counter
+  }
+  return f;
+}
+
+__global__ __launch_bounds__(256) void k_esum(const double* E, int64_t n, Fix192* partial, int* inexact) {
+  __shared__ Fix192 red[256];
+  Fix192 acc{0ull, 0ull, 0ull};
+  int bad = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+    fix_add(acc, fix_of(E[v], &bad));
+  if (bad) atomicOr(inexact, 1);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) fix_add(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void k_check_weights(const int32_t* w, int64_t n, int* bad) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+    if (w[v] < 1) *bad = 1;
+}
+
+__global__ void k_esum_final(const Fix192* partial, int nblocks, Fix192* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  Fix192 acc{0ull, 0ull, 0ull};
+  for (int b = 0; b < nblocks; ++b) fix_add(acc, partial[b]);
+  *out = acc;
 }
 
 // Ensemble initialisation: as k_init_nodes, with K = 2^seg_log counters per
@@ -1343,6 +1490,33 @@ hipError_t launch_init_nodes(int log2m, int64_t n, uint64_t seed, uint8_t* cur, 
   return hipGetLastError();
 }
 
+hipError_t launch_init_weighted(int log2m, int64_t n, uint64_t seed, const int32_t* w, uint8_t* cur, uint8_t* nxt,
+                                double* S, double* H, double* D, double* E, const double* lc, double alpha_pp,
+                                hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t threads = n * (((int64_t)1 << log2m) / 16);
+  hipLaunchKernelGGL(k_init_weighted, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, log2m, n, seed, w,
+                     cur, nxt);
+  hipLaunchKernelGGL(k_row_estimate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, log2m, n, cur, S, H, D, E,
+                     lc, alpha_pp);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_weights(const int32_t* w, int64_t n, int* bad, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_weights, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, w, n, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_esum(const double* E, int64_t n, uint64_t* partial, int max_blocks, uint64_t* out, int* inexact,
+                       hipStream_t s) {
+  const int blocks = (int)grid_for(n, 256 * 8, max_blocks);
+  Fix192* part = reinterpret_cast<Fix192*>(partial);
+  hipLaunchKernelGGL(k_esum, dim3((unsigned)blocks), dim3(256), 0, s, E, n, part, inexact);
+  hipLaunchKernelGGL(k_esum_final, dim3(1), dim3(64), 0, s, part, blocks, reinterpret_cast<Fix192*>(out));
+  return hipGetLastError();
+}
+
 hipError_t launch_init_ensemble(int log2m, int seg_log, int64_t n, const uint64_t* seeds, uint8_t* cur, uint8_t* nxt,
                                 double* S, double* H, double* E, const double* lc, double alpha_pp, hipStream_t s) {
   if (n == 0) return hipSuccess;
@@ -1361,21 +1535,24 @@ hipError_t launch_ensemble_summary(int64_t n, int k, int which, const double* S,
   return hipGetLastError();
 }
 
-// Ensemble rows (seg_lanes below the lanes of a row): expand and merge.
-hipError_t launch_pass_ens(int log2m, const PassArgs& a, hipStream_t s, hipEvent_t ev_mid) {
+// Expand and merge kernels of one lane-group pass for flavour FL.
+template <int FL>
+hipError_t launch_lanes(int log2m, const PassArgs& a, hipStream_t s, hipEvent_t ev_mid) {
   const int64_t grid = a.n_items + (a.n_medium + 3) / 4 + (a.n_light + 255) / 256;
   const bool q = !(a.mode == MODE_FIRST || a.mode == MODE_DENSE) || a.qdense;
   if (grid > 0) {
     const dim3 g((unsigned)grid), t(256);
     switch (log2m * 2 + (q ? 1 : 0)) {
-      case 10: hipLaunchKernelGGL((k_expand<5, true>), g, t, 0, s, a); break;
-      case 11: hipLaunchKernelGGL((k_expand_q<5, true>), g, t, 0, s, a); break;
-      case 12: hipLaunchKernelGGL((k_expand<6, true>), g, t, 0, s, a); break;
-      case 13: hipLaunchKernelGGL((k_expand_q<6, true>), g, t, 0, s, a); break;
-      case 14: hipLaunchKernelGGL((k_expand<7, true>), g, t, 0, s, a); break;
-      case 15: hipLaunchKernelGGL((k_expand_q<7, true>), g, t, 0, s, a); break;
-      case 16: hipLaunchKernelGGL((k_expand<8, true>), g, t, 0, s, a); break;
-      case 17: hipLaunchKernelGGL((k_expand_q<8, true>), g, t, 0, s, a); break;
+      case 8: hipLaunchKernelGGL((k_expand<4, FL>), g, t, 0, s, a); break;
+      case 9: hipLaunchKernelGGL((k_expand_q<4, FL>), g, t, 0, s, a); break;
+      case 10: hipLaunchKernelGGL((k_expand<5, FL>), g, t, 0, s, a); break;
+      case 11: hipLaunchKernelGGL((k_expand_q<5, FL>), g, t, 0, s, a); break;
+      case 12: hipLaunchKernelGGL((k_expand<6, FL>), g, t, 0, s, a); break;
+      case 13: hipLaunchKernelGGL((k_expand_q<6, FL>), g, t, 0, s, a); break;
+      case 14: hipLaunchKernelGGL((k_expand<7, FL>), g, t, 0, s, a); break;
+      case 15: hipLaunchKernelGGL((k_expand_q<7, FL>), g, t, 0, s, a); break;
+      case 16: hipLaunchKernelGGL((k_expand<8, FL>), g, t, 0, s, a); break;
+      case 17: hipLaunchKernelGGL((k_expand_q<8, FL>), g, t, 0, s, a); break;
       default: return hipErrorInvalidValue;
     }
   }
@@ -1388,10 +1565,11 @@ hipError_t launch_pass_ens(int log2m, const PassArgs& a, hipStream_t s, hipEvent
   if (a.n_hrows > 0) {
     const unsigned mg = (unsigned)((a.n_hrows + 3) / 4);
     switch (log2m) {
-      case 5: hipLaunchKernelGGL((k_merge<5, false, true>), dim3(mg), dim3(256), 0, s, a); break;
-      case 6: hipLaunchKernelGGL((k_merge<6, false, true>), dim3(mg), dim3(256), 0, s, a); break;
-      case 7: hipLaunchKernelGGL((k_merge<7, false, true>), dim3(mg), dim3(256), 0, s, a); break;
-      default: hipLaunchKernelGGL((k_merge<8, false, true>), dim3(mg), dim3(256), 0, s, a); break;
+      case 4: hipLaunchKernelGGL((k_merge<4, false, FL>), dim3(mg), dim3(256), 0, s, a); break;
+      case 5: hipLaunchKernelGGL((k_merge<5, false, FL>), dim3(mg), dim3(256), 0, s, a); break;
+      case 6: hipLaunchKernelGGL((k_merge<6, false, FL>), dim3(mg), dim3(256), 0, s, a); break;
+      case 7: hipLaunchKernelGGL((k_merge<7, false, FL>), dim3(mg), dim3(256), 0, s, a); break;
+      default: hipLaunchKernelGGL((k_merge<8, false, FL>), dim3(mg), dim3(256), 0, s, a); break;
     }
   }
   return hipGetLastError();
@@ -1399,43 +1577,12 @@ hipError_t launch_pass_ens(int log2m, const PassArgs& a, hipStream_t s, hipEvent
 
 hipError_t launch_pass(int log2m, const PassArgs& a, hipStream_t s, hipEvent_t ev_mid) {
   if (a.n_blocks == 0) return hipSuccess;
-  if (log2m <= 8 && a.seg_lanes > 0 && a.seg_lanes < (1 << log2m) / 16) return launch_pass_ens(log2m, a, s, ev_mid);
   if (log2m <= 8) {
-    const int64_t grid = a.n_items + (a.n_medium + 3) / 4 + (a.n_light + 255) / 256;
-    const bool q = !(a.mode == MODE_FIRST || a.mode == MODE_DENSE) || a.qdense;
-    if (grid > 0) {
-      const dim3 g((unsigned)grid), t(256);
-      switch (log2m * 2 + (q ? 1 : 0)) {
-        case 8: hipLaunchKernelGGL(k_expand<4>, g, t, 0, s, a); break;
-        case 9: hipLaunchKernelGGL(k_expand_q<4>, g, t, 0, s, a); break;
-        case 10: hipLaunchKernelGGL(k_expand<5>, g, t, 0, s, a); break;
-        case 11: hipLaunchKernelGGL(k_expand_q<5>, g, t, 0, s, a); break;
-        case 12: hipLaunchKernelGGL(k_expand<6>, g, t, 0, s, a); break;
-        case 13: hipLaunchKernelGGL(k_expand_q<6>, g, t, 0, s, a); break;
-        case 14: hipLaunchKernelGGL(k_expand<7>, g, t, 0, s, a); break;
-        case 15: hipLaunchKernelGGL(k_expand_q<7>, g, t, 0, s, a); break;
-        case 16: hipLaunchKernelGGL(k_expand<8>, g, t, 0, s, a); break;
-        default: hipLaunchKernelGGL(k_expand_q<8>, g, t, 0, s, a); break;
-      }
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (ev_mid) {
-      e = hipEventRecord(ev_mid, s);
-      if (e != hipSuccess) return e;
-    }
-    if (a.n_hrows > 0) {
-      const unsigned mg = (unsigned)((a.n_hrows + 3) / 4);
-      switch (log2m) {
-        case 4: hipLaunchKernelGGL((k_merge<4, false>), dim3(mg), dim3(256), 0, s, a); break;
-        case 5: hipLaunchKernelGGL((k_merge<5, false>), dim3(mg), dim3(256), 0, s, a); break;
-        case 6: hipLaunchKernelGGL((k_merge<6, false>), dim3(mg), dim3(256), 0, s, a); break;
-        case 7: hipLaunchKernelGGL((k_merge<7, false>), dim3(mg), dim3(256), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_merge<8, false>), dim3(mg), dim3(256), 0, s, a); break;
-      }
-    }
-    return hipGetLastError();
+    if (a.seg_lanes > 0 && a.seg_lanes < (1 << log2m) / 16) return launch_lanes<FL_ENS>(log2m, a, s, ev_mid);
+    if (a.D) return launch_lanes<FL_DISC>(log2m, a, s, ev_mid);
+    return launch_lanes<FL_PLAIN>(log2m, a, s, ev_mid);
   }
+  if (a.D) return hipErrorInvalidValue;  // discounted sums need the lane-group kernels
   const size_t lds = (size_t)1 << log2m;
   if (lds > 32768) {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_expand_wide),

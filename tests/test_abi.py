@@ -114,3 +114,19 @@ def test_ensemble_argument_errors():
     with pytest.raises(hb.HBError) as e:
         hb.Ensemble(np.array([0, 1, 3], dtype=np.int64), idx, 4, [1, 2])    # offsets[n] != m
     assert e.value.status == hb.HB_EINVAL
+
+
+def test_distance_stats_equal_oracle():
+    """hb_distance_stats is host arithmetic: equal to the oracle's bit for bit."""
+    import oracle
+    import paper_1308_2144_amd as hb
+
+    rng = np.random.default_rng(8)
+    for T in (1, 2, 5, 17, 60):
+        N = np.cumsum(rng.lognormal(3.0, 1.0, size=T))
+        for alpha in (0.5, 0.9, 0.99):
+            got, ref = hb.hb_distance_stats(N, alpha), oracle.distance_stats(N, alpha)
+            assert got == ref
+    assert hb.hb_distance_stats([5.0]) == oracle.distance_stats([5.0])
+    with pytest.raises(hb.HBError):
+        hb.hb_distance_stats([])
