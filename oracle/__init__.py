@@ -188,6 +188,9 @@ def run_ext(offsets, indices, b: int, seed: int, max_passes: int = 0, weights=No
         raise ValueError("need one weight >= 1 per node")
     f = None if discount is None else np.ascontiguousarray(discount, dtype=np.float64)
     rows = cap + 1 if trace else 0
+    if trace and rows * max(n, 1) > (1 << 25):
+        # large graph: learn the pass count first, then trace exactly that many rows
+        rows = run_ext(offsets, indices, b, seed, max_passes=max_passes, weights=weights)["passes"] + 1
     et = np.zeros((max(rows, 1), max(n, 1))) if trace else None
     passes = ctypes.c_int(0)
     rc = _load().hbo_run_ext(n, _p(o), _p(i), b, seed, max_passes, None if w is None else _p(w),
