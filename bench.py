@@ -282,6 +282,55 @@ def bench_ensemble(args, torch, hb, K: int = 8, b: int = 4, steps: int = 3):
             "identical": bool(same)}
 
 
+def bench_extensions(args, torch, hb, steps: int = 3):
+    """Cost of node weights (1..4), the logarithmic discount and the
+    neighbourhood function on R-MAT scale 20 (edge factor 16, transposed,
+    log2m 6), against the plain computation; inputs resident, each step =
+    reset + passes + centralities (+ discounted sums and N(t))."""
+    w = WORKLOADS["rmat-s20"]
+    off, idx = make_graph(w)
+    n, m = len(off) - 1, len(idx)
+    dev = torch.device("cuda:0")
+    o = torch.from_numpy(off.astype(np.int32)).to(dev)
+    x = torch.from_numpy(idx).to(dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    outs = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(5)]
+    weights = torch.from_numpy(np.random.default_rng(9).integers(1, 5, size=n).astype(np.int32)).to(dev)
+    res = {}
+    for name in ("plain", "extended"):
+        ext = name == "extended"
+        g = hb.HyperBall(o, x, w["log2m"], 42, stream=stream, neighbourhood=int(ext))
+        if ext:
+            g.set_weights(weights)
+            g.set_discount(hb.discount_table("logarithmic", 64))
+
+        def step():
+            g.reset(42)
+            p = g.run()
+            hb.hb_centralities(g._ctx, *outs[:4], True)
+            if ext:
+                hb.hb_get_discounted(g._ctx, outs[4], True)
+                hb.hb_neighbourhood(g._ctx)
+            return p
+
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            passes = step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        res[name] = {"ms": dt * 1e3, "passes": passes, "edge_visits_per_s": m * passes / dt}
+        if ext:
+            N = g.neighbourhood()
+            res[name]["N_last"] = float(N[-1])
+            res[name]["distance_stats"] = hb.hb_distance_stats(N)
+        g.close()
+    return {"workload": "R-MAT scale 20, edge factor 16, transposed, log2m=6; extended = node weights "
+                        "uniform in 1..4 + logarithmic discount + neighbourhood function",
+            **res, "overhead": res["extended"]["ms"] / res["plain"]["ms"] - 1.0}
+
+
 class PinnedArena:
     """First-fit allocator over one pinned host buffer (result buffers of
     served requests, so that their copies run asynchronously)."""
@@ -478,6 +527,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the multi-seed ensemble measurement")
     ap.add_argument("--ensemble-only", action="store_true", help="only the ensemble measurement (its own line)")
+    ap.add_argument("--no-extensions", action="store_true", help="skip the weights/discount/N(t) measurement")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1308_2144_amd", "tune_cache.txt"),
                     help="autotuner cache of the batched form ('' for none: tune every run)")
     ap.add_argument("--batch-only", action="store_true", help="only the batched measurement (its own line)")
@@ -599,6 +649,10 @@ def main():
     if not args.no_batch:
         log("batched form ...")
         out["batched"] = bench_batch(args, torch, hb)
+        torch.cuda.empty_cache()
+    if not args.no_extensions:
+        log("weights, discount, neighbourhood function ...")
+        out["extensions"] = bench_extensions(args, torch, hb)
         torch.cuda.empty_cache()
     if not args.no_ensemble:
         log("multi-seed ensemble ...")
