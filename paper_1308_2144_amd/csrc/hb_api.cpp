@@ -149,12 +149,12 @@ double fix_to_double(const uint64_t* w) {
   return std::ldexp((double)mant, e);
 }
 
-// Enqueues the exact sum of the current estimates and its readback.
+// Enqueues the exact sum of the current estimates and its readback
+// (esum_out: 3 sum words, the inexact flag, and the zeroed flag word the
+// kernels use).
 hipError_t enqueue_esum(hb_ctx* c) {
-  hipError_t e = hb::launch_fill_zero(c->esum_out + 3, sizeof(uint64_t), c->stream);
-  if (e == hipSuccess)
-    e = hb::launch_esum(c->E, c->n, c->esum_part, ESUM_BLOCKS, c->esum_out, reinterpret_cast<int*>(c->esum_out + 3),
-                        c->stream);
+  hipError_t e = hb::launch_esum(c->E, c->n, c->esum_part, ESUM_BLOCKS, c->esum_out,
+                                 reinterpret_cast<int*>(c->esum_out + 4), c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->esum_host, c->esum_out, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream);
   return e;
@@ -349,7 +349,8 @@ hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, co
   if (c->n_seeds > 1) HB_HIP(dmalloc(&c->seeds_dev, (size_t)c->n_seeds));
   if (c->opt.neighbourhood && !blk_graph && c->n_seeds == 1) {
     HB_HIP(dmalloc(&c->esum_part, (size_t)3 * ESUM_BLOCKS));
-    HB_HIP(dmalloc(&c->esum_out, 4));
+    HB_HIP(dmalloc(&c->esum_out, 5));
+    HB_HIP(hb::launch_fill_zero(c->esum_out, 5 * sizeof(uint64_t), c->stream));
     HB_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->esum_host), 4 * sizeof(uint64_t), hipHostMallocDefault));
   }
   HB_HIP(dmalloc(&c->partial, (size_t)c->n_items * (size_t)c->p));

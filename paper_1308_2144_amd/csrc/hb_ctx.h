@@ -60,7 +60,7 @@ struct hb_ctx {
   // Neighbourhood function N(0..t) (opt.neighbourhood) and its exact-sum scratch.
   std::vector<double> nf;
   uint64_t* esum_part = nullptr;
-  uint64_t* esum_out = nullptr;  // 3 words + the inexact flag word
+  uint64_t* esum_out = nullptr;  // 3 sum words, the reported inexact flag, the kernels' flag word
   uint64_t* esum_host = nullptr; // pinned copy of esum_out
   uint64_t seed = 0;
   hb_options opt{};

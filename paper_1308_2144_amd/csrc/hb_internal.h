@@ -151,8 +151,10 @@ hipError_t launch_init_weighted(int log2m, int64_t n, uint64_t seed, const int32
 // Sets *bad to 1 if some w[v] < 1.
 hipError_t launch_check_weights(const int32_t* w, int64_t n, int* bad, hipStream_t s);
 // Exact sum of E[0..n) as a 192-bit integer E * 2^52 (three words, low
-// first) into out; partial holds 3 * max_blocks words of scratch; *inexact
-// becomes 1 if an E is not a multiple of 2^-52 (never for counter estimates).
+// first) into out[0..2]; out[3] becomes 1 if an E is not a multiple of 2^-52
+// (never for counter estimates).  partial holds 3 * max_blocks words of
+// scratch; *inexact is a flag word that must be zero before the first sum
+// (each sum leaves it zero).
 hipError_t launch_esum(const double* E, int64_t n, uint64_t* partial, int max_blocks, uint64_t* out, int* inexact,
                        hipStream_t s);
 // Ensemble initialisation: rows of K = 2^seg_log counters of p = 2^log2m

@@ -1090,11 +1090,25 @@ __global__ void k_check_weights(const int32_t* w, int64_t n, int* bad) {
     if (w[v] < 1) *bad = 1;
 }
 
-__global__ void k_esum_final(const Fix192* partial, int nblocks, Fix192* out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Sums the block partials; out[3] receives the inexact flag, which is
+// cleared for the next sum.
+__global__ __launch_bounds__(256) void k_esum_final(const Fix192* partial, int nblocks, uint64_t* out, int* inexact) {
+  __shared__ Fix192 red[256];
   Fix192 acc{0ull, 0ull, 0ull};
-  for (int b = 0; b < nblocks; ++b) fix_add(acc, partial[b]);
-  *out = acc;
+  for (int b = (int)threadIdx.x; b < nblocks; b += (int)blockDim.x) fix_add(acc, partial[b]);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) fix_add(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = red[0].w0;
+    out[1] = red[0].w1;
+    out[2] = red[0].w2;
+    out[3] = (uint64_t)(*inexact != 0 ? 1 : 0);
+    *inexact = 0;
+  }
 }
 
 // Ensemble initialisation: as k_init_nodes, with K = 2^seg_log counters per
@@ -1513,7 +1527,7 @@ hipError_t launch_esum(const double* E, int64_t n, uint64_t* partial, int max_bl
   const int blocks = (int)grid_for(n, 256 * 8, max_blocks);
   Fix192* part = reinterpret_cast<Fix192*>(partial);
   hipLaunchKernelGGL(k_esum, dim3((unsigned)blocks), dim3(256), 0, s, E, n, part, inexact);
-  hipLaunchKernelGGL(k_esum_final, dim3(1), dim3(64), 0, s, part, blocks, reinterpret_cast<Fix192*>(out));
+  hipLaunchKernelGGL(k_esum_final, dim3(1), dim3(256), 0, s, part, blocks, out, inexact);
   return hipGetLastError();
 }
 
