@@ -476,11 +476,12 @@ __device__ __forceinline__ RowPre preload(const PassArgs& A, int64_t row, int gl
 
 // Completes row `row` for a group of G lanes: a = own U gathered, write-back
 // rule, change detection, the fused estimator/accumulator, the change bit
-// and the mask of changed slices.  In an ensemble row (FL_ENS) every seed's
+// and the mask of changed slices (with DEFER the caller sets the change bit,
+// see set_change_bits).  In an ensemble row (FL_ENS) every seed's
 // counter gets its own estimator and accumulators, and the row's change bit
 // is set if any of them changed; FL_DISC also accumulates the discounted sum
 // D += f(t+1) * delta.  Returns whether the row changed.
-template <int B, bool MG, int FL = FL_PLAIN>
+template <int B, bool MG, int FL = FL_PLAIN, bool DEFER = false>
 __device__ __forceinline__ bool finish_row(const PassArgs& A, int64_t row, uint4 acc, bool got,
                                            const RowPre& pre, bool own_mod, int gl, int grp,
                                            Counts& c) {
@@ -530,7 +531,7 @@ __device__ __forceinline__ bool finish_row(const PassArgs& A, int64_t row, uint4
     }
     if (changed && gl == 0) {
       if (A.dmask_cur) A.dmask_cur[row] = (uint16_t)msk;
-      atomicOr(A.mod_cur + (row >> 6), 1ull << (row & 63));
+      if (!DEFER) atomicOr(A.mod_cur + (row >> 6), 1ull << (row & 63));
     }
   } else if (changed) {
     const Parts pr = reg_parts(a);
@@ -551,7 +552,7 @@ __device__ __forceinline__ bool finish_row(const PassArgs& A, int64_t row, uint4
       if constexpr (FL == FL_DISC) st_stream(A.D + row, pre.dd + A.disc_f * delta);
       st_stream(A.E + row, En);
       if (A.dmask_cur) A.dmask_cur[row] = (uint16_t)msk;
-      atomicOr(A.mod_cur + (row >> 6), 1ull << (row & 63));
+      if (!DEFER) atomicOr(A.mod_cur + (row >> 6), 1ull << (row & 63));
     }
   }
   return changed;
@@ -585,6 +586,30 @@ __device__ __forceinline__ void flush_counts(const PassArgs& A, Counts c, int64_
 
 __device__ __forceinline__ uint64_t lanes_below(int lane) { return (1ull << lane) - 1ull; }
 
+// Sets the change bits of the rows whose leader lanes have `has` set, one
+// device-scope atomic per distinct bitmap word instead of one per row (the
+// rows of a light-row round are consecutive list entries, mostly in one or
+// two words).  Must be called by the whole wavefront.
+__device__ __forceinline__ void set_change_bits(uint64_t* mod_cur, int64_t row, bool has, int lane) {
+  uint64_t pending = __ballot(has);
+  const int64_t word = row >> 6;
+  const uint64_t bit = 1ull << (row & 63);
+  while (pending) {
+    const int first = __ffsll((long long)pending) - 1;
+    const int64_t w0 = __shfl(word, first);
+    const bool mine = has && word == w0;
+    uint32_t lo = mine ? (uint32_t)bit : 0u;
+    uint32_t hi = mine ? (uint32_t)(bit >> 32) : 0u;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      lo |= __shfl_xor(lo, o);
+      hi |= __shfl_xor(hi, o);
+    }
+    if (lane == first) atomicOr(mod_cur + w0, ((uint64_t)hi << 32) | lo);
+    pending &= ~__ballot(mine);
+  }
+}
+
 // 64 consecutive entries of the light-row list per wavefront; entry
 // q*W + grp goes to lane group grp in round q.
 template <int B, bool Q, bool MG, int FL = FL_PLAIN>
@@ -614,6 +639,7 @@ __device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, int64_t 
       const int64_t rrow = __shfl(row, rl);
       const int64_t rs = __shfl(s, rl);
       const int64_t rd = __shfl(deg, rl);
+      bool chg = false;
       if ((needs >> rl) & 1ull) {
         const bool rmod = ((mods >> rl) & 1ull) != 0ull;
         const RowPre pre = preload<B, FL>(A, rrow, gl);
@@ -624,8 +650,13 @@ __device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, int64_t 
         else
           acc = gather<B>(A, rs, rs + rd, 1, gl, got, c);
         if (gl == 0) c.arcs += (uint32_t)rd;
-        finish_row<B, MG, FL>(A, rrow, acc, got, pre, rmod, gl, grp, c);
+        // Multi-graph passes run many short rows per byte moved, so there the
+        // change bits of a round are combined into one atomic per bitmap
+        // word; single-graph kernels keep one atomic per row (fewer live
+        // registers).
+        chg = finish_row<B, MG, FL, MG>(A, rrow, acc, got, pre, rmod, gl, grp, c);
       }
+      if constexpr (MG) set_change_bits(A.mod_cur, rrow, chg && gl == 0, lane);
     }
   }
   flush_counts<FL>(A, c, lw, lane);
@@ -743,6 +774,18 @@ __device__ __forceinline__ bool queued_mode(const PassArgs& A) {
 #else
 #define HB_EXPAND_ATTR __launch_bounds__(256)
 #endif
+// Waves per SIMD the persistent (multi-graph) expand kernel is compiled for:
+// it holds more state than the grid kernels (work cursor, graph lookups), and
+// at 4 waves its 128 registers avoid the spills it has at 5 (measured 15 %
+// faster on the 4096-graph batch).
+#ifndef HB_PERSIST_WAVES
+#define HB_PERSIST_WAVES 4
+#endif
+#if HB_PERSIST_WAVES > 0
+#define HB_PERSIST_ATTR __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HB_PERSIST_WAVES)))
+#else
+#define HB_PERSIST_ATTR __launch_bounds__(256)
+#endif
 
 template <int B, int FL = FL_PLAIN>
 __global__ HB_EXPAND_ATTR void k_expand(PassArgs A) {
@@ -760,7 +803,7 @@ __global__ HB_EXPAND_ATTR void k_expand_q(PassArgs A) {
 // forms are launched every pass; the one that does not match the pass mode
 // returns at once.
 template <int B, bool Q>
-__global__ HB_EXPAND_ATTR void k_expand_p(PassArgs A0) {
+__global__ HB_PERSIST_ATTR void k_expand_p(PassArgs A0) {
   const PassArgs A = resolve(A0);
   if (queued_mode(A) != Q) return;
   __shared__ QEnt qbuf[Q ? 4 : 1][Q ? QCAP : 1];
