@@ -15,7 +15,8 @@ Parity status of every function (pins live in ``tests/test_oracle_*.py``):
 * ``run``                    - pinned: registers equal the HyperLogLog state of
   breadth-first balls (computed with scipy), termination count, closed-form
   accumulators on cycles, paths, stars, complete graphs in the exact regime.
-* ``node``                   - pinned: agrees with ``run`` and with closed forms.
+* ``node``                   - pinned: agrees with ``run`` and with closed forms;
+  with weights and a discount table it agrees with ``run_ext`` bit for bit.
 * ``finalize``               - pinned: closed forms on the same graphs.
 * ``run_ext``                - ``run`` with Sec. 6 node weights (replicas),
   a Sec. 7 discount accumulator and the per-pass estimate trace; pinned:
@@ -84,6 +85,8 @@ def _load():
         L.hbo_finalize.restype = None
         L.hbo_node.argtypes = [i64, vp, vp, ci, u64, i64, ci, vp, vp, vp, vp, vp]
         L.hbo_node.restype = ci
+        L.hbo_node_ext.argtypes = [i64, vp, vp, ci, u64, i64, ci, vp, vp, ci, vp, vp, vp, vp, vp, vp]
+        L.hbo_node_ext.restype = ci
         _lib = L
     return _lib
 
@@ -249,24 +252,33 @@ def finalize(regs: np.ndarray, b: int, S: np.ndarray, H: np.ndarray):
     return dict(closeness=clo, lin=lin, harmonic=harm, coreach=core)
 
 
-def node(offsets, indices, b: int, seed: int, x: int, radius: int = -1):
-    """Per-node evaluation from breadth-first balls.
+def node(offsets, indices, b: int, seed: int, x: int, radius: int = -1, weights=None, discount=None):
+    """Per-node evaluation from breadth-first balls (with optional node
+    weights and discount table, as in run_ext).
 
     Returns dict(regs (registers of B(x, radius), or of the reachable set when
-    radius < 0), S, H, last_change, ecc).
+    radius < 0), S, H, D (with a discount), last_change, ecc).
     """
     o, i = _csr(offsets, indices)
     n = o.shape[0] - 1
     regs = new_counter(b)
     S = ctypes.c_double(0.0)
     H = ctypes.c_double(0.0)
+    D = ctypes.c_double(0.0)
     last = ctypes.c_int(0)
     ecc = ctypes.c_int(0)
-    rc = _load().hbo_node(n, _p(o), _p(i), b, seed, x, radius, _p(regs), ctypes.byref(S),
-                          ctypes.byref(H), ctypes.byref(last), ctypes.byref(ecc))
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.int32)
+    f = None if discount is None else np.ascontiguousarray(discount, dtype=np.float64)
+    rc = _load().hbo_node_ext(n, _p(o), _p(i), b, seed, x, radius, None if w is None else _p(w),
+                              None if f is None else _p(f), 0 if f is None else f.shape[0], _p(regs),
+                              ctypes.byref(S), ctypes.byref(H), ctypes.byref(D), ctypes.byref(last),
+                              ctypes.byref(ecc))
     if rc != 0:
         raise RuntimeError("oracle node evaluation failed")
-    return dict(regs=regs, S=S.value, H=H.value, last_change=last.value, ecc=ecc.value)
+    out = dict(regs=regs, S=S.value, H=H.value, last_change=last.value, ecc=ecc.value)
+    if f is not None:
+        out["D"] = D.value
+    return out
 
 
 def ensemble(offsets, indices, b: int, seeds, max_passes: int = 0):

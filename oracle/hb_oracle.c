@@ -227,10 +227,16 @@ void hbo_finalize(int64_t n, const uint8_t* regs, int b, const double* S, const 
  * pass does).  ecc: the eccentricity of x (largest finite distance).
  * Returns 0, or -1 on bad arguments / allocation failure.
  */
-int hbo_node(int64_t n, const int64_t* offsets, const int32_t* indices, int b, uint64_t seed,
-             int64_t x, int radius, uint8_t* regs_at, double* S, double* H, int* last_change,
-             int* ecc) {
+/* One node from breadth-first balls: the counter of x after t passes is the
+ * HyperLogLog state of B(x, t) (of the replicas of its nodes when weights
+ * are given), so S, H and D follow from the ball sizes layer by layer.
+ * weights / disc as in hbo_run_ext (nullable).  regs_at receives the
+ * registers at `radius` (< 0: at convergence). */
+int hbo_node_ext(int64_t n, const int64_t* offsets, const int32_t* indices, int b, uint64_t seed, int64_t x,
+                 int radius, const int32_t* weights, const double* disc, int disc_len, uint8_t* regs_at, double* S,
+                 double* H, double* D, int* last_change, int* ecc) {
   if (x < 0 || x >= n || b < 4 || b > 16) return -1;
+  if (disc && disc_len < 1) return -1;
   int p = 1 << b;
   uint8_t* seen = (uint8_t*)calloc((size_t)n, 1);
   int32_t* queue = (int32_t*)malloc((size_t)n * sizeof(int32_t));
@@ -240,10 +246,13 @@ int hbo_node(int64_t n, const int64_t* offsets, const int32_t* indices, int b, u
     free(seen); free(queue); free(cur); free(nxt);
     return -1;
   }
-  double s = 0.0, h = 0.0;
+  double s = 0.0, h = 0.0, dsum = 0.0;
   int last = 0;
   /* B(x, 0) = {x}. */
-  hbo_add(cur, b, (uint64_t)x, seed);
+  {
+    const int64_t w = weights ? weights[x] : 1;
+    for (int64_t j = 0; j < w; ++j) hbo_add(cur, b, replica_item(x, j), seed);
+  }
   seen[x] = 1;
   queue[0] = (int32_t)x;
   int64_t layer_begin = 0, layer_end = 1, tail = 1;
@@ -263,11 +272,16 @@ int hbo_node(int64_t n, const int64_t* offsets, const int32_t* indices, int b, u
     }
     if (tail == layer_end) break; /* the ball stops growing: no later pass changes x */
     memcpy(nxt, cur, (size_t)p);
-    for (int64_t q = layer_end; q < tail; ++q) hbo_add(nxt, b, (uint64_t)queue[q], seed);
+    for (int64_t q = layer_end; q < tail; ++q) {
+      const int64_t y = queue[q];
+      const int64_t w = weights ? weights[y] : 1;
+      for (int64_t j = 0; j < w; ++j) hbo_add(nxt, b, replica_item(y, j), seed);
+    }
     double delta = hbo_size(nxt, b) - hbo_size(cur, b);
     double d = (double)(t + 1);
     s = s + d * delta;
     h = h + delta / d;
+    if (disc) dsum = dsum + disc[t + 1 <= disc_len ? t : disc_len - 1] * delta;
     if (memcmp(nxt, cur, (size_t)p) != 0) last = t + 1;
     memcpy(cur, nxt, (size_t)p);
     layer_begin = layer_end;
@@ -278,8 +292,15 @@ int hbo_node(int64_t n, const int64_t* offsets, const int32_t* indices, int b, u
   if (regs_at && (radius < 0 || radius > t)) memcpy(regs_at, cur, (size_t)p);
   if (S) *S = s;
   if (H) *H = h;
+  if (D) *D = dsum;
   if (last_change) *last_change = last;
   if (ecc) *ecc = t;
   free(seen); free(queue); free(cur); free(nxt);
   return 0;
+}
+
+int hbo_node(int64_t n, const int64_t* offsets, const int32_t* indices, int b, uint64_t seed,
+             int64_t x, int radius, uint8_t* regs_at, double* S, double* H, int* last_change,
+             int* ecc) {
+  return hbo_node_ext(n, offsets, indices, b, seed, x, radius, NULL, NULL, 0, regs_at, S, H, NULL, last_change, ecc);
 }

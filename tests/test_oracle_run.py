@@ -323,3 +323,15 @@ def test_distance_stats_closed_forms(orc):
     assert abs(st["average_distance"] - n / 2) < 1e-12
     assert abs(st["effective_diameter"] - (0.9 * n - 1)) < 1e-12
     assert orc.distance_stats([7.0])["effective_diameter"] == 0.0     # no arcs
+
+
+def test_node_ext_matches_run_ext_bitwise(orc, gg):
+    table = [1.0 / math.log2(d + 1) for d in range(1, 20)]
+    for name, (o, i) in small_graphs(gg):
+        n = o.shape[0] - 1
+        w = np.random.default_rng(n).integers(1, 6, size=n).astype(np.int32)
+        r = orc.run_ext(o, i, 6, 21, weights=w, discount=table)
+        for x in range(0, n, max(1, n // 7)):
+            q = orc.node(o, i, 6, 21, x, weights=w, discount=table)
+            assert np.array_equal(q["regs"], r["regs"][x]), (name, x)
+            assert q["S"] == r["S"][x] and q["H"] == r["H"][x] and q["D"] == r["D"][x], (name, x)
