@@ -184,7 +184,9 @@ hb_status hb_stats(hb_ctx* c, hb_stats_t* s);
  *   arcs_scanned       successor ids read (every arc of every row the pass runs)
  *   counters_gathered  successors whose counter (or part of it) was read
  *   slices_gathered    16-byte counter slices read for them
- *   rows_loaded        rows the pass ran (own counter read)
+ *   rows_loaded        rows whose own counter the pass read (in edge, slice and
+ *                      sparse passes only rows with a changed successor or a
+ *                      counter changed in the previous pass)
  *   rows_written       counters written into the next buffer
  *   rows_changed       counters that changed (= n_modified)
  *   slices_changed     16-byte slices that changed

@@ -586,6 +586,15 @@ __device__ __forceinline__ void flush_counts(const PassArgs& A, Counts c, int64_
 
 __device__ __forceinline__ uint64_t lanes_below(int lane) { return (1ull << lane) - 1ull; }
 
+// Whether a row reads its own counter only after its gather found a changed
+// successor: in the queued passes that gather changed successors only, for
+// rows whose counter did not change in the previous pass (such a row with no
+// changed successor cannot change and needs no write).
+template <bool Q>
+__device__ __forceinline__ bool lazy_row(const PassArgs& A, bool own_mod) {
+  return Q && !own_mod && A.mode != MODE_FIRST && A.mode != MODE_DENSE;
+}
+
 // Sets the change bits of the rows whose leader lanes have `has` set, one
 // device-scope atomic per distinct bitmap word instead of one per row (the
 // rows of a light-row round are consecutive list entries, mostly in one or
@@ -642,7 +651,13 @@ __device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, int64_t 
       bool chg = false;
       if ((needs >> rl) & 1ull) {
         const bool rmod = ((mods >> rl) & 1ull) != 0ull;
-        const RowPre pre = preload<B, FL>(A, rrow, gl);
+        // In passes that gather only changed successors, a row that finds
+        // none and did not change before is left as it is, so its own
+        // counter and accumulators are read only once a changed successor
+        // turned up (most rows of a sparse tail find none).
+        const bool lazy = lazy_row<Q>(A, rmod);
+        RowPre pre;
+        if (!lazy) pre = preload<B, FL>(A, rrow, gl);
         bool got = false;
         uint4 acc;
         if constexpr (Q)
@@ -650,11 +665,12 @@ __device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, int64_t 
         else
           acc = gather<B>(A, rs, rs + rd, 1, gl, got, c);
         if (gl == 0) c.arcs += (uint32_t)rd;
+        if (lazy && got) pre = preload<B, FL>(A, rrow, gl);
         // Multi-graph passes run many short rows per byte moved, so there the
         // change bits of a round are combined into one atomic per bitmap
         // word; single-graph kernels keep one atomic per row (fewer live
         // registers).
-        chg = finish_row<B, MG, FL, MG>(A, rrow, acc, got, pre, rmod, gl, grp, c);
+        if (!lazy || got) chg = finish_row<B, MG, FL, MG>(A, rrow, acc, got, pre, rmod, gl, grp, c);
       }
       if constexpr (MG) set_change_bits(A.mod_cur, rrow, chg && gl == 0, lane);
     }
@@ -678,8 +694,9 @@ __device__ __forceinline__ void medium_wave(const PassArgs& A, QEnt* qw, int64_t
   row_flags<MG>(A, row, own_mod, need);
   Counts c{};
   if (need) {
+    const bool lazy = lazy_row<Q>(A, own_mod);  // as in light_wave
     RowPre pre;
-    if (grp == 0) pre = preload<B, FL>(A, row, gl);
+    if (grp == 0 && !lazy) pre = preload<B, FL>(A, row, gl);
     bool got = false;
     uint4 acc;
     if constexpr (Q)
@@ -690,7 +707,8 @@ __device__ __forceinline__ void medium_wave(const PassArgs& A, QEnt* qw, int64_t
 #pragma unroll
     for (int o = G; o < 64; o <<= 1) acc = bmax(acc, shfl_xor4(acc, o));
     got = __ballot(got) != 0ull;
-    if (grp == 0) finish_row<B, MG, FL>(A, row, acc, got, pre, own_mod, gl, 0, c);
+    if (grp == 0 && lazy && got) pre = preload<B, FL>(A, row, gl);
+    if (grp == 0 && (!lazy || got)) finish_row<B, MG, FL>(A, row, acc, got, pre, own_mod, gl, 0, c);
   }
   flush_counts<FL>(A, c, mi, lane);
 }

@@ -189,7 +189,9 @@ def test_pass_counters():
         assert a["mode"] == (0 if t == 0 else 2) and c["mode"] == (0 if t == 0 else 3)
         assert b_["arcs_scanned"] == m and b_["counters_gathered"] == m and b_["rows_loaded"] == nonempty
         assert b_["slices_gathered"] == m * G
-        assert c["arcs_scanned"] == m and c["rows_loaded"] == nonempty
+        # slice passes scan every row but read a row's own counter only when a
+        # changed slice turned up or the row changed before
+        assert c["arcs_scanned"] == m and c["rows_changed"] <= c["rows_loaded"] <= nonempty
         assert c["slices_gathered"] <= G * c["counters_gathered"] and c["counters_gathered"] <= m
         assert a["arcs_scanned"] <= m and a["counters_gathered"] <= a["arcs_scanned"]
         assert a["rows_changed"] == b_["rows_changed"] == c["rows_changed"]
