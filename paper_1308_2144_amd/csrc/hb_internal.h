@@ -198,9 +198,9 @@ hipError_t launch_widen_offsets(const int32_t* in, int64_t* out, int64_t count, 
 hipError_t launch_validate(const int64_t* off, const int32_t* idx, int64_t n, int64_t m,
                            int* bad, hipStream_t s);
 
-// Reverse CSR (row w lists every v with an arc v->w).  roff: n+1 entries,
-// ridx: m entries.  Needs n+1 scratch counters (zeroed here) and hipcub scan
-// storage; both are allocated and freed inside.
+// Reverse CSR (row w lists every v with an arc v->w, in increasing v).
+// roff: n+1 entries, ridx: m entries.  Radix-sorts the arcs by target; the
+// sort's scratch (2m int32 and hipcub storage) is allocated and freed inside.
 hipError_t build_reverse(const int64_t* off, const int32_t* idx, int64_t n, int64_t m, int64_t* roff,
                          int32_t* ridx, hipStream_t s);
 // Marks act[v] = epoch for every v with an arc to a node whose bit is set in

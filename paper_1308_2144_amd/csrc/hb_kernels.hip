@@ -1261,23 +1261,31 @@ __global__ void k_validate(const int64_t* off, const int32_t* idx, int64_t n, in
 
 // --- reverse CSR and push activation ---------------------------------------
 
-__global__ void k_count_in(const int32_t* idx, int64_t m, unsigned long long* cnt) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride)
-    atomicAdd(cnt + idx[e], 1ull);
-}
-
-// One wavefront per row (grid-stride): every arc v->w appends v to row w.
-__global__ void k_scatter_rev(const int64_t* off, const int32_t* idx, int64_t n,
-                              unsigned long long* cursor, int32_t* ridx) {
+// Reverse CSR by sorting: the arcs (v -> w) as (key w, value v) pairs are
+// radix-sorted by w, which lists the predecessors of each node in increasing
+// order; k_arc_rows makes the values, k_lower_bound the offsets.
+__global__ void k_arc_rows(const int64_t* off, int64_t n, int32_t* rows) {
   const int lane = threadIdx.x & 63;
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
   for (int64_t v = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); v < n; v += nw) {
     const int64_t e1 = off[v + 1];
-    for (int64_t e = off[v] + lane; e < e1; e += 64) {
-      const unsigned long long pos = atomicAdd(cursor + idx[e], 1ull);
-      ridx[pos] = (int32_t)v;
+    for (int64_t e = off[v] + lane; e < e1; e += 64) rows[e] = (int32_t)v;
+  }
+}
+
+// roff[w] = number of sorted keys below w, for w = 0..n.
+__global__ void k_lower_bound(const int32_t* keys, int64_t m, int64_t n, int64_t* roff) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w <= n; w += stride) {
+    int64_t lo = 0, hi = m;
+    while (lo < hi) {
+      const int64_t mid = lo + ((hi - lo) >> 1);
+      if ((int64_t)keys[mid] < w)
+        lo = mid + 1;
+      else
+        hi = mid;
     }
+    roff[w] = lo;
   }
 }
 
@@ -1694,34 +1702,34 @@ hipError_t launch_validate(const int64_t* off, const int32_t* idx, int64_t n, in
 
 hipError_t build_reverse(const int64_t* off, const int32_t* idx, int64_t n, int64_t m, int64_t* roff,
                          int32_t* ridx, hipStream_t s) {
-  unsigned long long* cnt = nullptr;
+  if (m == 0) return launch_fill_zero(roff, sizeof(int64_t) * (size_t)(n + 1), s);
+  if (m > 0x7fffffffLL) return hipErrorInvalidValue;
+  int32_t* rows = nullptr;
+  int32_t* keys = nullptr;
   void* tmp = nullptr;
   size_t tmp_bytes = 0;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(&cnt), sizeof(unsigned long long) * (size_t)(n + 1));
-  if (e != hipSuccess) return e;
-  e = launch_fill_zero(cnt, sizeof(unsigned long long) * (size_t)(n + 1), s);
-  if (e == hipSuccess && m > 0) {
-    hipLaunchKernelGGL(k_count_in, dim3(grid_for(m, 256, 65536)), dim3(256), 0, s, idx, m, cnt);
+  int end_bit = 1;
+  while (end_bit < 31 && ((int64_t)1 << end_bit) < n) ++end_bit;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&rows), sizeof(int32_t) * (size_t)m);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&keys), sizeof(int32_t) * (size_t)m);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_arc_rows, dim3(grid_for(n, 4, 65536)), dim3(256), 0, s, off, n, rows);
     e = hipGetLastError();
   }
-  // roff[0..n] = exclusive prefix sums of the counts (count[n] = 0 gives roff[n] = m).
   if (e == hipSuccess)
-    e = hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, cnt, reinterpret_cast<unsigned long long*>(roff),
-                                         (int)(n + 1), s);
+    e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, idx, keys, rows, ridx, (int)m, 0, end_bit, s);
   if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1);
   if (e == hipSuccess)
-    e = hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, cnt, reinterpret_cast<unsigned long long*>(roff),
-                                         (int)(n + 1), s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(cnt, roff, sizeof(int64_t) * (size_t)(n + 1), hipMemcpyDeviceToDevice, s);
-  if (e == hipSuccess && n > 0) {
-    hipLaunchKernelGGL(k_scatter_rev, dim3(grid_for(n, 4, 65536)), dim3(256), 0, s, off, idx, n, cnt, ridx);
+    e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, idx, keys, rows, ridx, (int)m, 0, end_bit, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_lower_bound, dim3(grid_for(n + 1, 256, 65536)), dim3(256), 0, s, keys, m, n, roff);
     e = hipGetLastError();
   }
   const hipError_t e2 = hipStreamSynchronize(s);
   if (e == hipSuccess) e = e2;
   (void)hipFree(tmp);
-  (void)hipFree(cnt);
+  (void)hipFree(keys);
+  (void)hipFree(rows);
   return e;
 }
 
