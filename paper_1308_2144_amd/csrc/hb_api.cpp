@@ -1,7 +1,9 @@
 // Host side of libhb: context management, validation, allocation and the
 // per-pass driver loop.  See include/hb.h for the contract of every entry
 // point.
+#include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <string>
@@ -117,6 +119,90 @@ void plan_rows(hb_ctx* c, const int64_t* off_host, std::vector<int32_t>& light,
     hr.nitems = (int64_t)items.size() - hr.item0;
     hrows.push_back(hr);
   }
+}
+
+// The same classification on the device for a single graph: light and
+// medium row lists by stream compaction (row order kept); the few heavy rows
+// are copied back with their offsets and cut into chunks on the host.
+hb_status plan_rows_device(hb_ctx* c) {
+  const int64_t n = c->n, m = c->m;
+  if (n == 0) {
+    c->n_light = c->n_medium = c->n_items = c->n_hrows = 0;
+    return HB_OK;
+  }
+  const int64_t lmax = c->opt.light_max, hmin = c->opt.heavy_min, chunk = c->opt.chunk;
+  const int64_t med_cap = std::min<int64_t>(n, m / (lmax + 1) + 1);
+  const int64_t heavy_cap = std::min<int64_t>(n, m / hmin + 1);
+  int32_t* heavy = nullptr;
+  int* counts = nullptr;
+  void* tmp = nullptr;
+  size_t tmp_bytes = 0, b1 = 0;
+  HB_HIP(dmalloc(&c->light, (size_t)n));
+  HB_HIP(dmalloc(&c->medium, (size_t)med_cap));
+  HB_HIP(dmalloc(&heavy, (size_t)heavy_cap));
+  HB_HIP(dmalloc(&counts, 3));
+  hipError_t e = hb::select_rows(c->off, n, 1, lmax, c->light, counts, nullptr, &tmp_bytes, c->stream);
+  if (e == hipSuccess) e = hb::select_rows(c->off, n, lmax + 1, hmin - 1, c->medium, counts + 1, nullptr, &b1, c->stream);
+  tmp_bytes = std::max(tmp_bytes, b1);
+  if (e == hipSuccess) e = hb::select_rows(c->off, n, hmin, INT64_MAX, heavy, counts + 2, nullptr, &b1, c->stream);
+  tmp_bytes = std::max(tmp_bytes, b1);
+  if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes > 0 ? tmp_bytes : 1);
+  if (e == hipSuccess) e = hb::select_rows(c->off, n, 1, lmax, c->light, counts, tmp, &tmp_bytes, c->stream);
+  if (e == hipSuccess) e = hb::select_rows(c->off, n, lmax + 1, hmin - 1, c->medium, counts + 1, tmp, &tmp_bytes, c->stream);
+  if (e == hipSuccess) e = hb::select_rows(c->off, n, hmin, INT64_MAX, heavy, counts + 2, tmp, &tmp_bytes, c->stream);
+  int cnt[3] = {0, 0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(cnt, counts, sizeof(cnt), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  std::vector<int32_t> hrow_ids;
+  std::vector<int64_t> hoff;
+  int64_t* hoff_dev = nullptr;
+  if (e == hipSuccess && cnt[2] > 0) {
+    hrow_ids.resize((size_t)cnt[2]);
+    hoff.resize(2 * (size_t)cnt[2]);
+    e = dmalloc(&hoff_dev, 2 * (size_t)cnt[2]);
+    if (e == hipSuccess) e = hb::launch_take_offsets(heavy, cnt[2], c->off, hoff_dev, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hrow_ids.data(), heavy, sizeof(int32_t) * hrow_ids.size(), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hoff.data(), hoff_dev, sizeof(int64_t) * hoff.size(), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  }
+  (void)hipFree(tmp);
+  (void)hipFree(counts);
+  (void)hipFree(heavy);
+  (void)hipFree(hoff_dev);
+  if (e != hipSuccess) return fail(HB_EDEVICE, std::string("row classification: ") + hipGetErrorString(e));
+  c->n_light = cnt[0];
+  c->n_medium = cnt[1];
+  std::vector<hb::HeavyItem> items;
+  std::vector<hb::HeavyRow> hrows;
+  for (size_t h = 0; h < hrow_ids.size(); ++h) {
+    const int64_t v = hrow_ids[h], s0 = hoff[2 * h], e0 = hoff[2 * h + 1];
+    hb::HeavyRow hr;
+    hr.row = v;
+    hr.item0 = (int64_t)items.size();
+    for (int64_t k = s0; k < e0; k += chunk) {
+      hb::HeavyItem it;
+      it.row = v;
+      it.e0 = k;
+      it.e1 = k + chunk < e0 ? k + chunk : e0;
+      items.push_back(it);
+    }
+    hr.nitems = (int64_t)items.size() - hr.item0;
+    hrows.push_back(hr);
+  }
+  c->n_items = (int64_t)items.size();
+  c->n_hrows = (int64_t)hrows.size();
+  HB_HIP(dmalloc(&c->items, items.size()));
+  HB_HIP(dmalloc(&c->hrows, hrows.size()));
+  if (!items.empty())
+    HB_HIP(hipMemcpyAsync(c->items, items.data(), sizeof(hb::HeavyItem) * items.size(), hipMemcpyHostToDevice,
+                          c->stream));
+  if (!hrows.empty())
+    HB_HIP(hipMemcpyAsync(c->hrows, hrows.data(), sizeof(hb::HeavyRow) * hrows.size(), hipMemcpyHostToDevice,
+                          c->stream));
+  HB_HIP(hipStreamSynchronize(c->stream));  // host staging dies here
+  return HB_OK;
 }
 
 }  // namespace hbh
@@ -289,38 +375,38 @@ hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, co
     if (bad & 1) return fail(HB_EINVAL, "malformed CSR offsets (need offsets[0]=0, nondecreasing, offsets[n]=m)");
     if (bad & 2) return fail(HB_EINVAL, "CSR index outside [0, n)");
   }
-  if (g->on_device) {
-    off_host.resize((size_t)n + 1);
-    HB_HIP(hipMemcpyAsync(off_host.data(), c->off, sizeof(int64_t) * ((size_t)n + 1), hipMemcpyDeviceToHost,
-                          c->stream));
-    HB_HIP(hipStreamSynchronize(c->stream));
+  if (blk_graph) {
+    // Multi-graph arena (built on the host): classify rows on the host.
+    std::vector<int32_t> light, medium;
+    std::vector<hb::HeavyItem> items;
+    std::vector<hb::HeavyRow> hrows;
+    plan_rows(c, off_host.data(), light, medium, items, hrows);
+    c->n_light = (int64_t)light.size();
+    c->n_medium = (int64_t)medium.size();
+    c->n_items = (int64_t)items.size();
+    c->n_hrows = (int64_t)hrows.size();
+    HB_HIP(dmalloc(&c->light, light.size()));
+    HB_HIP(dmalloc(&c->medium, medium.size()));
+    HB_HIP(dmalloc(&c->items, items.size()));
+    HB_HIP(dmalloc(&c->hrows, hrows.size()));
+    if (!light.empty())
+      HB_HIP(hipMemcpyAsync(c->light, light.data(), sizeof(int32_t) * light.size(), hipMemcpyHostToDevice,
+                            c->stream));
+    if (!medium.empty())
+      HB_HIP(hipMemcpyAsync(c->medium, medium.data(), sizeof(int32_t) * medium.size(), hipMemcpyHostToDevice,
+                            c->stream));
+    if (!items.empty())
+      HB_HIP(hipMemcpyAsync(c->items, items.data(), sizeof(hb::HeavyItem) * items.size(), hipMemcpyHostToDevice,
+                            c->stream));
+    if (!hrows.empty())
+      HB_HIP(hipMemcpyAsync(c->hrows, hrows.data(), sizeof(hb::HeavyRow) * hrows.size(), hipMemcpyHostToDevice,
+                            c->stream));
+    HB_HIP(hipStreamSynchronize(c->stream));  // host staging dies here
+  } else {
+    hb_status st = plan_rows_device(c);
+    if (st != HB_OK) return st;
   }
-
-  std::vector<int32_t> light, medium;
-  std::vector<hb::HeavyItem> items;
-  std::vector<hb::HeavyRow> hrows;
-  plan_rows(c, off_host.data(), light, medium, items, hrows);
-  c->n_light = (int64_t)light.size();
-  c->n_medium = (int64_t)medium.size();
-  c->n_items = (int64_t)items.size();
-  c->n_hrows = (int64_t)hrows.size();
   c->n_nonempty = c->n_light + c->n_medium + c->n_hrows;
-  HB_HIP(dmalloc(&c->light, light.size()));
-  HB_HIP(dmalloc(&c->medium, medium.size()));
-  HB_HIP(dmalloc(&c->items, items.size()));
-  HB_HIP(dmalloc(&c->hrows, hrows.size()));
-  if (!light.empty())
-    HB_HIP(hipMemcpyAsync(c->light, light.data(), sizeof(int32_t) * light.size(), hipMemcpyHostToDevice,
-                          c->stream));
-  if (!medium.empty())
-    HB_HIP(hipMemcpyAsync(c->medium, medium.data(), sizeof(int32_t) * medium.size(), hipMemcpyHostToDevice,
-                          c->stream));
-  if (!items.empty())
-    HB_HIP(hipMemcpyAsync(c->items, items.data(), sizeof(hb::HeavyItem) * items.size(), hipMemcpyHostToDevice,
-                          c->stream));
-  if (!hrows.empty())
-    HB_HIP(hipMemcpyAsync(c->hrows, hrows.data(), sizeof(hb::HeavyRow) * hrows.size(), hipMemcpyHostToDevice,
-                          c->stream));
 
   // Reverse CSR for push activation of sparse passes (lane-group kernels only).
   if (c->opt.frontier && c->opt.push && c->p <= 256 && n > 0) {

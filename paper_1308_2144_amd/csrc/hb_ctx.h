@@ -127,6 +127,7 @@ namespace hbh {
 void release(hb_ctx* c);
 void plan_rows(hb_ctx* c, const int64_t* off_host, std::vector<int32_t>& light, std::vector<int32_t>& medium,
                std::vector<hb::HeavyItem>& items, std::vector<hb::HeavyRow>& hrows);
+hb_status plan_rows_device(hb_ctx* c);
 hb::PassArgs device_args(hb_ctx* c);
 hb_status read_ctl(hb_ctx* c);
 

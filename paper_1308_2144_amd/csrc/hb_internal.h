@@ -198,6 +198,13 @@ hipError_t launch_widen_offsets(const int32_t* in, int64_t* out, int64_t count, 
 hipError_t launch_validate(const int64_t* off, const int32_t* idx, int64_t n, int64_t m,
                            int* bad, hipStream_t s);
 
+// Stream compaction of the rows whose degree lies in [lo, hi], in increasing
+// order, into out; *count (device) receives their number.  With tmp NULL,
+// *tmp_bytes receives the scratch size (hipcub DeviceSelect).
+hipError_t select_rows(const int64_t* off, int64_t n, int64_t lo, int64_t hi, int32_t* out, int* count, void* tmp,
+                       size_t* tmp_bytes, hipStream_t s);
+// out[2i], out[2i+1] = off[rows[i]], off[rows[i] + 1].
+hipError_t launch_take_offsets(const int32_t* rows, int64_t count, const int64_t* off, int64_t* out, hipStream_t s);
 // Reverse CSR (row w lists every v with an arc v->w, in increasing v).
 // roff: n+1 entries, ridx: m entries.  Radix-sorts the arcs by target; the
 // sort's scratch (2m int32 and hipcub storage) is allocated and freed inside.

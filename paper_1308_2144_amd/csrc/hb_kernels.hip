@@ -1261,6 +1261,23 @@ __global__ void k_validate(const int64_t* off, const int32_t* idx, int64_t n, in
 
 // --- reverse CSR and push activation ---------------------------------------
 
+// Rows with lo <= degree <= hi (row classes of the degree-aware schedule).
+struct DegreeIn {
+  const int64_t* off;
+  int64_t lo, hi;
+  __host__ __device__ bool operator()(const int32_t& v) const {
+    const int64_t d = off[v + 1] - off[v];
+    return d >= lo && d <= hi;
+  }
+};
+
+__global__ void k_take_offsets(const int32_t* rows, int64_t count, const int64_t* off, int64_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  out[2 * i] = off[rows[i]];
+  out[2 * i + 1] = off[rows[i] + 1];
+}
+
 // Reverse CSR by sorting: the arcs (v -> w) as (key w, value v) pairs are
 // radix-sorted by w, which lists the predecessors of each node in increasing
 // order; k_arc_rows makes the values, k_lower_bound the offsets.
@@ -1697,6 +1714,19 @@ hipError_t launch_validate(const int64_t* off, const int32_t* idx, int64_t n, in
                            hipStream_t s) {
   hipLaunchKernelGGL(k_validate, dim3(grid_for(n + m + 1, 256, 16384)), dim3(256), 0, s, off, idx, n, m,
                      bad);
+  return hipGetLastError();
+}
+
+hipError_t select_rows(const int64_t* off, int64_t n, int64_t lo, int64_t hi, int32_t* out, int* count, void* tmp,
+                       size_t* tmp_bytes, hipStream_t s) {
+  hipcub::CountingInputIterator<int32_t> rows(0);
+  DegreeIn op{off, lo, hi};
+  return hipcub::DeviceSelect::If(tmp, *tmp_bytes, rows, out, count, (int)n, op, s);
+}
+
+hipError_t launch_take_offsets(const int32_t* rows, int64_t count, const int64_t* off, int64_t* out, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_take_offsets, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, rows, count, off, out);
   return hipGetLastError();
 }
 
