@@ -143,9 +143,12 @@ def bench_batch(args, torch, hb, plain_sample: int = 512):
     opt, tune = hb.hb_batch_autotune(graphs, b, seeds, sample=256, cache_path=args.tune_cache or None)
     tuned = hb.options_dict(opt)
     log(f"batch: autotune {tune} -> {tuned} in {time.time() - t:.1f}s")
-    t = time.time()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
     bt = hb.Batch(graphs, b, seeds, options=opt)
-    log(f"batch: context built in {time.time() - t:.1f}s; stats {bt.stats()}")
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t
+    log(f"batch: context built in {init_s:.2f}s; stats {bt.stats()}")
     outs = [torch.empty(max(bt.total, 1), dtype=torch.float64, device="cuda") for _ in range(4)]
 
     def bstep():
@@ -210,6 +213,7 @@ def bench_batch(args, torch, hb, plain_sample: int = 512):
     return {"workload": "4096 graphs: 2048 Barabasi-Albert (m=4) + 2048 Watts-Strogatz (k=10, beta=0.1), "
                         "n log-uniform in [1000, 200000], log2m=5, hash seeds 42+i",
             "graphs": k, "batched_graphs_per_s": k / bdt, "batched_ms": bdt * 1e3,
+            "init_s": init_s, "batched_graphs_per_s_with_init": k / (init_s + bdt),
             "engine_passes": int(engine_passes), "max_graph_passes": int(passes.max()),
             "plain_graphs_per_s": k / pdt, "plain_ms_estimated": pdt * 1e3,
             "plain_sample": int(len(sample)),

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "hb_ctx.h"
@@ -89,41 +90,11 @@ hb_status check_ctx(hb_ctx* c) {
 
 namespace hbh {
 
-// Classify the non-empty rows by degree (empty rows never change and are
-// left out of every pass) and cut heavy rows into chunks.
-void plan_rows(hb_ctx* c, const int64_t* off_host, std::vector<int32_t>& light,
-               std::vector<int32_t>& medium, std::vector<hb::HeavyItem>& items,
-               std::vector<hb::HeavyRow>& hrows) {
-  const int64_t lmax = c->opt.light_max, hmin = c->opt.heavy_min, chunk = c->opt.chunk;
-  for (int64_t v = 0; v < c->n; ++v) {
-    const int64_t s = off_host[v], e = off_host[v + 1], deg = e - s;
-    if (deg == 0) continue;
-    if (deg <= lmax) {
-      light.push_back((int32_t)v);
-      continue;
-    }
-    if (deg < hmin) {
-      medium.push_back((int32_t)v);
-      continue;
-    }
-    hb::HeavyRow hr;
-    hr.row = v;
-    hr.item0 = (int64_t)items.size();
-    for (int64_t k = s; k < e; k += chunk) {
-      hb::HeavyItem it;
-      it.row = v;
-      it.e0 = k;
-      it.e1 = k + chunk < e ? k + chunk : e;
-      items.push_back(it);
-    }
-    hr.nitems = (int64_t)items.size() - hr.item0;
-    hrows.push_back(hr);
-  }
-}
-
-// The same classification on the device for a single graph: light and
-// medium row lists by stream compaction (row order kept); the few heavy rows
-// are copied back with their offsets and cut into chunks on the host.
+// Row classes of the degree-aware schedule (empty rows never change and are
+// left out of every pass): rows with 1..light_max arcs, rows up to heavy_min
+// arcs, and heavy rows cut into chunks of `chunk` arcs.  Light and medium
+// lists by stream compaction on the device (row order kept); the few heavy
+// rows are copied back with their offsets and cut into chunks on the host.
 hb_status plan_rows_device(hb_ctx* c) {
   const int64_t n = c->n, m = c->m;
   if (n == 0) {
@@ -191,6 +162,25 @@ hb_status plan_rows_device(hb_ctx* c) {
     hr.nitems = (int64_t)items.size() - hr.item0;
     hrows.push_back(hr);
   }
+  return upload_plan(c, {}, {}, items, hrows);
+}
+
+// Copies host-made row lists to the device (light / medium only when given:
+// the device planner fills those itself).
+hb_status upload_plan(hb_ctx* c, const std::vector<int32_t>& light, const std::vector<int32_t>& medium,
+                      const std::vector<hb::HeavyItem>& items, const std::vector<hb::HeavyRow>& hrows) {
+  if (!c->light) {
+    c->n_light = (int64_t)light.size();
+    c->n_medium = (int64_t)medium.size();
+    HB_HIP(dmalloc(&c->light, light.size()));
+    HB_HIP(dmalloc(&c->medium, medium.size()));
+    if (!light.empty())
+      HB_HIP(hipMemcpyAsync(c->light, light.data(), sizeof(int32_t) * light.size(), hipMemcpyHostToDevice,
+                            c->stream));
+    if (!medium.empty())
+      HB_HIP(hipMemcpyAsync(c->medium, medium.data(), sizeof(int32_t) * medium.size(), hipMemcpyHostToDevice,
+                            c->stream));
+  }
   c->n_items = (int64_t)items.size();
   c->n_hrows = (int64_t)hrows.size();
   HB_HIP(dmalloc(&c->items, items.size()));
@@ -210,6 +200,7 @@ hb_status plan_rows_device(hb_ctx* c) {
 namespace {
 
 constexpr int ESUM_BLOCKS = 1024;
+constexpr int64_t HOST_PLAN_MAX = 1 << 20;  // graphs up to this many nodes are classified on the host
 
 // X * 2^-52 rounded to the nearest double (ties to even), X the 192-bit
 // integer w[0] + w[1] 2^64 + w[2] 2^128 of an exact sum of estimates.
@@ -335,20 +326,23 @@ hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, co
   const int64_t n = c->n, m = c->m;
   c->n_blocks = (n + 63) / 64;
 
-  // Graph arrays.
-  std::vector<int64_t> off_host;
+  // Graph arrays (int32 offsets are widened on the device).
   if (!g->on_device) {
-    off_host.resize((size_t)n + 1);
-    if (g->offsets_bits == 64) {
-      std::memcpy(off_host.data(), g->offsets, sizeof(int64_t) * ((size_t)n + 1));
-    } else {
-      const int32_t* o32 = static_cast<const int32_t*>(g->offsets);
-      for (int64_t i = 0; i <= n; ++i) off_host[(size_t)i] = o32[i];
-    }
     HB_HIP(dmalloc(&c->off, (size_t)n + 1));
     c->own_off = true;
-    HB_HIP(hipMemcpyAsync(c->off, off_host.data(), sizeof(int64_t) * ((size_t)n + 1),
-                          hipMemcpyHostToDevice, c->stream));
+    if (g->offsets_bits == 64) {
+      HB_HIP(hipMemcpyAsync(c->off, g->offsets, sizeof(int64_t) * ((size_t)n + 1), hipMemcpyHostToDevice,
+                            c->stream));
+    } else {
+      int32_t* o32 = nullptr;
+      HB_HIP(dmalloc(&o32, (size_t)n + 1));
+      hipError_t e = hipMemcpyAsync(o32, g->offsets, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice,
+                                    c->stream);
+      if (e == hipSuccess) e = hb::launch_widen_offsets(o32, c->off, n + 1, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      (void)hipFree(o32);
+      if (e != hipSuccess) return fail(HB_EDEVICE, std::string("offsets upload: ") + hipGetErrorString(e));
+    }
     HB_HIP(dmalloc(&c->idx_owned, (size_t)m));
     if (m > 0)
       HB_HIP(hipMemcpyAsync(c->idx_owned, g->indices, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice,
@@ -375,35 +369,20 @@ hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, co
     if (bad & 1) return fail(HB_EINVAL, "malformed CSR offsets (need offsets[0]=0, nondecreasing, offsets[n]=m)");
     if (bad & 2) return fail(HB_EINVAL, "CSR index outside [0, n)");
   }
-  if (blk_graph) {
-    // Multi-graph arena (built on the host): classify rows on the host.
+  if (n <= HOST_PLAN_MAX) {
+    // Small graphs: one pass over the offsets on the host costs less than the
+    // device planner's scratch allocation and readbacks.
+    std::vector<int64_t> oh((size_t)n + 1);
+    HB_HIP(hipMemcpyAsync(oh.data(), c->off, sizeof(int64_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, c->stream));
+    HB_HIP(hipStreamSynchronize(c->stream));
     std::vector<int32_t> light, medium;
     std::vector<hb::HeavyItem> items;
     std::vector<hb::HeavyRow> hrows;
-    plan_rows(c, off_host.data(), light, medium, items, hrows);
-    c->n_light = (int64_t)light.size();
-    c->n_medium = (int64_t)medium.size();
-    c->n_items = (int64_t)items.size();
-    c->n_hrows = (int64_t)hrows.size();
-    HB_HIP(dmalloc(&c->light, light.size()));
-    HB_HIP(dmalloc(&c->medium, medium.size()));
-    HB_HIP(dmalloc(&c->items, items.size()));
-    HB_HIP(dmalloc(&c->hrows, hrows.size()));
-    if (!light.empty())
-      HB_HIP(hipMemcpyAsync(c->light, light.data(), sizeof(int32_t) * light.size(), hipMemcpyHostToDevice,
-                            c->stream));
-    if (!medium.empty())
-      HB_HIP(hipMemcpyAsync(c->medium, medium.data(), sizeof(int32_t) * medium.size(), hipMemcpyHostToDevice,
-                            c->stream));
-    if (!items.empty())
-      HB_HIP(hipMemcpyAsync(c->items, items.data(), sizeof(hb::HeavyItem) * items.size(), hipMemcpyHostToDevice,
-                            c->stream));
-    if (!hrows.empty())
-      HB_HIP(hipMemcpyAsync(c->hrows, hrows.data(), sizeof(hb::HeavyRow) * hrows.size(), hipMemcpyHostToDevice,
-                            c->stream));
-    HB_HIP(hipStreamSynchronize(c->stream));  // host staging dies here
+    plan_rows_host(oh.data(), n, c->opt.light_max, c->opt.heavy_min, c->opt.chunk, light, medium, items, hrows);
+    const hb_status st = upload_plan(c, light, medium, items, hrows);
+    if (st != HB_OK) return st;
   } else {
-    hb_status st = plan_rows_device(c);
+    const hb_status st = plan_rows_device(c);
     if (st != HB_OK) return st;
   }
   c->n_nonempty = c->n_light + c->n_medium + c->n_hrows;
@@ -982,30 +961,77 @@ hb_status hb_batch_init(hb_ctx** out, const hb_csr* graphs, int32_t k, int32_t l
   std::vector<int64_t> off((size_t)nodes + 1);
   std::vector<int32_t> idx((size_t)(arcs > 0 ? arcs : 1));
   std::vector<int32_t> blk((size_t)(nodes / 64));
-  int64_t a = 0;
+  std::vector<int64_t> abase((size_t)k + 1, 0);
+  for (int32_t i = 0; i < k; ++i) abase[(size_t)i + 1] = abase[(size_t)i] + graphs[i].m;
+  off[(size_t)nodes] = arcs;
   const bool validate = !opt || opt->validate;
-  for (int32_t i = 0; i < k; ++i) {
-    const hb_csr& g = graphs[i];
-    const int64_t base = gh[(size_t)i].node_base;
-    const int64_t npad = (g.n + 63) / 64 * 64;
-    for (int64_t b = base / 64; b < (base + npad) / 64; ++b) blk[(size_t)b] = i;
-    for (int64_t v = 0; v <= g.n; ++v) {
-      const int64_t o = g.offsets_bits == 64 ? static_cast<const int64_t*>(g.offsets)[v]
-                                             : static_cast<const int32_t*>(g.offsets)[v];
-      if (validate && (o < 0 || o > g.m || (v > 0 && o < off[(size_t)(base + v - 1)] - a) ||
-                       (v == 0 && o != 0) || (v == g.n && o != g.m)))
-        return fail(HB_EINVAL, "graph " + std::to_string(i) + ": malformed offsets");
-      off[(size_t)(base + v)] = a + o;
+  // Graphs [g0, g1) into their arena ranges; returns 0, or 1 + the kind of
+  // malformation (1 offsets, 2 index) of the first bad graph.
+  auto fill = [&](int32_t g0, int32_t g1, int32_t* bad_graph) -> int {
+    for (int32_t i = g0; i < g1; ++i) {
+      const hb_csr& g = graphs[i];
+      const int64_t base = gh[(size_t)i].node_base;
+      const int64_t npad = (g.n + 63) / 64 * 64;
+      const int64_t a = abase[(size_t)i];
+      for (int64_t b = base / 64; b < (base + npad) / 64; ++b) blk[(size_t)b] = i;
+      if (g.n == 0) {  // no rows: its one offset entry belongs to the next graph
+        const int64_t o = g.offsets_bits == 64 ? static_cast<const int64_t*>(g.offsets)[0]
+                                               : static_cast<const int32_t*>(g.offsets)[0];
+        if (validate && (o != 0 || g.m != 0)) {
+          *bad_graph = i;
+          return 1;
+        }
+        continue;
+      }
+      int64_t prev = 0;
+      for (int64_t v = 0; v <= g.n; ++v) {
+        const int64_t o = g.offsets_bits == 64 ? static_cast<const int64_t*>(g.offsets)[v]
+                                               : static_cast<const int32_t*>(g.offsets)[v];
+        if (validate && (o < prev || o > g.m || (v == 0 && o != 0) || (v == g.n && o != g.m))) {
+          *bad_graph = i;
+          return 1;
+        }
+        prev = o;
+        off[(size_t)(base + v)] = a + o;
+      }
+      for (int64_t v = g.n + 1; v < npad; ++v) off[(size_t)(base + v)] = a + g.m;
+      for (int64_t e = 0; e < g.m; ++e) {
+        const int32_t w = g.indices[e];
+        if (validate && (w < 0 || w >= g.n)) {
+          *bad_graph = i;
+          return 2;
+        }
+        idx[(size_t)(a + e)] = (int32_t)(base + w);
+      }
     }
-    for (int64_t v = g.n + 1; v <= npad; ++v) off[(size_t)(base + v)] = a + g.m;
-    for (int64_t e = 0; e < g.m; ++e) {
-      const int32_t w = g.indices[e];
-      if (validate && (w < 0 || w >= g.n))
-        return fail(HB_EINVAL, "graph " + std::to_string(i) + ": index outside [0, n)");
-      idx[(size_t)(a + e)] = (int32_t)(base + w);
-    }
-    a += g.m;
+    return 0;
+  };
+  // Contiguous ranges of graphs with about equal arcs, one thread each.
+  unsigned nt = std::thread::hardware_concurrency();
+  nt = std::max(1u, std::min({nt, 32u, (unsigned)k}));
+  std::vector<int32_t> cut(nt + 1, k);
+  cut[0] = 0;
+  for (unsigned t = 1, i = 0; t < nt; ++t) {
+    const int64_t target = (arcs + nodes) / (int64_t)nt * (int64_t)t;
+    while (i < (unsigned)k && abase[i] + gh[i].node_base < target) ++i;
+    cut[t] = (int32_t)i;
   }
+  std::vector<int> kind(nt, 0);
+  std::vector<int32_t> badg(nt, -1);
+  std::vector<std::thread> pool;
+  try {
+    for (unsigned t = 1; t < nt; ++t)
+      pool.emplace_back([&, t] { kind[t] = fill(cut[t], std::max(cut[t], cut[t + 1]), &badg[t]); });
+  } catch (...) {
+    for (auto& th : pool) th.join();
+    return fail(HB_ENOMEM, "cannot start arena threads");
+  }
+  kind[0] = fill(cut[0], std::max(cut[0], cut[1]), &badg[0]);
+  for (auto& th : pool) th.join();
+  for (unsigned t = 0; t < nt; ++t)
+    if (kind[t])
+      return fail(HB_EINVAL, "graph " + std::to_string(badg[t]) +
+                                 (kind[t] == 1 ? ": malformed offsets" : ": index outside [0, n)"));
   hb_ctx* c = new (std::nothrow) hb_ctx();
   if (!c) return fail(HB_ENOMEM, "cannot allocate context");
   c->n_graphs = k;

@@ -31,6 +31,38 @@ hipError_t dmalloc(T** p, size_t count) {
   return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
 }
 
+// Row classes of the degree-aware schedule, on the host, for offsets of type
+// T (int32 or int64): rows with 1..light_max arcs, rows below heavy_min arcs,
+// and heavy rows cut into chunks of `chunk` arcs (item offsets are the CSR's
+// own); empty rows never change and are left out.
+template <class T>
+void plan_rows_host(const T* off, int64_t n, int64_t light_max, int64_t heavy_min, int64_t chunk,
+                    std::vector<int32_t>& light, std::vector<int32_t>& medium, std::vector<hb::HeavyItem>& items,
+                    std::vector<hb::HeavyRow>& hrows) {
+  for (int64_t v = 0; v < n; ++v) {
+    const int64_t s = (int64_t)off[v], e = (int64_t)off[v + 1], deg = e - s;
+    if (deg == 0) continue;
+    if (deg <= light_max) {
+      light.push_back((int32_t)v);
+    } else if (deg < heavy_min) {
+      medium.push_back((int32_t)v);
+    } else {
+      hb::HeavyRow hr;
+      hr.row = v;
+      hr.item0 = (int64_t)items.size();
+      for (int64_t k = s; k < e; k += chunk) {
+        hb::HeavyItem it;
+        it.row = v;
+        it.e0 = k;
+        it.e1 = k + chunk < e ? k + chunk : e;
+        items.push_back(it);
+      }
+      hr.nitems = (int64_t)items.size() - hr.item0;
+      hrows.push_back(hr);
+    }
+  }
+}
+
 // alpha_p of Flajolet-Fusy-Gandouet-Meunier 2007 (Algorithm 1 defers to it).
 inline double alpha_for(int p) {
   if (p == 16) return 0.673;
@@ -125,9 +157,9 @@ struct hb_ctx {
 namespace hbh {
 
 void release(hb_ctx* c);
-void plan_rows(hb_ctx* c, const int64_t* off_host, std::vector<int32_t>& light, std::vector<int32_t>& medium,
-               std::vector<hb::HeavyItem>& items, std::vector<hb::HeavyRow>& hrows);
 hb_status plan_rows_device(hb_ctx* c);
+hb_status upload_plan(hb_ctx* c, const std::vector<int32_t>& light, const std::vector<int32_t>& medium,
+                      const std::vector<hb::HeavyItem>& items, const std::vector<hb::HeavyRow>& hrows);
 hb::PassArgs device_args(hb_ctx* c);
 hb_status read_ctl(hb_ctx* c);
 

@@ -249,35 +249,6 @@ bool csr_ok(const T* off, const int32_t* idx, int64_t n, int64_t m) {
   return true;
 }
 
-// Row classes of one graph in local ids (the rule of the single-graph
-// planner: empty rows are left out).
-template <class T>
-void plan_local(const T* off, int64_t n, const hb_options& o, Req* r) {
-  const int64_t lmax = o.light_max, hmin = o.heavy_min, chunk = o.chunk;
-  for (int64_t v = 0; v < n; ++v) {
-    const int64_t s = (int64_t)off[v], e = (int64_t)off[v + 1], deg = e - s;
-    if (deg == 0) continue;
-    if (deg <= lmax) {
-      r->light_v.push_back((int32_t)v);
-    } else if (deg < hmin) {
-      r->medium_v.push_back((int32_t)v);
-    } else {
-      hb::HeavyRow hr;
-      hr.row = v;
-      hr.item0 = (int64_t)r->items_v.size();
-      for (int64_t k = s; k < e; k += chunk) {
-        hb::HeavyItem it;
-        it.row = v;
-        it.e0 = k;
-        it.e1 = std::min(k + chunk, e);
-        r->items_v.push_back(it);
-      }
-      hr.nitems = (int64_t)r->items_v.size() - hr.item0;
-      r->hrows_v.push_back(hr);
-    }
-  }
-}
-
 void release_engine(Engine* e) {
   if (!e) return;
   if (e->c && e->c->stream) (void)hipStreamSynchronize(e->c->stream);
@@ -706,10 +677,13 @@ hb_status serve_step(hb_server* s, bool* progress) {
     if (st != HB_OK) return st;
     if (!r->planned) {
       const hb_csr& g = r->rq.graph;
+      const hb_options& o = s->cfg.opt;
       if (g.offsets_bits == 64)
-        plan_local(static_cast<const int64_t*>(g.offsets), r->n, s->cfg.opt, r);
+        plan_rows_host(static_cast<const int64_t*>(g.offsets), r->n, o.light_max, o.heavy_min, o.chunk, r->light_v,
+                       r->medium_v, r->items_v, r->hrows_v);
       else
-        plan_local(static_cast<const int32_t*>(g.offsets), r->n, s->cfg.opt, r);
+        plan_rows_host(static_cast<const int32_t*>(g.offsets), r->n, o.light_max, o.heavy_min, o.chunk, r->light_v,
+                       r->medium_v, r->items_v, r->hrows_v);
       r->planned = true;
     }
     {
