@@ -77,6 +77,9 @@ struct PassCtl {
   int32_t frontier, dense_pct, sparse_pct, has_reverse;
   int32_t n_graphs;
   int32_t pad;
+  // changed rows and their in-arcs in the last pass, plus those of graphs
+  // admitted since (every row of an admitted graph counts as changed)
+  unsigned long long chg, pairs;
 };
 
 // Everything one pass needs.  `cur` holds counters of radius t, `nxt`
@@ -183,8 +186,8 @@ hipError_t launch_pack(const double* src, double* dst, int64_t n_arena, const in
 // pass, planning totals, and a whole slot record.
 hipError_t launch_rebase_csr(const void* off_l, int bits, int64_t n, int64_t m, int64_t node_base, int64_t arc_base,
                              int64_t* off, int32_t* idx, hipStream_t s);
-hipError_t launch_admit(PassCtl* ctl, GraphDev* graphs, int32_t slot, const GraphDev& val, int32_t* blk_graph,
-                        uint64_t* mod0, uint64_t* mod1, int64_t b0, int64_t b1, hipStream_t s);
+hipError_t launch_admit(PassCtl* ctl, GraphDev* graphs, int32_t slot, const GraphDev& val, int64_t m,
+                        int32_t* blk_graph, uint64_t* mod0, uint64_t* mod1, int64_t b0, int64_t b1, hipStream_t s);
 hipError_t launch_set_plan(PassCtl* ctl, int64_t listed_rows, int64_t arcs, hipStream_t s);
 hipError_t launch_set_slot(GraphDev* graphs, int32_t slot, const GraphDev& val, hipStream_t s);
 hipError_t launch_pack_u8(const uint8_t* src, uint8_t* dst, int64_t n_arena, int p, const int32_t* blk_graph,

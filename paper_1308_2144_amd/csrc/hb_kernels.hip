@@ -1401,6 +1401,19 @@ __global__ void k_graph_done(PassArgs A0) {
   }
 }
 
+// Mode of the next pass from the changed rows (chg) and their in-arcs
+// (pairs) of the last pass, the same rule the host applies to single graphs.
+__device__ __forceinline__ int32_t plan_mode(const PassCtl* c) {
+  if (!c->frontier) return MODE_DENSE;
+  const int64_t N = c->listed_rows > 0 ? c->listed_rows : 1;
+  const int64_t M = c->arcs > 0 ? c->arcs : 1;
+  const bool dense = c->has_reverse ? 100 * (int64_t)c->pairs >= (int64_t)c->dense_pct * M
+                                    : 100 * (int64_t)c->chg >= (int64_t)c->dense_pct * N;
+  if (dense) return MODE_DENSE;
+  if (c->has_reverse && 100 * (int64_t)c->chg < (int64_t)c->sparse_pct * N) return MODE_SPARSE;
+  return MODE_EDGE;
+}
+
 // Plans the next pass from this pass's counters (the same rule the host
 // applies to single graphs), then advances the pass index and parity.
 __global__ void k_pass_ctl(PassArgs A0) {
@@ -1419,20 +1432,9 @@ __global__ void k_pass_ctl(PassArgs A0) {
   }
   for (int i = lane; i < STAT_SLOTS * STAT_K; i += 64) A.stats_next[i] = 0ull;
   if (lane == 0) {
-    const int64_t N = c->listed_rows > 0 ? c->listed_rows : 1;
-    const int64_t M = c->arcs > 0 ? c->arcs : 1;
-    int32_t mode = MODE_DENSE;
-    if (c->frontier) {
-      const bool dense = c->has_reverse ? 100 * (int64_t)pairs >= (int64_t)c->dense_pct * M
-                                        : 100 * (int64_t)chg >= (int64_t)c->dense_pct * N;
-      if (dense)
-        mode = MODE_DENSE;
-      else if (c->has_reverse && 100 * (int64_t)chg < (int64_t)c->sparse_pct * N)
-        mode = MODE_SPARSE;
-      else
-        mode = MODE_EDGE;
-    }
-    c->mode = mode;
+    c->chg = chg;
+    c->pairs = pairs;
+    c->mode = plan_mode(c);
     c->t += 1;
     c->parity ^= 1;
     c->work = 0ull;
@@ -1527,19 +1529,21 @@ __global__ void k_rebase_csr(const void* off_l, int bits, int64_t n, int64_t m, 
 
 // Puts a graph into slot `slot` so that the engine's next pass is its pass 0:
 // t0 is the engine pass index at that point, the region's blocks map to the
-// slot, and every node of the region counts as changed in the previous pass
+// slot, and every node of the graph counts as changed in the previous pass
 // (so any pass mode gathers all of its successors) and as unchanged so far in
 // the next one.
-__global__ void k_admit(PassCtl* ctl, GraphDev* graphs, int32_t slot, GraphDev val, int32_t* blk_graph, uint64_t* mod0,
-                        uint64_t* mod1, int64_t b0, int64_t b1) {
+__global__ void k_admit(PassCtl* ctl, GraphDev* graphs, int32_t slot, GraphDev val, int64_t m, int32_t* blk_graph,
+                        uint64_t* mod0, uint64_t* mod1, int64_t b0, int64_t b1) {
   const int par = ctl->parity;
   uint64_t* prev = par ? mod1 : mod0;
   uint64_t* next = par ? mod0 : mod1;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t b = b0 + t0; b < b1; b += stride) {
+    // the graph's own rows only (padding rows never count as changed)
+    const int64_t real = val.node_base + val.n - b * 64;
     blk_graph[b] = slot;
-    prev[b] = ~0ull;
+    prev[b] = real >= 64 ? ~0ull : (real > 0 ? (1ull << real) - 1ull : 0ull);
     next[b] = 0ull;
   }
   if (t0 == 0) {
@@ -1548,13 +1552,18 @@ __global__ void k_admit(PassCtl* ctl, GraphDev* graphs, int32_t slot, GraphDev v
     val.passes = 0;
     val.active = 1;
     graphs[slot] = val;
+    ctl->chg += (unsigned long long)val.n;
+    ctl->pairs += (unsigned long long)m;
   }
 }
 
+// New planning totals; the mode of the pass about to run is planned again
+// with them (admissions since the last pass changed both its inputs).
 __global__ void k_set_plan(PassCtl* ctl, int64_t listed_rows, int64_t arcs) {
   if (threadIdx.x == 0) {
     ctl->listed_rows = listed_rows;
     ctl->arcs = arcs;
+    ctl->mode = plan_mode(ctl);
   }
 }
 
@@ -1845,9 +1854,9 @@ hipError_t launch_rebase_csr(const void* off_l, int bits, int64_t n, int64_t m, 
   return hipGetLastError();
 }
 
-hipError_t launch_admit(PassCtl* ctl, GraphDev* graphs, int32_t slot, const GraphDev& val, int32_t* blk_graph,
-                        uint64_t* mod0, uint64_t* mod1, int64_t b0, int64_t b1, hipStream_t s) {
-  hipLaunchKernelGGL(k_admit, dim3(grid_for(b1 - b0 + 1, 256, 4096)), dim3(256), 0, s, ctl, graphs, slot, val,
+hipError_t launch_admit(PassCtl* ctl, GraphDev* graphs, int32_t slot, const GraphDev& val, int64_t m,
+                        int32_t* blk_graph, uint64_t* mod0, uint64_t* mod1, int64_t b0, int64_t b1, hipStream_t s) {
+  hipLaunchKernelGGL(k_admit, dim3(grid_for(b1 - b0 + 1, 256, 4096)), dim3(256), 0, s, ctl, graphs, slot, val, m,
                      blk_graph, mod0, mod1, b0, b1);
   return hipGetLastError();
 }

@@ -330,6 +330,7 @@ hb_status make_engine(hb_server* s, int b, Engine** out) {
   ENG_ALLOC(c->graphs, e->n_slots);
   ENG_ALLOC(c->blk_graph, N / 64);
   ENG_ALLOC(c->ctl, 1);
+
   hipStream_t st = c->stream;
   ENG_HIP(hb::launch_fill_zero(c->off, sizeof(int64_t) * (size_t)(N + 1), st));
   for (int i = 0; i < 2; ++i) ENG_HIP(hb::launch_fill_zero(c->mod[i], sizeof(uint64_t) * (size_t)(N / 64), st));
@@ -486,8 +487,8 @@ hb_status enqueue_admit(hb_server* s, Engine* e, Req* r) {
   gd.n = r->n;
   gd.packed = 0;
   gd.seed = r->rq.seed;
-  HB_HIP(hb::launch_admit(c->ctl, c->graphs, r->slot, gd, c->blk_graph, c->mod[0], c->mod[1], r->node_base / 64,
-                          (r->node_base + r->npad) / 64, st));
+  HB_HIP(hb::launch_admit(c->ctl, c->graphs, r->slot, gd, r->m, c->blk_graph, c->mod[0], c->mod[1],
+                          r->node_base / 64, (r->node_base + r->npad) / 64, st));
   HB_HIP(hb::launch_init_arena(e->b, r->node_base, r->node_base + r->npad, c->blk_graph, c->graphs, c->cnt[0],
                                c->cnt[1], c->S, c->H, c->E, c->lc, c->alpha_pp, st));
   e->slot_req[(size_t)r->slot] = r;

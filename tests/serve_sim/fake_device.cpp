@@ -127,13 +127,14 @@ hipError_t launch_set_plan(PassCtl* ctl, int64_t l, int64_t a, hipStream_t) {
   ctl->arcs = a;
   return hipSuccess;
 }
-hipError_t launch_admit(PassCtl* ctl, GraphDev* graphs, int32_t slot, const GraphDev& val, int32_t* blk, uint64_t* m0,
-                        uint64_t* m1, int64_t b0, int64_t b1, hipStream_t) {
+hipError_t launch_admit(PassCtl* ctl, GraphDev* graphs, int32_t slot, const GraphDev& val, int64_t m, int32_t* blk,
+                        uint64_t* m0, uint64_t* m1, int64_t b0, int64_t b1, hipStream_t) {
   uint64_t* prev = ctl->parity ? m1 : m0;
   uint64_t* next = ctl->parity ? m0 : m1;
   for (int64_t b = b0; b < b1; ++b) {
+    const int64_t real = val.node_base + val.n - b * 64;
     blk[b] = slot;
-    prev[b] = ~0ull;
+    prev[b] = real >= 64 ? ~0ull : (real > 0 ? (1ull << real) - 1ull : 0ull);
     next[b] = 0;
   }
   GraphDev v = val;
@@ -142,6 +143,8 @@ hipError_t launch_admit(PassCtl* ctl, GraphDev* graphs, int32_t slot, const Grap
   v.passes = 0;
   v.active = 1;
   graphs[slot] = v;
+  ctl->chg += (unsigned long long)val.n;
+  ctl->pairs += (unsigned long long)m;
   return hipSuccess;
 }
 hipError_t launch_rebase_csr(const void* off_l, int bits, int64_t n, int64_t m, int64_t nb, int64_t ab, int64_t* off,
@@ -191,6 +194,17 @@ hipError_t launch_device_pass(int, const PassArgs& a, int, uint2*, unsigned long
       abort();
     }
   }
+  // Change bits of the pass only ever name rows of resident graphs.
+  const uint64_t* prev = a.modb[c->parity];
+  for (int64_t w = 0; w < a.n / 64; ++w)
+    for (uint64_t bits = prev[w]; bits; bits &= bits - 1ull) {
+      const int64_t r = w * 64 + __builtin_ctzll(bits);
+      const GraphDev& gd = a.graphs[a.blk_graph[r >> 6]];
+      if (!gd.active || r < gd.node_base || r >= gd.node_base + gd.n) {
+        fprintf(stderr, "invariant: change bit of row %lld outside a resident graph\n", (long long)r);
+        abort();
+      }
+    }
   for (int g = 1; g < a.n_graphs; ++g) {
     const GraphDev& gd = a.graphs[g];
     if (!gd.active) continue;
@@ -205,6 +219,8 @@ hipError_t launch_device_pass(int, const PassArgs& a, int, uint2*, unsigned long
         abort();
       }
   }
+  // the bitmap this pass read is the one the next pass writes: cleared
+  for (int64_t w = 0; w < a.n / 64; ++w) a.modb[c->parity][w] = 0ull;
   c->t += 1;
   c->parity ^= 1;
   return hipSuccess;
@@ -250,6 +266,8 @@ hb::PassArgs device_args(hb_ctx* c) {
   a.blk_graph = c->blk_graph;
   a.ctl = c->ctl;
   a.n_graphs = c->n_graphs;
+  a.modb[0] = c->mod[0];
+  a.modb[1] = c->mod[1];
   return a;
 }
 thread_local std::string g_err;
