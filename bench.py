@@ -87,6 +87,16 @@ def read_traffic(kname, workload):
     return int(rec["hbm_bytes_per_launch"])
 
 
+def codes_pass(ps):
+    """A first pass that recomputed singleton counters from node hashes
+    instead of reading them."""
+    return ps["mode"] == 0 and ps["slices_gathered"] == 0 and ps["counters_gathered"] > 0
+
+
+def kernel_of(ps, b):
+    return ("k_expand_codes<{b}>" if codes_pass(ps) else KERNEL_OF_MODE[ps["mode"]]).format(b=b)
+
+
 def pass_bytes(ps, listed, p):
     """Algorithmic HBM bytes of one pass's expand kernel.
 
@@ -96,8 +106,13 @@ def pass_bytes(ps, listed, p):
     (24 B).  Every scanned arc: its successor id (4 B).  Every gathered
     successor in a slice pass: its 2 B slice mask.  Every gathered 16-byte
     counter slice: 16 B.  Every written counter: p B.  Every changed row:
-    estimate, accumulators and slice mask written back (26 B)."""
+    estimate, accumulators and slice mask written back (26 B).  A first pass
+    from node hashes reads no counter: its rows read only the estimate and
+    accumulators, its arcs only the successor id."""
     per_row = 28 + (4 if ps["mode"] == 2 else 0)
+    if codes_pass(ps):
+        return (per_row * listed + 24 * ps["rows_loaded"] + 4 * ps["arcs_scanned"]
+                + p * ps["rows_written"] + 26 * ps["rows_changed"])
     per_arc = 4
     return (per_row * listed + (p + 24) * ps["rows_loaded"] + per_arc * ps["arcs_scanned"]
             + 16 * ps["slices_gathered"] + 2 * (ps["counters_gathered"] if ps["mode"] == 3 else 0)
@@ -595,7 +610,7 @@ def main():
         step_passes.append(passes)
         infos = [g.pass_stats(t) for t in range(passes)]
         for ps in infos:
-            kname = KERNEL_OF_MODE[ps["mode"]].format(b=w["log2m"])
+            kname = kernel_of(ps, w["log2m"])
             acc = per_kernel.setdefault(kname, [0.0, 0, 0])
             acc[0] += ps["expand_ms"]
             acc[1] += pass_bytes(ps, listed, p)

@@ -183,7 +183,10 @@ hb_status hb_stats(hb_ctx* c, hb_stats_t* s);
 /* Per-pass record (pass in [0, passes)).  Work counters are exact:
  *   arcs_scanned       successor ids read (every arc of every row the pass runs)
  *   counters_gathered  successors whose counter (or part of it) was read
- *   slices_gathered    16-byte counter slices read for them
+ *   slices_gathered    16-byte counter slices read for them (0 in a first pass
+ *                      of an unweighted single-seed context with p <= 256,
+ *                      which recomputes each successor's singleton counter
+ *                      from its hash)
  *   rows_loaded        rows whose own counter the pass read (in edge, slice and
  *                      sparse passes only rows with a changed successor or a
  *                      counter changed in the previous pass)

@@ -288,12 +288,14 @@ hb_status do_reset(hb_ctx* c, uint64_t seed) {
     HB_HIP(hipStreamSynchronize(c->stream));  // the seed upload reads host memory
     return HB_OK;
   }
+  c->singletons = false;
   if (c->weights) {
     HB_HIP(hb::launch_init_weighted(c->b, c->n, seed, c->weights, c->cnt[0], c->cnt[1], c->S, c->H, c->D, c->E, c->lc,
                                     c->alpha_pp, c->stream));
   } else {
     HB_HIP(hb::launch_init_nodes(c->b, c->n, seed, c->cnt[0], c->cnt[1], c->S, c->H, c->E, c->lc,
                                  c->alpha_pp, c->stream));
+    c->singletons = true;
     if (c->D) HB_HIP(hb::launch_fill_zero(c->D, sizeof(double) * (size_t)c->n, c->stream));
   }
   c->nf.clear();
@@ -720,6 +722,8 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
   a.qdense = c->opt.qdense ? 1 : 0;
   a.seg_lanes = (1 << c->b_seed) / 16;
   a.D = c->D;
+  a.singletons = (mode == hb::MODE_FIRST && c->singletons) ? 1 : 0;
+  a.seed = c->seed;
   a.disc_f = c->disc.empty() ? 0.0 : c->disc[(size_t)std::min<int64_t>(c->t, (int64_t)c->disc.size() - 1)];
   const bool timing = c->opt.timing != 0;
   hipError_t e = hipSuccess;

@@ -86,6 +86,9 @@ struct hb_ctx {
   std::vector<int32_t> seed_passes;  // pass count of each seed once converged, else -1
   // Sec. 6 node weights (device, n entries; null: every weight 1).
   int32_t* weights = nullptr;
+  // The counters hold singletons (an unweighted single-graph, single-seed
+  // reset): the first pass recomputes successor counters from node hashes.
+  bool singletons = false;
   // Sec. 7 discounted-gain accumulator and its table f(1..L) (empty: off).
   double* D = nullptr;
   std::vector<double> disc;

@@ -127,6 +127,11 @@ struct PassArgs {
   // disc_f = f(t+1) for this pass.
   double* D;
   double disc_f;
+  // First pass of an unweighted single-graph, single-seed context: nonzero
+  // when every counter still holds only its own node's item, so a counter
+  // can be recomputed from the node's hash with `seed`.
+  int32_t singletons;
+  uint64_t seed;
   // Multi-graph contexts (null otherwise): graph of each 64-node block, the
   // per-graph state, and the device pass control; with ctl set, cur/nxt,
   // mod_prev/mod_cur, mode, epoch and the stats halves are taken from ctl
@@ -142,6 +147,8 @@ struct PassArgs {
 
 // Launchers (hb_kernels.hip).  All return the launch status.
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+// Singleton counters of nodes 0..n-1 in both buffers, S = H = 0, E their
+// estimate.
 hipError_t launch_init_nodes(int log2m, int64_t n, uint64_t seed, uint8_t* cur, uint8_t* nxt,
                              double* S, double* H, double* E, const double* lc, double alpha_pp,
                              hipStream_t s);

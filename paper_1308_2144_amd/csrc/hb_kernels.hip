@@ -868,6 +868,214 @@ __global__ __launch_bounds__(256) void k_merge(PassArgs A0) {
   flush_counts<FL>(A, c, h, lane);
 }
 
+// --- the first pass from node hashes --------------------------------------------
+//
+// Before the first pass every counter holds its own node's single item, so it
+// is fully described by the index j and value of its one nonzero register,
+// both taken from the node's hash (code = j << 8 | value), and the
+// register-wise maximum over a row's successors is the maximum, per register
+// index, of their codes' values.  The first pass of an unweighted
+// single-graph context therefore recomputes each successor's code from its id
+// instead of reading its p-byte counter: lanes take consecutive arcs, hash
+// the successor, and fold the code into a register array in LDS (one 32-bit
+// word per register, LDS atomic max), which the row's lane group then packs
+// into its 16-byte slices.  The pass reads only the arc list; the counters,
+// accumulators and change bits it writes are the ones the gather over
+// counters writes.
+
+constexpr int CODE_WORDS = 1024;  // LDS words per wavefront: (64 / G) rows x p registers
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Code of node v's singleton counter: register index j (the hash's top B
+// bits) and value rho+ of the remaining bits, as the counters are initialised.
+template <int B>
+__device__ __forceinline__ uint32_t singleton_code(uint64_t v, uint64_t seed) {
+  const uint64_t h = node_hash(v, seed);
+  const uint32_t j = (uint32_t)(h >> (64 - B));
+  const uint64_t rest = h << B;
+  const uint32_t r = rest == 0ull ? (uint32_t)(65 - B) : (uint32_t)__clzll((long long)rest) + 1u;
+  return (j << 8) | r;
+}
+
+// Lane gl's 16-byte slice of the singleton counter with code x.
+__device__ __forceinline__ uint4 code_slice(uint32_t x, int gl) {
+  const uint32_t j = x >> 8;
+  const uint32_t val = (x & 0xffu) << (8u * (j & 3u));
+  const uint32_t q = (j >> 2) & 3u;
+  const bool mine = (int)(j >> 4) == gl;
+  return make_uint4(mine && q == 0u ? val : 0u, mine && q == 1u ? val : 0u, mine && q == 2u ? val : 0u,
+                    mine && q == 3u ? val : 0u);
+}
+
+// Registers gl*16 .. gl*16+15 of an LDS register array packed into the
+// lane's slice; the words are cleared for the next row.
+__device__ __forceinline__ uint4 take_slice(uint32_t* regs, int gl) {
+  uint4* q = reinterpret_cast<uint4*>(regs + gl * 16);
+  const uint4 a = q[0], b = q[1], c = q[2], d = q[3];
+  q[0] = zero4();
+  q[1] = zero4();
+  q[2] = zero4();
+  q[3] = zero4();
+  return make_uint4(a.x | a.y << 8 | a.z << 16 | a.w << 24, b.x | b.y << 8 | b.z << 16 | b.w << 24,
+                    c.x | c.y << 8 | c.z << 16 | c.w << 24, d.x | d.y << 8 | d.z << 16 | d.w << 24);
+}
+
+// Folds the codes of successors idx[k], idx[k + st], ... < e into regs.
+template <int B>
+__device__ __forceinline__ void fold_codes(const PassArgs& A, uint32_t* regs, int64_t k, int64_t e, int64_t st) {
+  for (; k < e; k += st * U) {
+    int32_t w[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t kk = k + u * st;
+      w[u] = kk < e ? ld_stream(A.idx + kk) : -1;
+    }
+    uint32_t x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) x[u] = w[u] >= 0 ? singleton_code<B>((uint64_t)w[u], A.seed) : 0u;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (x[u] & 0xffu)
+        __hip_atomic_fetch_max(regs + (x[u] >> 8), x[u] & 0xffu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
+// As preload, with the own counter taken from its code.
+template <int B>
+__device__ __forceinline__ RowPre preload_code(const PassArgs& A, int64_t row, int gl) {
+  RowPre r;
+  r.own = code_slice(singleton_code<B>((uint64_t)row, A.seed), gl);
+  r.e = r.s = r.h = r.dd = 0.0;
+  if (gl == 0) {
+    r.e = ld_stream(A.E + row);
+    r.s = ld_stream(A.S + row);
+    r.h = ld_stream(A.H + row);
+  }
+  return r;
+}
+
+// 64 light-row list entries per wavefront, W rows at a time (one per lane group).
+template <int B>
+__device__ __forceinline__ void light_codes(const PassArgs& A, uint32_t* lds, int64_t lw, int lane) {
+  constexpr int P = 1 << B;
+  constexpr int G = P / 16;
+  constexpr int W = 64 / G;
+  const int gl = lane % G;
+  const int grp = lane / G;
+  const int64_t i = lw * 64 + lane;
+  int64_t row = 0, s = 0, deg = 0;
+  if (i < A.n_light) {
+    row = A.light[i];
+    s = A.off[row];
+    deg = A.off[row + 1] - s;
+  }
+  const uint64_t live = __ballot(i < A.n_light);
+  uint32_t* regs = lds + grp * P;
+  Counts c{};
+  for (int r = 0; r < G; ++r) {
+    const int rl = r * W + grp;
+    const int64_t rrow = __shfl(row, rl);
+    const int64_t rs = __shfl(s, rl);
+    const int64_t rd = __shfl(deg, rl);
+    const bool on = ((live >> rl) & 1ull) != 0ull;
+    RowPre pre;
+    if (on) {
+      pre = preload_code<B>(A, rrow, gl);
+      fold_codes<B>(A, regs, rs + gl, rs + rd, G);
+    }
+    wave_sync();
+    if (on) {
+      const uint4 acc = take_slice(regs, gl);
+      if (gl == 0) {
+        c.gath += (uint32_t)rd;
+        c.arcs += (uint32_t)rd;
+      }
+      (void)finish_row<B, false>(A, rrow, acc, rd > 0, pre, false, gl, grp, c);
+    }
+    wave_sync();
+  }
+  flush_counts(A, c, lw, lane);
+}
+
+// One medium row per wavefront: all 64 lanes fold its arcs.
+template <int B>
+__device__ __forceinline__ void medium_codes(const PassArgs& A, uint32_t* lds, int64_t mi, int lane) {
+  constexpr int G = (1 << B) / 16;
+  const int gl = lane % G;
+  const int grp = lane / G;
+  const int64_t row = A.medium[mi];
+  const int64_t s = A.off[row];
+  const int64_t deg = A.off[row + 1] - s;
+  Counts c{};
+  RowPre pre;
+  if (grp == 0) pre = preload_code<B>(A, row, gl);
+  fold_codes<B>(A, lds, s + lane, s + deg, 64);
+  wave_sync();
+  if (grp == 0) {
+    const uint4 acc = take_slice(lds, gl);
+    if (gl == 0) {
+      c.gath += (uint32_t)deg;
+      c.arcs += (uint32_t)deg;
+    }
+    (void)finish_row<B, false>(A, row, acc, deg > 0, pre, false, gl, 0, c);
+  }
+  flush_counts(A, c, mi, lane);
+}
+
+// One chunk of a heavy row per workgroup: its four wavefronts fold into one
+// register array; the chunk's maximum goes to its partial counter (merged
+// with the row's own counter by k_merge).
+template <int B>
+__device__ __forceinline__ void heavy_codes(const PassArgs& A, uint32_t* lds, int64_t item, int lane, int wave) {
+  constexpr int P = 1 << B;
+  constexpr int G = P / 16;
+  const int gl = lane % G;
+  const int grp = lane / G;
+  const HeavyItem it = A.items[item];
+  fold_codes<B>(A, lds, it.e0 + wave * 64 + lane, it.e1, 256);
+  Counts c{};
+  if (lane == 0 && wave == 0) {
+    c.gath += (uint32_t)(it.e1 - it.e0);
+    c.arcs += (uint32_t)(it.e1 - it.e0);
+  }
+  flush_counts(A, c, item, lane);
+  __syncthreads();
+  if (wave == 0 && grp == 0)
+    *reinterpret_cast<uint4*>(A.partial + (size_t)item * P + (size_t)gl * 16) = take_slice(lds, gl);
+}
+
+// Work items as in expand_item: [heavy chunks][medium rows][light rows].
+template <int B>
+__global__ HB_EXPAND_ATTR void k_expand_codes(PassArgs A) {
+  __shared__ uint32_t regs[4][CODE_WORDS];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  uint4* z = reinterpret_cast<uint4*>(&regs[0][0]);
+  for (int i = threadIdx.x; i < CODE_WORDS; i += 256) z[i] = zero4();  // 4 waves x CODE_WORDS words
+  __syncthreads();
+  int64_t b = blockIdx.x;
+  if (b == 0)
+    for (int i = threadIdx.x; i < STAT_SLOTS * STAT_K; i += blockDim.x) A.stats_next[i] = 0ull;
+  if (b < A.n_items) {
+    heavy_codes<B>(A, regs[0], b, lane, wave);
+    return;
+  }
+  b -= A.n_items;
+  const int64_t med_wgs = (A.n_medium + 3) / 4;
+  if (b < med_wgs) {
+    const int64_t mi = b * 4 + wave;
+    if (mi < A.n_medium) medium_codes<B>(A, regs[wave], mi, lane);
+    return;
+  }
+  b -= med_wgs;
+  const int64_t lw = b * 4 + wave;
+  if (lw * 64 < A.n_light) light_codes<B>(A, regs[wave], lw, lane);
+}
+
 // Counters wider than 256 bytes: one workgroup per 64-row block, rows in
 // sequence, each thread owning 16-byte chunks tid, tid+256, ...; the new
 // counter is staged in LDS (p bytes) until the change decision is known.
@@ -1684,8 +1892,44 @@ hipError_t launch_lanes(int log2m, const PassArgs& a, hipStream_t s, hipEvent_t 
   return hipGetLastError();
 }
 
+// First pass from node hashes: the codes kernel, then the plain merge of heavy
+// rows.
+hipError_t launch_codes(int log2m, const PassArgs& a, hipStream_t s, hipEvent_t ev_mid) {
+  const int64_t grid = a.n_items + (a.n_medium + 3) / 4 + (a.n_light + 255) / 256;
+  if (grid > 0) {
+    const dim3 g((unsigned)grid), t(256);
+    switch (log2m) {
+      case 4: hipLaunchKernelGGL(k_expand_codes<4>, g, t, 0, s, a); break;
+      case 5: hipLaunchKernelGGL(k_expand_codes<5>, g, t, 0, s, a); break;
+      case 6: hipLaunchKernelGGL(k_expand_codes<6>, g, t, 0, s, a); break;
+      case 7: hipLaunchKernelGGL(k_expand_codes<7>, g, t, 0, s, a); break;
+      case 8: hipLaunchKernelGGL(k_expand_codes<8>, g, t, 0, s, a); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (ev_mid) {
+    e = hipEventRecord(ev_mid, s);
+    if (e != hipSuccess) return e;
+  }
+  if (a.n_hrows > 0) {
+    const unsigned mg = (unsigned)((a.n_hrows + 3) / 4);
+    switch (log2m) {
+      case 4: hipLaunchKernelGGL((k_merge<4, false>), dim3(mg), dim3(256), 0, s, a); break;
+      case 5: hipLaunchKernelGGL((k_merge<5, false>), dim3(mg), dim3(256), 0, s, a); break;
+      case 6: hipLaunchKernelGGL((k_merge<6, false>), dim3(mg), dim3(256), 0, s, a); break;
+      case 7: hipLaunchKernelGGL((k_merge<7, false>), dim3(mg), dim3(256), 0, s, a); break;
+      default: hipLaunchKernelGGL((k_merge<8, false>), dim3(mg), dim3(256), 0, s, a); break;
+    }
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_pass(int log2m, const PassArgs& a, hipStream_t s, hipEvent_t ev_mid) {
   if (a.n_blocks == 0) return hipSuccess;
+  if (a.singletons && a.mode == MODE_FIRST && !a.D && log2m <= 8 && !(a.seg_lanes > 0 && a.seg_lanes < (1 << log2m) / 16))
+    return launch_codes(log2m, a, s, ev_mid);
   if (log2m <= 8) {
     if (a.seg_lanes > 0 && a.seg_lanes < (1 << log2m) / 16) return launch_lanes<FL_ENS>(log2m, a, s, ev_mid);
     if (a.D) return launch_lanes<FL_DISC>(log2m, a, s, ev_mid);

@@ -188,7 +188,8 @@ def test_pass_counters():
         assert b_["mode"] == (0 if t == 0 else 1)
         assert a["mode"] == (0 if t == 0 else 2) and c["mode"] == (0 if t == 0 else 3)
         assert b_["arcs_scanned"] == m and b_["counters_gathered"] == m and b_["rows_loaded"] == nonempty
-        assert b_["slices_gathered"] == m * G
+        # the first pass recomputes singleton counters instead of reading slices
+        assert b_["slices_gathered"] == (0 if t == 0 else m * G)
         # slice passes scan every row but read a row's own counter only when a
         # changed slice turned up or the row changed before
         assert c["arcs_scanned"] == m and c["rows_changed"] <= c["rows_loaded"] <= nonempty
@@ -204,6 +205,48 @@ def test_pass_counters():
     assert sum(p["slices_gathered"] for p in sliced["pass_stats"]) < sliced["passes"] * m * G
     # the last pass visits only rows next to the previous pass's changes
     assert sparse["pass_stats"][-1]["rows_loaded"] < nonempty
+
+
+@pytest.mark.parametrize("b", [4, 5, 6, 7, 8])
+@pytest.mark.parametrize("opts", [dict(), dict(light_max=2, heavy_min=6, chunk=3),
+                                  dict(light_max=1, heavy_min=100000), dict(light_max=4, heavy_min=40, chunk=17)])
+def test_first_pass_from_hashes(b, opts):
+    """Pass 0 of a plain context recomputes the successors' singleton counters
+    from their hashes and folds them in LDS (light rows by lane groups, medium
+    rows by wavefronts, heavy chunks by workgroups): equal to the oracle's
+    pass 0, with no counter slice read."""
+    for name, (off, idx) in [("rmat10t", gg.rmat(10, 12, seed=31, transpose=True)), ("star700", gg.star(700)),
+                             ("rand3001", gg.random_digraph(3001, 30000, seed=32, self_loops=True)),
+                             ("isolated70", gg.empty(70))]:
+        got, _ = check(off, idx, b, 900 + b, f"{name}/b{b}/{opts}", max_passes=1, **opts)
+        p0 = got["pass_stats"][0]
+        assert p0["mode"] == 0 and p0["slices_gathered"] == 0
+        assert p0["counters_gathered"] == p0["arcs_scanned"] == len(idx)
+
+
+def test_first_pass_reads_counters_when_weighted():
+    """Weighted counters start with several items, so pass 0 gathers counter
+    slices (only singletons are recomputed from hashes); the result equals the
+    oracle's, and an unweighted reset afterwards recomputes them again."""
+    import paper_1308_2144_amd as hb
+
+    off, idx = gg.rmat(9, 8, seed=33, transpose=True)
+    n = len(off) - 1
+    w = np.random.default_rng(34).integers(1, 4, size=n).astype(np.int32)
+    with hb.HyperBall(off, idx, 6, 5) as g:
+        g.set_weights(w)
+        g.reset(5)
+        g.run(1)
+        assert g.pass_stats(0)["slices_gathered"] == 4 * len(idx)
+        regs = g.registers()
+        g.set_weights(None)
+        g.reset(5)
+        g.run(1)
+        assert g.pass_stats(0)["slices_gathered"] == 0
+        plain = g.registers()
+    ref = oracle.run_ext(off.astype(np.int64), idx, 6, 5, max_passes=1, weights=w)
+    assert np.array_equal(regs, ref["regs"])
+    assert np.array_equal(plain, oracle.run(off.astype(np.int64), idx, 6, 5, max_passes=1)["regs"])
 
 
 def test_validation_rejects_bad_indices():
