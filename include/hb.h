@@ -101,7 +101,12 @@ typedef struct {
  *   graph_passes batched contexts: passes per captured hipGraph replay in
  *              hb_run (<= 0: 4; convergence is read back once per replay).
  *   neighbourhood  single-graph contexts: 1 records the neighbourhood
- *              function N(t) at every pass (hb_neighbourhood). */
+ *              function N(t) at every pass (hb_neighbourhood).
+ *   pairs      single-graph contexts with push = 1: 1 runs sparse passes
+ *              from lists of the arcs into changed counters (sorted by
+ *              source row) instead of activation stamps, when they fit the
+ *              list capacity sized at init (about (m + n) / 16 pairs, all of
+ *              them for m + n <= 2^20); 0: activation stamps only. */
 typedef struct {
   int32_t frontier;
   int32_t light_max;
@@ -117,6 +122,7 @@ typedef struct {
   int32_t wgs_per_cu;
   int32_t graph_passes;
   int32_t neighbourhood;
+  int32_t pairs;
 } hb_options;
 
 void hb_default_options(hb_options* opt);

@@ -48,7 +48,8 @@ class hb_options(ctypes.Structure):
                 ("dense_pct", ctypes.c_int32), ("push", ctypes.c_int32),
                 ("sparse_pct", ctypes.c_int32), ("qdense", ctypes.c_int32),
                 ("slice", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
-                ("graph_passes", ctypes.c_int32), ("neighbourhood", ctypes.c_int32)]
+                ("graph_passes", ctypes.c_int32), ("neighbourhood", ctypes.c_int32),
+                ("pairs", ctypes.c_int32)]
 
 
 class hb_stats_t(ctypes.Structure):

@@ -51,6 +51,17 @@ void release(hb_ctx* c) {
   (void)hipFree(c->act);
   (void)hipFree(c->push_items);
   (void)hipFree(c->push_count);
+  {
+    hb::PairBufs& pb = c->pb;
+    for (int i = 0; i < 2; ++i) {
+      (void)hipFree(pb.keys[i]);
+      (void)hipFree(pb.vals[i]);
+    }
+    void* bufs[] = {pb.uniq, pb.cnt, pb.rstart, pb.ni, pb.ioff, pb.mp, pb.pbase, pb.num_runs, pb.num_items,
+                    pb.num_multi, pb.multi, pb.npairs, pb.ppos, pb.items, pb.partial, pb.tmp};
+    for (void* b : bufs) (void)hipFree(b);
+    if (c->npairs_host) (void)hipHostFree(c->npairs_host);
+  }
   (void)hipFree(c->items);
   (void)hipFree(c->hrows);
   (void)hipFree(c->partial);
@@ -307,6 +318,45 @@ hb_status do_reset(hb_ctx* c, uint64_t seed) {
   return HB_OK;
 }
 
+// Pair-list buffers of sparse passes: every pair for small graphs, else
+// about (m + n) / 16 (the sparse tail of a large graph needs far fewer).
+hb_status alloc_pairs(hb_ctx* c) {
+  hb::PairBufs& pb = c->pb;
+  const int64_t all = c->m + c->n;
+  const int64_t cap = std::min<int64_t>(all <= (1ll << 20) ? all : std::max<int64_t>(1ll << 20, all / 16),
+                                        0x7fffffffLL);
+  pb.cap = cap;
+  pb.items_cap = cap + cap / hb::RUN_CHUNK + 1;
+  pb.slots_cap = cap / (hb::RUN_CHUNK / 2) + 2;
+  pb.multi_cap = cap / (hb::RUN_CHUNK + 1) + 1;
+  int bits = 1;
+  while (bits < 32 && (1ll << bits) < c->n) ++bits;
+  pb.end_bit = bits;
+  pb.tmp_bytes = hb::pair_tmp_bytes(cap, bits);
+  bool ok = true;
+  for (int i = 0; i < 2; ++i) {
+    ok = ok && dmalloc(&pb.keys[i], (size_t)cap) == hipSuccess;
+    ok = ok && dmalloc(&pb.vals[i], (size_t)cap) == hipSuccess;
+  }
+  uint32_t** runs[7] = {&pb.uniq, &pb.cnt, &pb.rstart, &pb.ni, &pb.ioff, &pb.mp, &pb.pbase};
+  for (auto* r : runs) ok = ok && dmalloc(r, (size_t)cap) == hipSuccess;
+  ok = ok && dmalloc(&pb.num_runs, 1) == hipSuccess && dmalloc(&pb.num_items, 1) == hipSuccess &&
+       dmalloc(&pb.num_multi, 1) == hipSuccess && dmalloc(&pb.multi, (size_t)pb.multi_cap) == hipSuccess &&
+       dmalloc(&pb.npairs, 1) == hipSuccess && dmalloc(&pb.items, (size_t)pb.items_cap) == hipSuccess &&
+       dmalloc(&pb.ppos, (size_t)c->n + (size_t)(c->m / hb::PUSH_CHUNK) + 1) == hipSuccess &&
+       dmalloc(&pb.partial, (size_t)pb.slots_cap * (size_t)c->p) == hipSuccess &&
+       hipMalloc(&pb.tmp, pb.tmp_bytes) == hipSuccess &&
+       hipHostMalloc(reinterpret_cast<void**>(&c->npairs_host), sizeof(unsigned long long), hipHostMallocDefault) ==
+           hipSuccess;
+  if (!ok) return fail(HB_ENOMEM, "cannot allocate the pair lists of sparse passes");
+  // Unsorted lists start as valid pairs (row 0, no successor), so that a
+  // pass whose pair count disagreed with its plan could not read an
+  // undefined row; the host rejects such a pass after it ran.
+  HB_HIP(hb::launch_fill_zero(pb.keys[0], sizeof(uint32_t) * (size_t)cap, c->stream));
+  HB_HIP(hipMemsetAsync(pb.vals[0], 0xFF, sizeof(int32_t) * (size_t)cap, c->stream));
+  return HB_OK;
+}
+
 hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, const hb_options* opt,
                     void* stream, const std::vector<int32_t>* blk_graph = nullptr) {
   c->n = g->n;
@@ -397,6 +447,10 @@ hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, co
         dmalloc(&c->push_count, 1) != hipSuccess)
       return fail(HB_ENOMEM, "cannot allocate the reverse CSR");
     HB_HIP(hb::build_reverse(c->off, c->idx, n, m, c->roff, c->ridx, c->stream));
+    if (c->opt.pairs && !blk_graph) {
+      const hb_status st = alloc_pairs(c);
+      if (st != HB_OK) return st;
+    }
   }
 
   // Counters, bitmaps, accumulators.
@@ -585,6 +639,7 @@ void hb_default_options(hb_options* opt) {
   opt->wgs_per_cu = 5;
   opt->graph_passes = 4;
   opt->neighbourhood = 0;
+  opt->pairs = 1;
 }
 
 hb_status hb_init(hb_ctx** out, const hb_csr* g, int32_t log2m, uint64_t seed, const hb_options* opt,
@@ -726,16 +781,29 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
   a.seed = c->seed;
   a.disc_f = c->disc.empty() ? 0.0 : c->disc[(size_t)std::min<int64_t>(c->t, (int64_t)c->disc.size() - 1)];
   const bool timing = c->opt.timing != 0;
+  a.ridx = c->ridx;
+  // Sparse passes run from pair lists when the exact pair count (arcs into
+  // the counters that changed, plus those rows) fits the lists.
+  const int64_t pairs = (mode == hb::MODE_SPARSE && c->pb.cap > 0 && c->last_pairs >= 0 && c->last_nmod > 0)
+                            ? c->last_pairs + c->last_nmod
+                            : 0;
+  const bool use_pairs = pairs > 0 && pairs <= c->pb.cap;
+  if (use_pairs) a.act = nullptr;
   hipError_t e = hipSuccess;
   if (timing) e = hipEventRecord(c->ev[0], c->stream);
   if (e == hipSuccess && a.act)
     e = hb::launch_push(a.mod_prev, c->n_blocks, c->n, c->roff, c->ridx, c->push_items, c->push_count, c->act,
                         a.epoch, c->stream);
+  if (e == hipSuccess && use_pairs) e = hb::launch_pair_build(a, c->pb, pairs, c->push_items, c->push_count, c->stream);
   if (e == hipSuccess) e = hb::launch_fill_zero(a.mod_cur, sizeof(uint64_t) * (size_t)c->n_blocks, c->stream);
   if (e == hipSuccess && a.dmask_cur)
     e = hb::launch_fill_zero(a.dmask_cur, sizeof(uint16_t) * (size_t)c->n, c->stream);
   if (e == hipSuccess && timing) e = hipEventRecord(c->ev[1], c->stream);
-  if (e == hipSuccess) e = hb::launch_pass(c->b, a, c->stream, timing ? c->ev[2] : nullptr);
+  if (e == hipSuccess)
+    e = use_pairs ? hb::launch_pair_pass(c->b, a, c->pb, pairs, c->stream, timing ? c->ev[2] : nullptr)
+                  : hb::launch_pass(c->b, a, c->stream, timing ? c->ev[2] : nullptr);
+  if (e == hipSuccess && use_pairs)
+    e = hipMemcpyAsync(c->npairs_host, c->pb.npairs, sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess && timing) e = hipEventRecord(c->ev[3], c->stream);
   if (e == hipSuccess && c->esum_out) e = enqueue_esum(c);
   if (e == hipSuccess)
@@ -745,6 +813,11 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
   if (e != hipSuccess) {
     c->failed = true;
     return fail(HB_EDEVICE, std::string("pass ") + std::to_string(c->t) + ": " + hipGetErrorString(e));
+  }
+  if (use_pairs && *c->npairs_host != (unsigned long long)pairs) {
+    c->failed = true;
+    return fail(HB_EDEVICE, "pass " + std::to_string(c->t) + ": " + std::to_string(*c->npairs_host) +
+                                " pairs emitted, " + std::to_string(pairs) + " planned");
   }
   unsigned long long sum[hb::STAT_K] = {};
   unsigned long long seeds_changed = 0;

@@ -127,6 +127,8 @@ struct hb_ctx {
   int32_t* act = nullptr;
   uint2* push_items = nullptr;
   unsigned long long* push_count = nullptr;
+  hb::PairBufs pb;              // pair lists of sparse passes (pb.cap = 0: none)
+  unsigned long long* npairs_host = nullptr;  // pinned: pairs the last pair pass emitted
   uint8_t* partial = nullptr;
   unsigned long long* stats = nullptr;       // 2 halves of STAT_SLOTS * STAT_K
   unsigned long long* stats_host = nullptr;  // pinned

@@ -226,4 +226,60 @@ hipError_t launch_push(const uint64_t* mod_prev, int64_t n_words, int64_t n, con
                        const int32_t* ridx, uint2* items, unsigned long long* count, int32_t* act,
                        int32_t epoch, hipStream_t s);
 
+// ---- sparse passes from pair lists (single-graph contexts) ----------------
+// Every arc v -> u whose successor u changed in the previous pass becomes a
+// pair (v, u), every changed u also (u, -1) (its own write-back); the pairs
+// are sorted by v, and each run of equal v is one row's work, cut into items
+// of at most RUN_CHUNK pairs (runs of several items leave partial counters
+// that a merge kernel folds).
+constexpr int RUN_CHUNK = 64;
+
+struct PairItem {
+  int64_t start;   // first sorted pair
+  int32_t len;     // pairs
+  int32_t row;
+  int32_t nparts;  // items of the row's run
+  int32_t slot;    // partial slot (nparts > 1), else -1
+  int32_t pad[2];
+};
+
+// Device buffers of the pair path, sized for `cap` pairs at init.
+struct PairBufs {
+  int64_t cap = 0;                 // pairs
+  int64_t items_cap = 0;           // cap + cap / RUN_CHUNK + 1
+  int64_t slots_cap = 0;           // cap / (RUN_CHUNK / 2) + 2
+  int64_t multi_cap = 0;           // cap / (RUN_CHUNK + 1) + 1
+  int end_bit = 1;                 // key bits of the sort
+  uint32_t* keys[2] = {nullptr, nullptr};  // row of each pair: emitted, sorted
+  int32_t* vals[2] = {nullptr, nullptr};   // successor (-1: own write-back)
+  uint32_t* uniq = nullptr;        // per run: row
+  uint32_t* cnt = nullptr;         // per run: pairs
+  uint32_t* rstart = nullptr;      // per run: first sorted pair
+  uint32_t* ni = nullptr;          // per run: items
+  uint32_t* ioff = nullptr;        // per run: first item
+  uint32_t* mp = nullptr;          // per run: partial slots needed
+  uint32_t* pbase = nullptr;       // per run: first partial slot
+  int32_t* num_runs = nullptr;     // device scalars: runs, items, multi-item runs
+  uint32_t* num_items = nullptr;
+  uint32_t* num_multi = nullptr;
+  uint32_t* multi = nullptr;       // first item of each multi-item run
+  unsigned long long* npairs = nullptr;  // pairs reserved (checked against the plan)
+  uint32_t* ppos = nullptr;        // first pair of each push item (push item capacity)
+  PairItem* items = nullptr;
+  uint8_t* partial = nullptr;      // slots_cap x p bytes
+  void* tmp = nullptr;
+  size_t tmp_bytes = 0;
+};
+// hipcub scratch the pair path needs for `cap` pairs and `end_bit` key bits.
+size_t pair_tmp_bytes(int64_t cap, int end_bit);
+// Builds the sorted pair list and work items of a sparse pass (total = the
+// exact number of pairs: arcs into changed counters plus changed rows, at
+// most pb.cap); items/count are the push item scratch.  Enqueues only.
+hipError_t launch_pair_build(const PassArgs& a, const PairBufs& pb, int64_t total, uint2* items,
+                             unsigned long long* count, hipStream_t s);
+// Runs the pass over the pair items (expand, then the merge of multi-item
+// runs); ev_mid, if set, is recorded between the two.
+hipError_t launch_pair_pass(int log2m, const PassArgs& a, const PairBufs& pb, int64_t total, hipStream_t s,
+                            hipEvent_t ev_mid);
+
 }  // namespace hb

@@ -32,6 +32,8 @@
 //
 // There is no dense contraction here: the pass is a gather of p-byte rows and
 // byte-wise maxima, bound by HBM bandwidth, so no MFMA is involved.
+#include <algorithm>
+
 #include <hipcub/hipcub.hpp>
 
 #include "hb_internal.h"
@@ -924,23 +926,27 @@ __device__ __forceinline__ uint4 take_slice(uint32_t* regs, int gl) {
                     c.x | c.y << 8 | c.z << 16 | c.w << 24, d.x | d.y << 8 | d.z << 16 | d.w << 24);
 }
 
-// Folds the codes of successors idx[k], idx[k + st], ... < e into regs.
+// Folds the codes of successors idx[k], idx[k + st], ... < e into regs, UC
+// ids in flight.  The hash is the costly part (two 64-bit products), so a
+// slot no lane of the wavefront has is branched over, not computed and
+// discarded (light rows have only a few arcs per lane).
+constexpr int UC = 4;
+
 template <int B>
 __device__ __forceinline__ void fold_codes(const PassArgs& A, uint32_t* regs, int64_t k, int64_t e, int64_t st) {
-  for (; k < e; k += st * U) {
-    int32_t w[U];
+  for (; k < e; k += st * UC) {
+    int32_t w[UC];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+    for (int u = 0; u < UC; ++u) {
       const int64_t kk = k + u * st;
       w[u] = kk < e ? ld_stream(A.idx + kk) : -1;
     }
-    uint32_t x[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) x[u] = w[u] >= 0 ? singleton_code<B>((uint64_t)w[u], A.seed) : 0u;
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (x[u] & 0xffu)
-        __hip_atomic_fetch_max(regs + (x[u] >> 8), x[u] & 0xffu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    for (int u = 0; u < UC; ++u)
+      if (w[u] >= 0) {
+        const uint32_t x = singleton_code<B>((uint64_t)w[u], A.seed);
+        __hip_atomic_fetch_max(regs + (x >> 8), x & 0xffu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
   }
 }
 
@@ -1515,8 +1521,16 @@ __global__ void k_lower_bound(const int32_t* keys, int64_t m, int64_t n, int64_t
 }
 
 // One thread per bitmap word: every set bit w (a counter changed in the
-// previous pass) becomes ceil(rdeg(w)/PUSH_CHUNK) items.  Slots are reserved
-// with one atomic per wavefront.
+// previous pass) becomes ceil(rdeg(w)/PUSH_CHUNK) items (at least one with
+// OWN, whose first item also carries w's own write-back).  Slots are
+// reserved with one atomic per wavefront.
+template <bool OWN = false>
+__device__ __forceinline__ uint32_t push_item_count(const int64_t* roff, int64_t w) {
+  const uint32_t k = (uint32_t)((roff[w + 1] - roff[w] + PUSH_CHUNK - 1) / PUSH_CHUNK);
+  return OWN && k == 0u ? 1u : k;
+}
+
+template <bool OWN = false>
 __device__ __forceinline__ void push_items_body(const uint64_t* mod_prev, int64_t n_words, int64_t n,
                                                 const int64_t* roff, uint2* items, unsigned long long* count) {
   const int lane = threadIdx.x & 63;
@@ -1525,7 +1539,7 @@ __device__ __forceinline__ void push_items_body(const uint64_t* mod_prev, int64_
   uint32_t mine = 0;
   for (uint64_t bits = word; bits; bits &= bits - 1ull) {
     const int64_t w = i * 64 + __builtin_ctzll(bits);
-    if (w < n) mine += (uint32_t)((roff[w + 1] - roff[w] + PUSH_CHUNK - 1) / PUSH_CHUNK);
+    if (w < n) mine += push_item_count<OWN>(roff, w);
   }
   uint32_t incl = mine;
 #pragma unroll
@@ -1541,7 +1555,7 @@ __device__ __forceinline__ void push_items_body(const uint64_t* mod_prev, int64_
   for (uint64_t bits = word; bits; bits &= bits - 1ull) {
     const int64_t w = i * 64 + __builtin_ctzll(bits);
     if (w >= n) continue;
-    const uint32_t k = (uint32_t)((roff[w + 1] - roff[w] + PUSH_CHUNK - 1) / PUSH_CHUNK);
+    const uint32_t k = push_item_count<OWN>(roff, w);
     for (uint32_t c = 0; c < k; ++c) items[pos++] = make_uint2((uint32_t)w, c);
   }
 }
@@ -1584,6 +1598,205 @@ __global__ void k_push_apply_d(PassArgs A0, const uint2* items, const unsigned l
   const PassArgs A = resolve(A0);
   if (A.mode != MODE_SPARSE) return;
   push_apply_body(items, count, A.roff, A.ridx, const_cast<int32_t*>(A0.act), A.epoch);
+}
+
+// --- sparse passes from pair lists (single-graph contexts) -------------------
+//
+// A row can change in pass t only through a successor whose counter changed
+// in pass t-1, and must be rewritten if its own counter changed then.  Rather
+// than have every row with such a successor scan all its arcs and test each
+// successor's change bit, the pass lists exactly the pairs (v, u) with u
+// changed (u's in-arcs, from the reverse CSR) plus (u, -1) for every changed
+// u, sorts them by v, and runs each row over its own run of changed
+// successors.
+
+// One thread per bitmap word, as push_items_body with OWN, and also the
+// position of each item's pairs: a changed u owns rdeg(u) + 1 consecutive
+// pairs (its in-arcs in chunks of PUSH_CHUNK, its own entry after the first
+// chunk), reserved with one atomic per wavefront.
+__global__ void k_pair_items(const uint64_t* mod_prev, int64_t n_words, int64_t n, const int64_t* roff,
+                             uint2* items, uint32_t* ppos, unsigned long long* count, unsigned long long* npairs) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t word = i < n_words ? mod_prev[i] : 0ull;
+  uint32_t mine = 0;
+  unsigned long long mine_p = 0;
+  for (uint64_t bits = word; bits; bits &= bits - 1ull) {
+    const int64_t w = i * 64 + __builtin_ctzll(bits);
+    if (w >= n) continue;
+    mine += push_item_count<true>(roff, w);
+    mine_p += (unsigned long long)(roff[w + 1] - roff[w]) + 1ull;
+  }
+  uint32_t incl = mine;
+  unsigned long long incl_p = mine_p;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(incl, o);
+    const unsigned long long tp = __shfl_up(incl_p, o);
+    if (lane >= o) {
+      incl += t;
+      incl_p += tp;
+    }
+  }
+  const uint32_t total = __shfl(incl, 63);
+  const unsigned long long total_p = __shfl(incl_p, 63);
+  unsigned long long base = 0, base_p = 0;
+  if (lane == 63 && total) {
+    base = atomicAdd(count, (unsigned long long)total);
+    base_p = atomicAdd(npairs, total_p);
+  }
+  base = __shfl(base, 63);
+  base_p = __shfl(base_p, 63);
+  unsigned long long pos = base + incl - mine;
+  unsigned long long pp = base_p + incl_p - mine_p;
+  for (uint64_t bits = word; bits; bits &= bits - 1ull) {
+    const int64_t w = i * 64 + __builtin_ctzll(bits);
+    if (w >= n) continue;
+    const uint32_t k = push_item_count<true>(roff, w);
+    for (uint32_t c = 0; c < k; ++c) {
+      items[pos] = make_uint2((uint32_t)w, c);
+      ppos[pos] = (uint32_t)(pp + (unsigned long long)c * PUSH_CHUNK + (c > 0u ? 1ull : 0ull));
+      ++pos;
+    }
+    pp += (unsigned long long)(roff[w + 1] - roff[w]) + 1ull;
+  }
+}
+
+// One team of PAIR_TEAM lanes per push item (u, c): the pairs of u's in-arcs
+// c*PUSH_CHUNK .. at the item's position and, in u's first item, (u, -1)
+// after them (most changed nodes have few in-arcs, so a wavefront serves
+// several items at once).  Writes stop at cap (the host compares the reserved
+// total with its plan).
+constexpr int PAIR_TEAM = 8;
+
+__global__ void k_pair_apply(const uint2* items, const uint32_t* ppos, const unsigned long long* count,
+                             const int64_t* roff, const int32_t* ridx, uint32_t* keys, int32_t* vals, int64_t cap) {
+  const int tl = threadIdx.x % PAIR_TEAM;
+  const int64_t total = (int64_t)*count;
+  const int64_t nt = (int64_t)gridDim.x * (blockDim.x / PAIR_TEAM);
+  for (int64_t it = (int64_t)blockIdx.x * (blockDim.x / PAIR_TEAM) + threadIdx.x / PAIR_TEAM; it < total;
+       it += nt) {
+    const uint2 item = items[it];
+    const int64_t e0 = roff[item.x] + (int64_t)item.y * PUSH_CHUNK;
+    const int64_t left = roff[item.x + 1] - e0;
+    const int64_t ne = left < 0 ? 0 : (left < PUSH_CHUNK ? left : PUSH_CHUNK);
+    const int64_t base = ppos[it];
+    for (int64_t i = tl; i < ne; i += PAIR_TEAM) {
+      const int64_t at = base + i;
+      if (at < cap) {
+        keys[at] = (uint32_t)ridx[e0 + i];
+        vals[at] = (int32_t)item.x;
+      }
+    }
+    if (item.y == 0u && tl == 0 && base + ne < cap) {
+      keys[base + ne] = item.x;
+      vals[base + ne] = -1;
+    }
+  }
+}
+
+// Per run r < R: its items and partial slots; entries from R to total are
+// cleared so that the scans over `total` entries see zeros there.
+__global__ void k_run_parts(const int32_t* num_runs, int64_t total, uint32_t* cnt, uint32_t* ni, uint32_t* mp) {
+  const int64_t R = *num_runs;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < total; r += stride) {
+    uint32_t k = 0;
+    if (r < R)
+      k = (cnt[r] + RUN_CHUNK - 1) / RUN_CHUNK;
+    else
+      cnt[r] = 0u;
+    ni[r] = k;
+    mp[r] = k > 1u ? k : 0u;
+  }
+}
+
+// Writes the items of every run, the list of multi-item runs and the item count.
+__global__ void k_run_items(const int32_t* num_runs, const uint32_t* uniq, const uint32_t* cnt,
+                            const uint32_t* rstart, const uint32_t* ni, const uint32_t* ioff, const uint32_t* pbase,
+                            PairItem* items, uint32_t* multi, uint32_t* num_multi, uint32_t* num_items) {
+  const int64_t R = *num_runs;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r == 0 && R == 0) *num_items = 0u;
+  if (r >= R) return;
+  const uint32_t k = ni[r];
+  for (uint32_t j = 0; j < k; ++j) {
+    PairItem it;
+    it.start = (int64_t)rstart[r] + (int64_t)j * RUN_CHUNK;
+    const uint32_t rest = cnt[r] - j * RUN_CHUNK;
+    it.len = (int32_t)(rest < (uint32_t)RUN_CHUNK ? rest : (uint32_t)RUN_CHUNK);
+    it.row = (int32_t)uniq[r];
+    it.nparts = (int32_t)k;
+    it.slot = k > 1u ? (int32_t)(pbase[r] + j) : -1;
+    it.pad[0] = it.pad[1] = 0;
+    items[ioff[r] + j] = it;
+  }
+  if (k > 1u) multi[atomicAdd(num_multi, 1u)] = ioff[r];
+  if (r == R - 1) *num_items = ioff[r] + k;
+}
+
+// One lane group per item: gathers the item's changed successors; an item
+// that is its row's whole run finishes the row, the others leave a partial
+// counter for k_pair_merge.
+template <int B, int FL>
+__global__ HB_EXPAND_ATTR void k_pair_expand(PassArgs A, const int32_t* vals, const PairItem* items,
+                                             const uint32_t* num_items, uint8_t* partial) {
+  constexpr int P = 1 << B;
+  constexpr int G = P / 16;
+  constexpr int W = 64 / G;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int gl = lane % G;
+  const int grp = lane / G;
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < STAT_SLOTS * STAT_K; i += blockDim.x) A.stats_next[i] = 0ull;
+  const int64_t wi = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t it = wi * W + grp;
+  Counts c{};
+  if (it < (int64_t)*num_items) {
+    const PairItem pi = items[it];
+    PassArgs L = A;
+    L.idx = vals;
+    const bool whole = pi.nparts == 1;
+    RowPre pre;
+    if (whole) pre = preload<B, FL>(A, pi.row, gl);
+    bool got = false;
+    const uint32_t g0 = c.gath;
+    const uint4 acc = gather<B>(L, pi.start, pi.start + pi.len, 1, gl, got, c);
+    if (gl == 0) c.arcs += c.gath - g0;
+    if (whole)
+      (void)finish_row<B, false, FL>(A, pi.row, acc, got, pre, bit_of(A.mod_prev, pi.row), gl, grp, c);
+    else
+      *reinterpret_cast<uint4*>(partial + (size_t)pi.slot * P + (size_t)gl * 16) = acc;
+  }
+  flush_counts<FL>(A, c, wi, lane);
+}
+
+// One wavefront per multi-item run: folds its partial counters into the row
+// and finishes it like any other row.
+template <int B, int FL>
+__global__ __launch_bounds__(256) void k_pair_merge(PassArgs A, const PairItem* items, const uint32_t* multi,
+                                                    const uint32_t* num_multi, const uint8_t* partial) {
+  constexpr int P = 1 << B;
+  constexpr int G = P / 16;
+  constexpr int W = 64 / G;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int gl = lane % G;
+  const int grp = lane / G;
+  const int64_t h = (int64_t)blockIdx.x * 4 + wave;
+  if (h >= (int64_t)*num_multi) return;
+  const PairItem pi = items[multi[h]];
+  RowPre pre;
+  if (grp == 0) pre = preload<B, FL>(A, pi.row, gl);
+  uint4 acc = zero4();
+  for (int j = grp; j < pi.nparts; j += W)
+    acc = bmax(acc, *reinterpret_cast<const uint4*>(partial + (size_t)(pi.slot + j) * P + (size_t)gl * 16));
+#pragma unroll
+  for (int o = G; o < 64; o <<= 1) acc = bmax(acc, shfl_xor4(acc, o));
+  Counts c{};
+  if (grp == 0) (void)finish_row<B, false, FL>(A, pi.row, acc, true, pre, bit_of(A.mod_prev, pi.row), gl, 0, c);
+  flush_counts<FL>(A, c, h, lane);
 }
 
 // --- end-of-pass bookkeeping of multi-graph contexts ------------------------
@@ -2028,6 +2241,89 @@ hipError_t launch_push(const uint64_t* mod_prev, int64_t n_words, int64_t n, con
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_push_apply, dim3(4096), dim3(256), 0, s, items, count, roff, ridx, act, epoch);
   return hipGetLastError();
+}
+
+size_t pair_tmp_bytes(int64_t cap, int end_bit) {
+  size_t a = 0, b = 0, c = 0;
+  const int N = (int)cap;
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, a, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                           (const int32_t*)nullptr, (int32_t*)nullptr, N, 0, end_bit);
+  (void)hipcub::DeviceRunLengthEncode::Encode(nullptr, b, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                              (uint32_t*)nullptr, (int32_t*)nullptr, N);
+  (void)hipcub::DeviceScan::ExclusiveSum(nullptr, c, (const uint32_t*)nullptr, (uint32_t*)nullptr, N);
+  return std::max(a, std::max(b, c));
+}
+
+hipError_t launch_pair_build(const PassArgs& a, const PairBufs& pb, int64_t total, uint2* items,
+                             unsigned long long* count, hipStream_t s) {
+  if (total <= 0 || total > pb.cap) return hipErrorInvalidValue;
+  const int N = (int)total;
+  size_t tb = pb.tmp_bytes;
+  hipError_t e = launch_fill_zero(count, sizeof(unsigned long long), s);
+  if (e == hipSuccess) e = launch_fill_zero(pb.npairs, sizeof(unsigned long long), s);
+  if (e == hipSuccess) e = launch_fill_zero(pb.num_multi, sizeof(uint32_t), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pair_items, dim3((unsigned)((a.n_blocks + 255) / 256)), dim3(256), 0, s, a.mod_prev,
+                     a.n_blocks, a.n, a.roff, items, pb.ppos, count, pb.npairs);
+  hipLaunchKernelGGL(k_pair_apply, dim3(4096), dim3(256), 0, s, items, pb.ppos, count, a.roff, a.ridx, pb.keys[0],
+                     pb.vals[0], pb.cap);
+  e = hipGetLastError();
+  if (e == hipSuccess)
+    e = hipcub::DeviceRadixSort::SortPairs(pb.tmp, tb, pb.keys[0], pb.keys[1], pb.vals[0], pb.vals[1], N, 0,
+                                           pb.end_bit, s);
+  tb = pb.tmp_bytes;
+  if (e == hipSuccess)
+    e = hipcub::DeviceRunLengthEncode::Encode(pb.tmp, tb, pb.keys[1], pb.uniq, pb.cnt, pb.num_runs, N, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_run_parts, dim3(grid_for(total, 256, 16384)), dim3(256), 0, s, pb.num_runs, total, pb.cnt,
+                     pb.ni, pb.mp);
+  e = hipGetLastError();
+  tb = pb.tmp_bytes;
+  if (e == hipSuccess) e = hipcub::DeviceScan::ExclusiveSum(pb.tmp, tb, pb.cnt, pb.rstart, N, s);
+  tb = pb.tmp_bytes;
+  if (e == hipSuccess) e = hipcub::DeviceScan::ExclusiveSum(pb.tmp, tb, pb.ni, pb.ioff, N, s);
+  tb = pb.tmp_bytes;
+  if (e == hipSuccess) e = hipcub::DeviceScan::ExclusiveSum(pb.tmp, tb, pb.mp, pb.pbase, N, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_run_items, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, pb.num_runs, pb.uniq,
+                     pb.cnt, pb.rstart, pb.ni, pb.ioff, pb.pbase, pb.items, pb.multi, pb.num_multi, pb.num_items);
+  return hipGetLastError();
+}
+
+template <int B, int FL>
+hipError_t pair_pass_b(const PassArgs& a, const PairBufs& pb, int64_t total, hipStream_t s, hipEvent_t ev_mid) {
+  constexpr int W = 64 / ((1 << B) / 16);
+  const int64_t items_up = total + total / RUN_CHUNK + 1;  // runs <= total, plus the extra items of long runs
+  hipLaunchKernelGGL((k_pair_expand<B, FL>), dim3((unsigned)((items_up + 4 * W - 1) / (4 * W))), dim3(256), 0, s,
+                     a, pb.vals[1], pb.items, pb.num_items, pb.partial);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && ev_mid) e = hipEventRecord(ev_mid, s);
+  if (e != hipSuccess) return e;
+  const int64_t multi_up = total / (RUN_CHUNK + 1) + 1;
+  hipLaunchKernelGGL((k_pair_merge<B, FL>), dim3((unsigned)((multi_up + 3) / 4)), dim3(256), 0, s, a, pb.items,
+                     pb.multi, pb.num_multi, pb.partial);
+  return hipGetLastError();
+}
+
+template <int FL>
+hipError_t pair_pass_fl(int log2m, const PassArgs& a, const PairBufs& pb, int64_t total, hipStream_t s,
+                        hipEvent_t ev_mid) {
+  switch (log2m) {
+    case 4: return pair_pass_b<4, FL>(a, pb, total, s, ev_mid);
+    case 5: return pair_pass_b<5, FL>(a, pb, total, s, ev_mid);
+    case 6: return pair_pass_b<6, FL>(a, pb, total, s, ev_mid);
+    case 7: return pair_pass_b<7, FL>(a, pb, total, s, ev_mid);
+    case 8: return pair_pass_b<8, FL>(a, pb, total, s, ev_mid);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_pair_pass(int log2m, const PassArgs& a, const PairBufs& pb, int64_t total, hipStream_t s,
+                            hipEvent_t ev_mid) {
+  if (total <= 0 || total > pb.cap || log2m > 8) return hipErrorInvalidValue;
+  if (a.seg_lanes > 0 && a.seg_lanes < (1 << log2m) / 16) return pair_pass_fl<FL_ENS>(log2m, a, pb, total, s, ev_mid);
+  if (a.D) return pair_pass_fl<FL_DISC>(log2m, a, pb, total, s, ev_mid);
+  return pair_pass_fl<FL_PLAIN>(log2m, a, pb, total, s, ev_mid);
 }
 
 hipError_t launch_init_arena(int log2m, int64_t v0, int64_t v1, const int32_t* blk_graph,

@@ -71,6 +71,7 @@ def test_ensemble_equals_oracle_runs(name, b, K):
 
 
 @pytest.mark.parametrize("opt", [dict(frontier=0), dict(qdense=1), dict(push=0), dict(slice=1),
+                                 dict(dense_pct=101, sparse_pct=101), dict(dense_pct=101, sparse_pct=101, pairs=0),
                                  dict(light_max=4, heavy_min=40, chunk=16), dict(dense_pct=101)])
 def test_ensemble_modes_and_row_classes(opt):
     off, idx = gg.rmat(9, 12, seed=23, transpose=True)

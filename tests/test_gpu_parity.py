@@ -77,6 +77,8 @@ def test_every_pass_matches():
     dict(dense_pct=101, sparse_pct=101),          # every pass after the first is sparse
     dict(dense_pct=101),                          # edge passes, then sparse ones
     dict(dense_pct=101, push=0),                  # edge passes only (no reverse CSR)
+    dict(dense_pct=101, sparse_pct=101, pairs=0),  # sparse passes from activation stamps
+    dict(dense_pct=101, sparse_pct=101, pairs=0, light_max=2, heavy_min=6, chunk=3),
     dict(dense_pct=101, sparse_pct=0, slice=1, light_max=2, heavy_min=6, chunk=3),
     dict(dense_pct=101, sparse_pct=101, light_max=2, heavy_min=6, chunk=3),
     dict(slice=1),                                # default planning with slice masks
@@ -247,6 +249,24 @@ def test_first_pass_reads_counters_when_weighted():
     ref = oracle.run_ext(off.astype(np.int64), idx, 6, 5, max_passes=1, weights=w)
     assert np.array_equal(regs, ref["regs"])
     assert np.array_equal(plain, oracle.run(off.astype(np.int64), idx, 6, 5, max_passes=1)["regs"])
+
+
+@pytest.mark.parametrize("b", [4, 7, 8])
+def test_sparse_pair_lists_long_runs(b):
+    """Sparse passes from pair lists: the hub's 3000 successors all change in
+    pass 0, so in pass 1 its run of 3000 pairs is cut into items whose
+    partial counters are merged.  Equal to the oracle, and to the
+    activation-stamp path, pass by pass."""
+    k = 3000
+    edges = [(0, i) for i in range(1, k + 1)] + [(i, k + i) for i in range(1, k + 1)]
+    off, idx = gg.from_edges(2 * k + 1, edges)
+    for opts in (dict(dense_pct=101, sparse_pct=101), dict(dense_pct=101, sparse_pct=101, pairs=0)):
+        got, _ = check(off, idx, b, 77, f"hub{k}/b{b}/{opts}", **opts)
+        modes = [p["mode"] for p in got["pass_stats"]]
+        assert modes[0] == 0 and all(m == 2 for m in modes[1:]), modes
+        if opts.get("pairs", 1):
+            # pair passes scan only arcs into changed counters
+            assert all(p["arcs_scanned"] == p["counters_gathered"] for p in got["pass_stats"][1:])
 
 
 def test_validation_rejects_bad_indices():
