@@ -87,14 +87,14 @@ def read_traffic(kname, workload):
     return int(rec["hbm_bytes_per_launch"])
 
 
-def codes_pass(ps):
-    """A first pass that recomputed singleton counters from node hashes
-    instead of reading them."""
-    return ps["mode"] == 0 and ps["slices_gathered"] == 0 and ps["counters_gathered"] > 0
-
-
 def kernel_of(ps, b):
-    return ("k_expand_codes<{b}>" if codes_pass(ps) else KERNEL_OF_MODE[ps["mode"]]).format(b=b)
+    """Expand kernel of a pass: path 1 is the first pass from node hashes,
+    path 2 a sparse pass from pair lists."""
+    if ps["path"] == 1:
+        return f"k_expand_codes<{b}>"
+    if ps["path"] == 2:
+        return f"k_pair_expand<{b}, 0>"
+    return KERNEL_OF_MODE[ps["mode"]].format(b=b)
 
 
 def pass_bytes(ps, listed, p):
@@ -108,10 +108,14 @@ def pass_bytes(ps, listed, p):
     counter slice: 16 B.  Every written counter: p B.  Every changed row:
     estimate, accumulators and slice mask written back (26 B).  A first pass
     from node hashes reads no counter: its rows read only the estimate and
-    accumulators, its arcs only the successor id."""
+    accumulators, its arcs only the successor id.  A pair-list pass reads per
+    row (run) a 32 B work item and no list entry, per pair a 4 B successor id."""
     per_row = 28 + (4 if ps["mode"] == 2 else 0)
-    if codes_pass(ps):
+    if ps["path"] == 1:
         return (per_row * listed + 24 * ps["rows_loaded"] + 4 * ps["arcs_scanned"]
+                + p * ps["rows_written"] + 26 * ps["rows_changed"])
+    if ps["path"] == 2:
+        return ((32 + p + 24) * ps["rows_loaded"] + 4 * ps["arcs_scanned"] + 16 * ps["slices_gathered"]
                 + p * ps["rows_written"] + 26 * ps["rows_changed"])
     per_arc = 4
     return (per_row * listed + (p + 24) * ps["rows_loaded"] + per_arc * ps["arcs_scanned"]

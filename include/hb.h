@@ -203,6 +203,10 @@ hb_status hb_stats(hb_ctx* c, hb_stats_t* s);
  *                      next pass gathers with edge skipping; needs push = 1)
  *   mode               0 first pass, 1 dense, 2 sparse, 3 edge with slice
  *                      masks, 4 edge
+ *   path               0 counters gathered over the arcs, 1 first pass with
+ *                      successor counters recomputed from node hashes, 2
+ *                      sparse pass from pair lists (push_ms then includes
+ *                      building and sorting them)
  *   push_ms / expand_ms / merge_ms: kernel times from HIP events (timing = 1). */
 typedef struct {
   int64_t arcs_scanned;
@@ -217,6 +221,7 @@ typedef struct {
   double push_ms;
   double expand_ms;
   double merge_ms;
+  int32_t path;
 } hb_pass_info;
 
 hb_status hb_pass_stats(hb_ctx* c, int32_t pass, hb_pass_info* info);

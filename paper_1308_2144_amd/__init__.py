@@ -68,7 +68,7 @@ class hb_pass_info(ctypes.Structure):
                 ("slices_changed", ctypes.c_int64), ("arcs_to_changed", ctypes.c_int64),
                 ("mode", ctypes.c_int32),
                 ("push_ms", ctypes.c_double), ("expand_ms", ctypes.c_double),
-                ("merge_ms", ctypes.c_double)]
+                ("merge_ms", ctypes.c_double), ("path", ctypes.c_int32)]
 
 
 class hb_graph_info(ctypes.Structure):

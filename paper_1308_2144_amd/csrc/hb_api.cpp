@@ -837,6 +837,7 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
   info.slices_changed = (int64_t)sum[6];
   info.arcs_to_changed = c->roff ? (int64_t)sum[7] : -1;
   info.mode = mode;
+  info.path = use_pairs ? 2 : (a.singletons && c->p <= 256 && !a.D ? 1 : 0);
   if (timing) {
     float ms0 = 0.f, ms1 = 0.f, ms2 = 0.f;
     (void)hipEventElapsedTime(&ms0, c->ev[0], c->ev[1]);

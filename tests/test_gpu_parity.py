@@ -222,7 +222,7 @@ def test_first_pass_from_hashes(b, opts):
                              ("isolated70", gg.empty(70))]:
         got, _ = check(off, idx, b, 900 + b, f"{name}/b{b}/{opts}", max_passes=1, **opts)
         p0 = got["pass_stats"][0]
-        assert p0["mode"] == 0 and p0["slices_gathered"] == 0
+        assert p0["mode"] == 0 and p0["path"] == 1 and p0["slices_gathered"] == 0
         assert p0["counters_gathered"] == p0["arcs_scanned"] == len(idx)
 
 
@@ -239,7 +239,7 @@ def test_first_pass_reads_counters_when_weighted():
         g.set_weights(w)
         g.reset(5)
         g.run(1)
-        assert g.pass_stats(0)["slices_gathered"] == 4 * len(idx)
+        assert g.pass_stats(0)["slices_gathered"] == 4 * len(idx) and g.pass_stats(0)["path"] == 0
         regs = g.registers()
         g.set_weights(None)
         g.reset(5)
@@ -264,9 +264,13 @@ def test_sparse_pair_lists_long_runs(b):
         got, _ = check(off, idx, b, 77, f"hub{k}/b{b}/{opts}", **opts)
         modes = [p["mode"] for p in got["pass_stats"]]
         assert modes[0] == 0 and all(m == 2 for m in modes[1:]), modes
+        paths = [p["path"] for p in got["pass_stats"][1:]]
         if opts.get("pairs", 1):
             # pair passes scan only arcs into changed counters
             assert all(p["arcs_scanned"] == p["counters_gathered"] for p in got["pass_stats"][1:])
+            assert paths == [2] * len(paths)
+        else:
+            assert paths == [0] * len(paths)
 
 
 def test_validation_rejects_bad_indices():
