@@ -287,6 +287,7 @@ hb_status do_reset(hb_ctx* c, uint64_t seed) {
     HB_HIP(hipMemcpyAsync(c->ctl, c->ctl_host, sizeof(hb::PassCtl), hipMemcpyHostToDevice, c->stream));
     HB_HIP(hb::launch_init_arena(c->b, 0, c->n, c->blk_graph, c->graphs, c->cnt[0], c->cnt[1], c->S, c->H, c->E,
                                  c->lc, c->alpha_pp, c->stream));
+    c->singletons = c->p <= 256;  // the first pass recomputes counters from node hashes
     HB_HIP(hipStreamSynchronize(c->stream));  // ctl_host is reused by the next readback
     return HB_OK;
   }
@@ -547,6 +548,7 @@ hb::PassArgs device_args(hb_ctx* c) {
   a.n_items = c->n_items;
   a.n_hrows = c->n_hrows;
   a.qdense = c->opt.qdense ? 1 : 0;
+  a.singletons = c->singletons ? 1 : 0;  // device-driven: used only when the pass is a first pass
   a.blk_graph = c->blk_graph;
   a.graphs = c->graphs;
   a.ctl = c->ctl;

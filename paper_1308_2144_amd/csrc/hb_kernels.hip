@@ -826,6 +826,7 @@ template <int B, bool Q>
 __global__ HB_PERSIST_ATTR void k_expand_p(PassArgs A0) {
   const PassArgs A = resolve(A0);
   if (queued_mode(A) != Q) return;
+  if (!Q && A.mode == MODE_FIRST && A0.singletons) return;  // k_expand_codes_p runs it
   __shared__ QEnt qbuf[Q ? 4 : 1][Q ? QCAP : 1];
   __shared__ int64_t item;
   const int64_t total = pass_items(A);
@@ -932,8 +933,26 @@ __device__ __forceinline__ uint4 take_slice(uint32_t* regs, int gl) {
 // discarded (light rows have only a few arcs per lane).
 constexpr int UC = 4;
 
+// Hash key of a row's graph: arena base and hash seed (multi-graph contexts
+// number nodes within their graph; every arc stays inside it, so a row's
+// successors share the row's key).
+struct GraphKey {
+  int64_t base;
+  uint64_t seed;
+};
+
+template <bool MG>
+__device__ __forceinline__ GraphKey key_of(const PassArgs& A, int64_t row) {
+  if constexpr (MG) {
+    const GraphDev& gd = A.graphs[A.blk_graph[row >> 6]];
+    return GraphKey{gd.node_base, gd.seed};
+  }
+  return GraphKey{0, A.seed};
+}
+
 template <int B>
-__device__ __forceinline__ void fold_codes(const PassArgs& A, uint32_t* regs, int64_t k, int64_t e, int64_t st) {
+__device__ __forceinline__ void fold_codes(const PassArgs& A, uint32_t* regs, int64_t k, int64_t e, int64_t st,
+                                           GraphKey key) {
   for (; k < e; k += st * UC) {
     int32_t w[UC];
 #pragma unroll
@@ -944,7 +963,7 @@ __device__ __forceinline__ void fold_codes(const PassArgs& A, uint32_t* regs, in
 #pragma unroll
     for (int u = 0; u < UC; ++u)
       if (w[u] >= 0) {
-        const uint32_t x = singleton_code<B>((uint64_t)w[u], A.seed);
+        const uint32_t x = singleton_code<B>((uint64_t)(w[u] - key.base), key.seed);
         __hip_atomic_fetch_max(regs + (x >> 8), x & 0xffu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
   }
@@ -952,9 +971,9 @@ __device__ __forceinline__ void fold_codes(const PassArgs& A, uint32_t* regs, in
 
 // As preload, with the own counter taken from its code.
 template <int B>
-__device__ __forceinline__ RowPre preload_code(const PassArgs& A, int64_t row, int gl) {
+__device__ __forceinline__ RowPre preload_code(const PassArgs& A, int64_t row, int gl, GraphKey key) {
   RowPre r;
-  r.own = code_slice(singleton_code<B>((uint64_t)row, A.seed), gl);
+  r.own = code_slice(singleton_code<B>((uint64_t)(row - key.base), key.seed), gl);
   r.e = r.s = r.h = r.dd = 0.0;
   if (gl == 0) {
     r.e = ld_stream(A.E + row);
@@ -964,8 +983,10 @@ __device__ __forceinline__ RowPre preload_code(const PassArgs& A, int64_t row, i
   return r;
 }
 
-// 64 light-row list entries per wavefront, W rows at a time (one per lane group).
-template <int B>
+// 64 light-row list entries per wavefront, W rows at a time (one per lane
+// group).  Multi-graph passes combine a round's change bits into one atomic
+// per bitmap word, as light_wave does.
+template <int B, bool MG>
 __device__ __forceinline__ void light_codes(const PassArgs& A, uint32_t* lds, int64_t lw, int lane) {
   constexpr int P = 1 << B;
   constexpr int G = P / 16;
@@ -974,12 +995,15 @@ __device__ __forceinline__ void light_codes(const PassArgs& A, uint32_t* lds, in
   const int grp = lane / G;
   const int64_t i = lw * 64 + lane;
   int64_t row = 0, s = 0, deg = 0;
+  bool need = false;
   if (i < A.n_light) {
     row = A.light[i];
     s = A.off[row];
     deg = A.off[row + 1] - s;
+    bool own_mod;
+    row_flags<MG>(A, row, own_mod, need);
   }
-  const uint64_t live = __ballot(i < A.n_light);
+  const uint64_t live = __ballot(need);
   uint32_t* regs = lds + grp * P;
   Counts c{};
   for (int r = 0; r < G; ++r) {
@@ -990,44 +1014,52 @@ __device__ __forceinline__ void light_codes(const PassArgs& A, uint32_t* lds, in
     const bool on = ((live >> rl) & 1ull) != 0ull;
     RowPre pre;
     if (on) {
-      pre = preload_code<B>(A, rrow, gl);
-      fold_codes<B>(A, regs, rs + gl, rs + rd, G);
+      const GraphKey key = key_of<MG>(A, rrow);
+      pre = preload_code<B>(A, rrow, gl, key);
+      fold_codes<B>(A, regs, rs + gl, rs + rd, G, key);
     }
     wave_sync();
+    bool chg = false;
     if (on) {
       const uint4 acc = take_slice(regs, gl);
       if (gl == 0) {
         c.gath += (uint32_t)rd;
         c.arcs += (uint32_t)rd;
       }
-      (void)finish_row<B, false>(A, rrow, acc, rd > 0, pre, false, gl, grp, c);
+      chg = finish_row<B, MG, FL_PLAIN, MG>(A, rrow, acc, rd > 0, pre, false, gl, grp, c);
     }
+    if constexpr (MG) set_change_bits(A.mod_cur, rrow, chg && gl == 0, lane);
     wave_sync();
   }
   flush_counts(A, c, lw, lane);
 }
 
 // One medium row per wavefront: all 64 lanes fold its arcs.
-template <int B>
+template <int B, bool MG>
 __device__ __forceinline__ void medium_codes(const PassArgs& A, uint32_t* lds, int64_t mi, int lane) {
   constexpr int G = (1 << B) / 16;
   const int gl = lane % G;
   const int grp = lane / G;
   const int64_t row = A.medium[mi];
-  const int64_t s = A.off[row];
-  const int64_t deg = A.off[row + 1] - s;
+  bool own_mod, need;
+  row_flags<MG>(A, row, own_mod, need);
   Counts c{};
-  RowPre pre;
-  if (grp == 0) pre = preload_code<B>(A, row, gl);
-  fold_codes<B>(A, lds, s + lane, s + deg, 64);
-  wave_sync();
-  if (grp == 0) {
-    const uint4 acc = take_slice(lds, gl);
-    if (gl == 0) {
-      c.gath += (uint32_t)deg;
-      c.arcs += (uint32_t)deg;
+  if (need) {  // uniform over the wavefront
+    const int64_t s = A.off[row];
+    const int64_t deg = A.off[row + 1] - s;
+    const GraphKey key = key_of<MG>(A, row);
+    RowPre pre;
+    if (grp == 0) pre = preload_code<B>(A, row, gl, key);
+    fold_codes<B>(A, lds, s + lane, s + deg, 64, key);
+    wave_sync();
+    if (grp == 0) {
+      const uint4 acc = take_slice(lds, gl);
+      if (gl == 0) {
+        c.gath += (uint32_t)deg;
+        c.arcs += (uint32_t)deg;
+      }
+      (void)finish_row<B, MG>(A, row, acc, deg > 0, pre, false, gl, 0, c);
     }
-    (void)finish_row<B, false>(A, row, acc, deg > 0, pre, false, gl, 0, c);
   }
   flush_counts(A, c, mi, lane);
 }
@@ -1035,14 +1067,17 @@ __device__ __forceinline__ void medium_codes(const PassArgs& A, uint32_t* lds, i
 // One chunk of a heavy row per workgroup: its four wavefronts fold into one
 // register array; the chunk's maximum goes to its partial counter (merged
 // with the row's own counter by k_merge).
-template <int B>
+template <int B, bool MG>
 __device__ __forceinline__ void heavy_codes(const PassArgs& A, uint32_t* lds, int64_t item, int lane, int wave) {
   constexpr int P = 1 << B;
   constexpr int G = P / 16;
   const int gl = lane % G;
   const int grp = lane / G;
   const HeavyItem it = A.items[item];
-  fold_codes<B>(A, lds, it.e0 + wave * 64 + lane, it.e1, 256);
+  bool own_mod, need;
+  row_flags<MG>(A, it.row, own_mod, need);
+  if (!need) return;  // uniform over the workgroup; the merge kernel skips the row too
+  fold_codes<B>(A, lds, it.e0 + wave * 64 + lane, it.e1, 256, key_of<MG>(A, it.row));
   Counts c{};
   if (lane == 0 && wave == 0) {
     c.gath += (uint32_t)(it.e1 - it.e0);
@@ -1054,32 +1089,57 @@ __device__ __forceinline__ void heavy_codes(const PassArgs& A, uint32_t* lds, in
     *reinterpret_cast<uint4*>(A.partial + (size_t)item * P + (size_t)gl * 16) = take_slice(lds, gl);
 }
 
-// Work items as in expand_item: [heavy chunks][medium rows][light rows].
-template <int B>
-__global__ HB_EXPAND_ATTR void k_expand_codes(PassArgs A) {
-  __shared__ uint32_t regs[4][CODE_WORDS];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  uint4* z = reinterpret_cast<uint4*>(&regs[0][0]);
-  for (int i = threadIdx.x; i < CODE_WORDS; i += 256) z[i] = zero4();  // 4 waves x CODE_WORDS words
-  __syncthreads();
-  int64_t b = blockIdx.x;
+// One work item, numbered as in expand_item: [heavy chunks][medium rows][light rows].
+template <int B, bool MG>
+__device__ __forceinline__ void codes_item(const PassArgs& A, uint32_t (*regs)[CODE_WORDS], int64_t b, int lane,
+                                           int wave) {
   if (b == 0)
     for (int i = threadIdx.x; i < STAT_SLOTS * STAT_K; i += blockDim.x) A.stats_next[i] = 0ull;
   if (b < A.n_items) {
-    heavy_codes<B>(A, regs[0], b, lane, wave);
+    heavy_codes<B, MG>(A, regs[0], b, lane, wave);
     return;
   }
   b -= A.n_items;
   const int64_t med_wgs = (A.n_medium + 3) / 4;
   if (b < med_wgs) {
     const int64_t mi = b * 4 + wave;
-    if (mi < A.n_medium) medium_codes<B>(A, regs[wave], mi, lane);
+    if (mi < A.n_medium) medium_codes<B, MG>(A, regs[wave], mi, lane);
     return;
   }
   b -= med_wgs;
   const int64_t lw = b * 4 + wave;
-  if (lw * 64 < A.n_light) light_codes<B>(A, regs[wave], lw, lane);
+  if (lw * 64 < A.n_light) light_codes<B, MG>(A, regs[wave], lw, lane);
+}
+
+template <int B>
+__global__ HB_EXPAND_ATTR void k_expand_codes(PassArgs A) {
+  __shared__ uint32_t regs[4][CODE_WORDS];
+  uint4* z = reinterpret_cast<uint4*>(&regs[0][0]);
+  for (int i = threadIdx.x; i < CODE_WORDS; i += 256) z[i] = zero4();  // 4 waves x CODE_WORDS words
+  __syncthreads();
+  codes_item<B, false>(A, regs, blockIdx.x, threadIdx.x & 63, threadIdx.x >> 6);
+}
+
+// Persistent form for the first device-driven pass of a batched context (a
+// no-op in any other pass); items from the pass's work cursor.  The register
+// arrays are left clear by every item, so they are zeroed once.
+template <int B>
+__global__ HB_PERSIST_ATTR void k_expand_codes_p(PassArgs A0) {
+  const PassArgs A = resolve(A0);
+  if (A.mode != MODE_FIRST || !A0.singletons) return;
+  __shared__ uint32_t regs[4][CODE_WORDS];
+  __shared__ int64_t item;
+  uint4* z = reinterpret_cast<uint4*>(&regs[0][0]);
+  for (int i = threadIdx.x; i < CODE_WORDS; i += 256) z[i] = zero4();
+  const int64_t total = pass_items(A);
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) item = (int64_t)atomicAdd(&A0.ctl->work, 1ull);
+    __syncthreads();
+    const int64_t b = item;
+    if (b >= total) break;
+    codes_item<B, true>(A, regs, b, threadIdx.x & 63, threadIdx.x >> 6);
+  }
 }
 
 // Counters wider than 256 bytes: one workgroup per 64-row block, rows in
@@ -2347,6 +2407,7 @@ hipError_t device_pass_b(const PassArgs& a, int persist_wgs, uint2* push_items, 
                        push_count);
     hipLaunchKernelGGL(k_push_apply_d, dim3(4096), dim3(256), 0, s, a, push_items, push_count);
   }
+  if (a.singletons) hipLaunchKernelGGL((k_expand_codes_p<B>), dim3(persist_wgs), dim3(256), 0, s, a);
   hipLaunchKernelGGL((k_expand_p<B, false>), dim3(persist_wgs), dim3(256), 0, s, a);
   hipLaunchKernelGGL((k_expand_p<B, true>), dim3(persist_wgs), dim3(256), 0, s, a);
   if (a.n_hrows > 0) hipLaunchKernelGGL((k_merge<B, true>), dim3((unsigned)((a.n_hrows + 3) / 4)), dim3(256), 0, s, a);
