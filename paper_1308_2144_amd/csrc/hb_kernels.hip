@@ -785,6 +785,42 @@ __device__ __forceinline__ int64_t pass_items(const PassArgs& A) {
   return A.n_items + (A.n_medium + 3) / 4 + (A.n_light + 255) / 256;
 }
 
+// Tickets of the persistent kernels' work cursor: one per heavy chunk and
+// per medium workgroup item, one per K light-row items.  A ticket is one
+// atomic on a single address: in queued (edge and sparse) passes, where most
+// rows have little or nothing to do, one item per ticket makes that atomic
+// the bottleneck, so light items are taken K = 8 at a time.  Direct passes
+// take one item per ticket: with the whole GPU on a narrow window of
+// consecutive rows, the counters of nearby successors stay in L2 (measured:
+// K = 8 slows the dense passes of the 4096-graph batch by 20 %).
+
+struct Tickets {
+  int64_t single;  // heavy + medium items
+  int64_t total;   // items
+  int64_t count;   // tickets
+};
+
+template <int K>
+__device__ __forceinline__ Tickets pass_tickets(const PassArgs& A) {
+  Tickets t;
+  t.single = A.n_items + (A.n_medium + 3) / 4;
+  t.total = pass_items(A);
+  t.count = t.single + (t.total - t.single + K - 1) / K;
+  return t;
+}
+
+// Items [*b0, *b1) of ticket k.
+template <int K>
+__device__ __forceinline__ void ticket_items(const Tickets& t, int64_t k, int64_t* b0, int64_t* b1) {
+  if (k < t.single) {
+    *b0 = k;
+    *b1 = k + 1;
+  } else {
+    *b0 = t.single + (k - t.single) * K;
+    *b1 = *b0 + K < t.total ? *b0 + K : t.total;
+  }
+}
+
 __device__ __forceinline__ bool queued_mode(const PassArgs& A) {
   return !(A.mode == MODE_FIRST || A.mode == MODE_DENSE) || A.qdense;
 }
@@ -828,15 +864,18 @@ __global__ HB_PERSIST_ATTR void k_expand_p(PassArgs A0) {
   if (queued_mode(A) != Q) return;
   if (!Q && A.mode == MODE_FIRST && A0.singletons) return;  // k_expand_codes_p runs it
   __shared__ QEnt qbuf[Q ? 4 : 1][Q ? QCAP : 1];
-  __shared__ int64_t item;
-  const int64_t total = pass_items(A);
+  __shared__ int64_t ticket;
+  constexpr int K = Q ? 8 : 1;
+  const Tickets tk = pass_tickets<K>(A);
   for (;;) {
-    if (threadIdx.x == 0) item = (int64_t)atomicAdd(&A0.ctl->work, 1ull);
+    if (threadIdx.x == 0) ticket = (int64_t)atomicAdd(&A0.ctl->work, 1ull);
     __syncthreads();
-    const int64_t b = item;
+    const int64_t k = ticket;
     __syncthreads();
-    if (b >= total) break;
-    expand_item<B, Q, true>(A, Q ? qbuf[threadIdx.x >> 6] : nullptr, b);
+    if (k >= tk.count) break;
+    int64_t b0, b1;
+    ticket_items<K>(tk, k, &b0, &b1);
+    for (int64_t b = b0; b < b1; ++b) expand_item<B, Q, true>(A, Q ? qbuf[threadIdx.x >> 6] : nullptr, b);
   }
 }
 
@@ -1128,17 +1167,19 @@ __global__ HB_PERSIST_ATTR void k_expand_codes_p(PassArgs A0) {
   const PassArgs A = resolve(A0);
   if (A.mode != MODE_FIRST || !A0.singletons) return;
   __shared__ uint32_t regs[4][CODE_WORDS];
-  __shared__ int64_t item;
+  __shared__ int64_t ticket;
   uint4* z = reinterpret_cast<uint4*>(&regs[0][0]);
   for (int i = threadIdx.x; i < CODE_WORDS; i += 256) z[i] = zero4();
-  const int64_t total = pass_items(A);
+  const Tickets tk = pass_tickets<1>(A);
   for (;;) {
     __syncthreads();
-    if (threadIdx.x == 0) item = (int64_t)atomicAdd(&A0.ctl->work, 1ull);
+    if (threadIdx.x == 0) ticket = (int64_t)atomicAdd(&A0.ctl->work, 1ull);
     __syncthreads();
-    const int64_t b = item;
-    if (b >= total) break;
-    codes_item<B, true>(A, regs, b, threadIdx.x & 63, threadIdx.x >> 6);
+    const int64_t k = ticket;
+    if (k >= tk.count) break;
+    int64_t b0, b1;
+    ticket_items<1>(tk, k, &b0, &b1);
+    for (int64_t b = b0; b < b1; ++b) codes_item<B, true>(A, regs, b, threadIdx.x & 63, threadIdx.x >> 6);
   }
 }
 
