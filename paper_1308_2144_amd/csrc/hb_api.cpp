@@ -70,6 +70,7 @@ void release(hb_ctx* c) {
   (void)hipFree(c->bad);
   (void)hipFree(c->graphs);
   (void)hipFree(c->blk_graph);
+  (void)hipFree(c->chunk_graph);
   (void)hipFree(c->ctl);
   (void)hipFree(c->arena_tmp);
   (void)hipFree(c->seeds_dev);
@@ -284,6 +285,8 @@ hb_status do_reset(hb_ctx* c, uint64_t seed) {
     k.parity = 0;
     k.n_done = 0;
     k.work = 0;
+    k.rows_done = 0;
+    k.batch = 1;
     HB_HIP(hipMemcpyAsync(c->ctl, c->ctl_host, sizeof(hb::PassCtl), hipMemcpyHostToDevice, c->stream));
     HB_HIP(hb::launch_init_arena(c->b, 0, c->n, c->blk_graph, c->graphs, c->cnt[0], c->cnt[1], c->S, c->H, c->E,
                                  c->lc, c->alpha_pp, c->stream));
@@ -493,6 +496,10 @@ hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, co
     if (!blk_graph->empty())
       HB_HIP(hipMemcpyAsync(c->blk_graph, blk_graph->data(), sizeof(int32_t) * blk_graph->size(),
                             hipMemcpyHostToDevice, c->stream));
+    if (c->n_light > 0) {
+      HB_HIP(dmalloc(&c->chunk_graph, (size_t)((c->n_light + 63) / 64)));
+      HB_HIP(hb::launch_chunk_graph(c->light, c->n_light, c->blk_graph, c->chunk_graph, c->stream));
+    }
     HB_HIP(dmalloc(&c->ctl, 1));
     HB_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->ctl_host), sizeof(hb::PassCtl), hipHostMallocDefault));
     std::memset(c->ctl_host, 0, sizeof(hb::PassCtl));
@@ -550,6 +557,7 @@ hb::PassArgs device_args(hb_ctx* c) {
   a.qdense = c->opt.qdense ? 1 : 0;
   a.singletons = c->singletons ? 1 : 0;  // device-driven: used only when the pass is a first pass
   a.blk_graph = c->blk_graph;
+  a.chunk_graph = c->chunk_graph;
   a.graphs = c->graphs;
   a.ctl = c->ctl;
   a.cntb[0] = c->cnt[0];

@@ -128,6 +128,7 @@ struct hb_ctx {
   uint2* push_items = nullptr;
   unsigned long long* push_count = nullptr;
   hb::PairBufs pb;              // pair lists of sparse passes (pb.cap = 0: none)
+  int32_t* chunk_graph = nullptr;  // batched contexts: graph of each 64-entry light-list chunk
   unsigned long long* npairs_host = nullptr;  // pinned: pairs the last pair pass emitted
   uint8_t* partial = nullptr;
   unsigned long long* stats = nullptr;       // 2 halves of STAT_SLOTS * STAT_K

@@ -70,7 +70,7 @@ struct PassCtl {
   int32_t mode;                // PassMode of the pass about to run
   int32_t parity;              // counter buffer holding the current counters
   int32_t n_done;              // graphs converged so far
-  unsigned long long work;     // persistent work-queue cursor
+  unsigned long long work;     // persistent work-queue cursor (tickets)
   // planning inputs (set by the host)
   int64_t listed_rows;         // non-empty rows of the resident graphs
   int64_t arcs;                // arcs of the resident graphs
@@ -80,6 +80,11 @@ struct PassCtl {
   // changed rows and their in-arcs in the last pass, plus those of graphs
   // admitted since (every row of an admitted graph counts as changed)
   unsigned long long chg, pairs;
+  // batched contexts: rows of the graphs converged so far (batch = 1 marks
+  // such a context; served engines leave both 0)
+  unsigned long long rows_done;
+  int32_t batch;
+  int32_t pad2;
 };
 
 // Everything one pass needs.  `cur` holds counters of radius t, `nxt`
@@ -137,6 +142,10 @@ struct PassArgs {
   // mod_prev/mod_cur, mode, epoch and the stats halves are taken from ctl
   // (buffers cntb[], modb[], stats_base).
   const int32_t* blk_graph;
+  // Batched contexts (nullable): graph of every 64-entry chunk of the light
+  // list if all its rows belong to one graph, else -1 (lets a wavefront skip
+  // a converged graph's chunk with one lookup).
+  const int32_t* chunk_graph;
   GraphDev* graphs;
   PassCtl* ctl;
   uint8_t* cntb[2];
@@ -196,6 +205,9 @@ hipError_t launch_rebase_csr(const void* off_l, int bits, int64_t n, int64_t m, 
 hipError_t launch_admit(PassCtl* ctl, GraphDev* graphs, int32_t slot, const GraphDev& val, int64_t m,
                         int32_t* blk_graph, uint64_t* mod0, uint64_t* mod1, int64_t b0, int64_t b1, hipStream_t s);
 hipError_t launch_set_plan(PassCtl* ctl, int64_t listed_rows, int64_t arcs, hipStream_t s);
+// chunk_graph[j] for the 64-entry chunks j of a light list (see PassArgs).
+hipError_t launch_chunk_graph(const int32_t* light, int64_t n_light, const int32_t* blk_graph, int32_t* chunk_graph,
+                              hipStream_t s);
 hipError_t launch_set_slot(GraphDev* graphs, int32_t slot, const GraphDev& val, hipStream_t s);
 hipError_t launch_pack_u8(const uint8_t* src, uint8_t* dst, int64_t n_arena, int p, const int32_t* blk_graph,
                           const GraphDev* graphs, hipStream_t s);

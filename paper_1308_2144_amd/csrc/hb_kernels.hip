@@ -630,6 +630,12 @@ __device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, int64_t 
   constexpr int W = 64 / G;
   const int gl = lane % G;
   const int grp = lane / G;
+  if constexpr (MG) {
+    if (A.chunk_graph) {  // a chunk of one converged graph has nothing to do
+      const int32_t g = A.chunk_graph[lw];
+      if (g >= 0 && A.graphs[g].done) return;
+    }
+  }
   const int64_t i = lw * 64 + lane;
   int64_t row = 0, s = 0, deg = 0;
   bool own_mod = false, need = false;
@@ -787,12 +793,19 @@ __device__ __forceinline__ int64_t pass_items(const PassArgs& A) {
 
 // Tickets of the persistent kernels' work cursor: one per heavy chunk and
 // per medium workgroup item, one per K light-row items.  A ticket is one
-// atomic on a single address: in queued (edge and sparse) passes, where most
-// rows have little or nothing to do, one item per ticket makes that atomic
-// the bottleneck, so light items are taken K = 8 at a time.  Direct passes
+// atomic on a single address: where most rows have little or nothing to do
+// (queued passes, and direct passes of a batch once a third of its rows
+// belong to converged graphs) one item per ticket makes that atomic the
+// bottleneck, so light items are taken K = 8 at a time.  Other direct passes
 // take one item per ticket: with the whole GPU on a narrow window of
-// consecutive rows, the counters of nearby successors stay in L2 (measured:
-// K = 8 slows the dense passes of the 4096-graph batch by 20 %).
+// consecutive rows the counters of nearby successors stay in L2 (measured on
+// the 4096-graph batch: K = 8 makes its all-active dense passes 20 % slower,
+// K = 1 its first half-converged pass 45 % slower).
+__device__ __forceinline__ int ticket_batch(const PassArgs& A0, bool queued) {
+  if (queued) return 8;
+  const PassCtl* c = A0.ctl;
+  return c->batch && 3ull * c->rows_done > (unsigned long long)A0.n ? 8 : 1;
+}
 
 struct Tickets {
   int64_t single;  // heavy + medium items
@@ -800,8 +813,9 @@ struct Tickets {
   int64_t count;   // tickets
 };
 
-template <int K>
-__device__ __forceinline__ Tickets pass_tickets(const PassArgs& A) {
+__device__ __forceinline__ int64_t next_ticket(PassCtl* ctl) { return (int64_t)atomicAdd(&ctl->work, 1ull); }
+
+__device__ __forceinline__ Tickets pass_tickets(const PassArgs& A, int K) {
   Tickets t;
   t.single = A.n_items + (A.n_medium + 3) / 4;
   t.total = pass_items(A);
@@ -810,8 +824,7 @@ __device__ __forceinline__ Tickets pass_tickets(const PassArgs& A) {
 }
 
 // Items [*b0, *b1) of ticket k.
-template <int K>
-__device__ __forceinline__ void ticket_items(const Tickets& t, int64_t k, int64_t* b0, int64_t* b1) {
+__device__ __forceinline__ void ticket_items(const Tickets& t, int K, int64_t k, int64_t* b0, int64_t* b1) {
   if (k < t.single) {
     *b0 = k;
     *b1 = k + 1;
@@ -865,16 +878,16 @@ __global__ HB_PERSIST_ATTR void k_expand_p(PassArgs A0) {
   if (!Q && A.mode == MODE_FIRST && A0.singletons) return;  // k_expand_codes_p runs it
   __shared__ QEnt qbuf[Q ? 4 : 1][Q ? QCAP : 1];
   __shared__ int64_t ticket;
-  constexpr int K = Q ? 8 : 1;
-  const Tickets tk = pass_tickets<K>(A);
+  const int K = ticket_batch(A0, Q);
+  const Tickets tk = pass_tickets(A, K);
   for (;;) {
-    if (threadIdx.x == 0) ticket = (int64_t)atomicAdd(&A0.ctl->work, 1ull);
+    if (threadIdx.x == 0) ticket = next_ticket(A0.ctl);
     __syncthreads();
     const int64_t k = ticket;
     __syncthreads();
     if (k >= tk.count) break;
     int64_t b0, b1;
-    ticket_items<K>(tk, k, &b0, &b1);
+    ticket_items(tk, K, k, &b0, &b1);
     for (int64_t b = b0; b < b1; ++b) expand_item<B, Q, true>(A, Q ? qbuf[threadIdx.x >> 6] : nullptr, b);
   }
 }
@@ -1170,15 +1183,15 @@ __global__ HB_PERSIST_ATTR void k_expand_codes_p(PassArgs A0) {
   __shared__ int64_t ticket;
   uint4* z = reinterpret_cast<uint4*>(&regs[0][0]);
   for (int i = threadIdx.x; i < CODE_WORDS; i += 256) z[i] = zero4();
-  const Tickets tk = pass_tickets<1>(A);
+  const Tickets tk = pass_tickets(A, 1);
   for (;;) {
     __syncthreads();
-    if (threadIdx.x == 0) ticket = (int64_t)atomicAdd(&A0.ctl->work, 1ull);
+    if (threadIdx.x == 0) ticket = next_ticket(A0.ctl);
     __syncthreads();
     const int64_t k = ticket;
     if (k >= tk.count) break;
     int64_t b0, b1;
-    ticket_items<1>(tk, k, &b0, &b1);
+    ticket_items(tk, 1, k, &b0, &b1);
     for (int64_t b = b0; b < b1; ++b) codes_item<B, true>(A, regs, b, threadIdx.x & 63, threadIdx.x >> 6);
   }
 }
@@ -1920,6 +1933,7 @@ __global__ void k_graph_done(PassArgs A0) {
     gd->done = 1;
     gd->passes = A.epoch - gd->t0;
     atomicAdd(&A0.ctl->n_done, 1);
+    if (A0.ctl->batch) atomicAdd(&A0.ctl->rows_done, (unsigned long long)gd->n);
   }
 }
 
@@ -2077,6 +2091,20 @@ __global__ void k_admit(PassCtl* ctl, GraphDev* graphs, int32_t slot, GraphDev v
     ctl->chg += (unsigned long long)val.n;
     ctl->pairs += (unsigned long long)m;
   }
+}
+
+// One wavefront per 64-entry chunk of the light list: the graph all its rows
+// belong to, or -1.
+__global__ void k_chunk_graph(const int32_t* light, int64_t n_light, const int32_t* blk_graph, int32_t* chunk_graph) {
+  const int lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t i = j * 64 + lane;
+  if (j * 64 >= n_light) return;
+  const int32_t g = i < n_light ? blk_graph[light[i] >> 6] : -1;
+  const int32_t g0 = __shfl(g, 0);
+  const bool same = i >= n_light || g == g0;
+  const bool all = __ballot(!same) == 0ull;
+  if (lane == 0) chunk_graph[j] = all ? g0 : -1;
 }
 
 // New planning totals; the mode of the pass about to run is planned again
@@ -2500,6 +2528,15 @@ hipError_t launch_admit(PassCtl* ctl, GraphDev* graphs, int32_t slot, const Grap
                         int32_t* blk_graph, uint64_t* mod0, uint64_t* mod1, int64_t b0, int64_t b1, hipStream_t s) {
   hipLaunchKernelGGL(k_admit, dim3(grid_for(b1 - b0 + 1, 256, 4096)), dim3(256), 0, s, ctl, graphs, slot, val, m,
                      blk_graph, mod0, mod1, b0, b1);
+  return hipGetLastError();
+}
+
+hipError_t launch_chunk_graph(const int32_t* light, int64_t n_light, const int32_t* blk_graph, int32_t* chunk_graph,
+                              hipStream_t s) {
+  const int64_t chunks = (n_light + 63) / 64;
+  if (chunks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_chunk_graph, dim3((unsigned)((chunks + 3) / 4)), dim3(256), 0, s, light, n_light, blk_graph,
+                     chunk_graph);
   return hipGetLastError();
 }
 
