@@ -106,7 +106,8 @@ typedef struct {
  *              from lists of the arcs into changed counters (sorted by
  *              source row) instead of activation stamps, when they fit the
  *              list capacity sized at init (about (m + n) / 16 pairs, all of
- *              them for m + n <= 2^20); 0: activation stamps only. */
+ *              them for m + n <= 2^16; about 80 bytes of device memory per
+ *              pair); 0: activation stamps only. */
 typedef struct {
   int32_t frontier;
   int32_t light_max;

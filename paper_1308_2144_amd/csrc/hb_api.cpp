@@ -322,12 +322,14 @@ hb_status do_reset(hb_ctx* c, uint64_t seed) {
   return HB_OK;
 }
 
-// Pair-list buffers of sparse passes: every pair for small graphs, else
-// about (m + n) / 16 (the sparse tail of a large graph needs far fewer).
+// Pair-list buffers of sparse passes: every pair for small graphs (m + n <=
+// 2^16), else about (m + n) / 16 (the sparse tail of a large graph needs far
+// fewer; a pass with more pairs uses activation stamps).  About 80 bytes per
+// pair of capacity.
 hb_status alloc_pairs(hb_ctx* c) {
   hb::PairBufs& pb = c->pb;
   const int64_t all = c->m + c->n;
-  const int64_t cap = std::min<int64_t>(all <= (1ll << 20) ? all : std::max<int64_t>(1ll << 20, all / 16),
+  const int64_t cap = std::min<int64_t>(all <= (1ll << 16) ? all : std::max<int64_t>(1ll << 16, all / 16),
                                         0x7fffffffLL);
   pb.cap = cap;
   pb.items_cap = cap + cap / hb::RUN_CHUNK + 1;
