@@ -36,6 +36,8 @@ METRIC = "edge visits/s per iteration + % HBM peak (R-MAT s24); batched graphs/s
 
 WORKLOADS = {
     "rmat-s24": dict(scale=24, ef=16, gen_seed=3, log2m=7, offsets=64),
+    # the same graph without the seeded relabelling (R-MAT's own id locality)
+    "rmat-s24-raw": dict(scale=24, ef=16, gen_seed=3, log2m=7, offsets=64, relabel=False),
     "rmat-s20": dict(scale=20, ef=16, gen_seed=2, log2m=6, offsets=32),
     "rmat-s10u": dict(scale=10, ef=8, gen_seed=1, log2m=4, offsets=32, undirected=True),
 }
@@ -52,7 +54,8 @@ def make_graph(w):
     if w.get("undirected"):
         off, idx = graphgen.rmat(w["scale"], w["ef"], seed=w["gen_seed"], directed=False)
     else:
-        off, idx = graphgen.rmat(w["scale"], w["ef"], seed=w["gen_seed"], transpose=True, relabel=True)
+        off, idx = graphgen.rmat(w["scale"], w["ef"], seed=w["gen_seed"], transpose=True,
+                                 relabel=w.get("relabel", True))
     log(f"graph: n={len(off) - 1} m={len(idx)} generated in {time.time() - t:.1f}s")
     return off, idx
 
