@@ -77,6 +77,8 @@ def test_every_pass_matches():
     dict(dense_pct=101, sparse_pct=101),          # every pass after the first is sparse
     dict(dense_pct=101),                          # edge passes, then sparse ones
     dict(dense_pct=101, push=0),                  # edge passes only (no reverse CSR)
+    dict(dense_pct=101, slice=1),                 # edge passes with slice masks, then sparse pair passes
+    dict(dense_pct=101, sparse_pct=101, slice=1),  # sparse pair passes writing slice masks
     dict(dense_pct=101, sparse_pct=101, pairs=0),  # sparse passes from activation stamps
     dict(dense_pct=101, sparse_pct=101, pairs=0, light_max=2, heavy_min=6, chunk=3),
     dict(dense_pct=101, sparse_pct=0, slice=1, light_max=2, heavy_min=6, chunk=3),
