@@ -1183,7 +1183,7 @@ __global__ HB_PERSIST_ATTR void k_expand_codes_p(PassArgs A0) {
   __shared__ int64_t ticket;
   uint4* z = reinterpret_cast<uint4*>(&regs[0][0]);
   for (int i = threadIdx.x; i < CODE_WORDS; i += 256) z[i] = zero4();
-  const Tickets tk = pass_tickets(A, 1);
+  const Tickets tk = pass_tickets(A, 8);  // no counter gathers: no L2 window to keep narrow
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) ticket = next_ticket(A0.ctl);
@@ -1191,7 +1191,7 @@ __global__ HB_PERSIST_ATTR void k_expand_codes_p(PassArgs A0) {
     const int64_t k = ticket;
     if (k >= tk.count) break;
     int64_t b0, b1;
-    ticket_items(tk, 1, k, &b0, &b1);
+    ticket_items(tk, 8, k, &b0, &b1);
     for (int64_t b = b0; b < b1; ++b) codes_item<B, true>(A, regs, b, threadIdx.x & 63, threadIdx.x >> 6);
   }
 }
