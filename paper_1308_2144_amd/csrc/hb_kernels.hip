@@ -801,7 +801,12 @@ __device__ __forceinline__ int64_t pass_items(const PassArgs& A) {
 // consecutive rows the counters of nearby successors stay in L2 (measured on
 // the 4096-graph batch: K = 8 makes its all-active dense passes 20 % slower,
 // K = 1 its first half-converged pass 45 % slower).
+// Batching needs far more light items than workgroups (a served engine's
+// pass may have only thousands: taking them eight at a time would leave most
+// of the grid idle).
 __device__ __forceinline__ int ticket_batch(const PassArgs& A0, bool queued) {
+  const int64_t light_items = (A0.n_light + 255) / 256;
+  if (light_items < 64 * (int64_t)gridDim.x) return 1;
   if (queued) return 8;
   const PassCtl* c = A0.ctl;
   return c->batch && 3ull * c->rows_done > (unsigned long long)A0.n ? 8 : 1;
@@ -1183,7 +1188,9 @@ __global__ HB_PERSIST_ATTR void k_expand_codes_p(PassArgs A0) {
   __shared__ int64_t ticket;
   uint4* z = reinterpret_cast<uint4*>(&regs[0][0]);
   for (int i = threadIdx.x; i < CODE_WORDS; i += 256) z[i] = zero4();
-  const Tickets tk = pass_tickets(A, 8);  // no counter gathers: no L2 window to keep narrow
+  // no counter gathers, so no L2 window to keep narrow: batch when there are enough items
+  const int K = (A.n_light + 255) / 256 >= 64 * (int64_t)gridDim.x ? 8 : 1;
+  const Tickets tk = pass_tickets(A, K);
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) ticket = next_ticket(A0.ctl);
@@ -1191,7 +1198,7 @@ __global__ HB_PERSIST_ATTR void k_expand_codes_p(PassArgs A0) {
     const int64_t k = ticket;
     if (k >= tk.count) break;
     int64_t b0, b1;
-    ticket_items(tk, 8, k, &b0, &b1);
+    ticket_items(tk, K, k, &b0, &b1);
     for (int64_t b = b0; b < b1; ++b) codes_item<B, true>(A, regs, b, threadIdx.x & 63, threadIdx.x >> 6);
   }
 }
