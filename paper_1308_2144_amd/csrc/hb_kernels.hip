@@ -136,8 +136,11 @@ __device__ __forceinline__ uint4 bmax(uint4 a, uint4 b) {
   return a;
 }
 
-// Gather accumulator kept as even and odd bytes in separate 16-bit lanes, so
-// folding in one dword costs two masks and two packed maxima.
+// Gather accumulator in two sets of 16-bit lanes: e holds the even bytes
+// (masked into the low half of each lane), o the raw dwords.  A 16-bit
+// maximum orders lanes by their high byte first, so the high bytes of o are
+// the maxima of the odd bytes whatever the low bytes were; folding in one
+// dword costs one mask and two packed maxima.
 struct SplitAcc {
   uint4 e;
   uint4 o;
@@ -150,17 +153,19 @@ __device__ __forceinline__ uint32_t pkmax(uint32_t a, uint32_t b) {
 
 __device__ __forceinline__ void fold(SplitAcc& acc, uint4 x) {
   acc.e.x = pkmax(acc.e.x, x.x & 0x00FF00FFu);
-  acc.o.x = pkmax(acc.o.x, x.x & 0xFF00FF00u);
+  acc.o.x = pkmax(acc.o.x, x.x);
   acc.e.y = pkmax(acc.e.y, x.y & 0x00FF00FFu);
-  acc.o.y = pkmax(acc.o.y, x.y & 0xFF00FF00u);
+  acc.o.y = pkmax(acc.o.y, x.y);
   acc.e.z = pkmax(acc.e.z, x.z & 0x00FF00FFu);
-  acc.o.z = pkmax(acc.o.z, x.z & 0xFF00FF00u);
+  acc.o.z = pkmax(acc.o.z, x.z);
   acc.e.w = pkmax(acc.e.w, x.w & 0x00FF00FFu);
-  acc.o.w = pkmax(acc.o.w, x.w & 0xFF00FF00u);
+  acc.o.w = pkmax(acc.o.w, x.w);
 }
 
 __device__ __forceinline__ uint4 unsplit(const SplitAcc& acc) {
-  return make_uint4(acc.e.x | acc.o.x, acc.e.y | acc.o.y, acc.e.z | acc.o.z, acc.e.w | acc.o.w);
+  constexpr uint32_t ODD = 0xFF00FF00u;
+  return make_uint4(acc.e.x | (acc.o.x & ODD), acc.e.y | (acc.o.y & ODD), acc.e.z | (acc.o.z & ODD),
+                    acc.e.w | (acc.o.w & ODD));
 }
 
 __device__ __forceinline__ bool differs(uint4 a, uint4 b) {
@@ -294,37 +299,55 @@ __device__ __forceinline__ PassArgs resolve(const PassArgs& A) {
 
 // Direct gather-max (dense passes) over the arcs k, k+st, k+2st, ... < e of
 // a row: every lane of the group loads its 16-byte slice of each successor
-// counter, U successors in flight.
-template <int B>
-__device__ __forceinline__ uint4 gather(const PassArgs& A, int64_t k, int64_t e, int64_t st, int gl,
+// counter, U successors in flight.  Slots past the end (and, with NEG,
+// negative ids, which mark no successor) load the row's own counter instead:
+// the row's result is the maximum with its own counter anyway, so the extra
+// operand changes nothing, and every load is unconditional (no zeroing, no
+// exec masking).  Only real successors count as gathered; without NEG their
+// number is known from the range, so the loop keeps no tally.
+template <int B, bool NEG = false>
+__device__ __forceinline__ uint4 gather(const PassArgs& A, int64_t k, int64_t e, int64_t st, int gl, int64_t own,
                                         bool& got, Counts& c) {
   constexpr int P = 1 << B;
-  constexpr int G = P / 16;
   SplitAcc acc{zero4(), zero4()};
   const uint8_t* base = A.cur + gl * 16;
+  const uint32_t own32 = (uint32_t)own;  // node ids fit 31 bits
+  const int32_t st32 = (int32_t)st;
+  if constexpr (!NEG) {
+    const uint32_t n = k < e ? (uint32_t)((e - k + st - 1) / st) : 0u;
+    got |= n > 0u;
+    c.slices += n;
+    if (gl == 0) c.gath += n;
+  }
   for (; k < e; k += st * U) {
+    // offsets from k in 32 bits: a row's or a chunk's arcs number < 2^31
+    const int32_t rem = (int32_t)(e - 1 - k);
     int32_t w[U];
+    bool ok[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t kk = k + u * st;
-      w[u] = kk < e ? ld_stream(A.idx + kk) : -1;
+      const int32_t d = u * st32;
+      ok[u] = d <= rem;
+      w[u] = ld_stream(A.idx + k + (d < rem ? d : rem));
     }
     uint4 v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      v[u] = zero4();
-      if (w[u] >= 0) v[u] = *reinterpret_cast<const uint4*>(base + (size_t)w[u] * P);
+      if constexpr (NEG) ok[u] = ok[u] && w[u] >= 0;
+      const uint32_t src = ok[u] ? (uint32_t)w[u] : own32;
+      v[u] = *reinterpret_cast<const uint4*>(base + (size_t)src * P);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       fold(acc, v[u]);
-      const uint32_t hit = w[u] >= 0 ? 1u : 0u;
-      got |= hit != 0u;
-      c.slices += hit;
-      if (gl == 0) c.gath += hit;
+      if constexpr (NEG) {
+        const uint32_t hit = ok[u] ? 1u : 0u;
+        got |= hit != 0u;
+        c.slices += hit;
+        if (gl == 0) c.gath += hit;
+      }
     }
   }
-  (void)G;
   return unsplit(acc);
 }
 
@@ -671,7 +694,7 @@ __device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, int64_t 
         if constexpr (Q)
           acc = gather_group_q<B>(A, q, rs, rs + rd, gl, gmask, lanes_below(lane), got, c);
         else
-          acc = gather<B>(A, rs, rs + rd, 1, gl, got, c);
+          acc = gather<B>(A, rs, rs + rd, 1, gl, rrow, got, c);
         if (gl == 0) c.arcs += (uint32_t)rd;
         if (lazy && got) pre = preload<B, FL>(A, rrow, gl);
         // Multi-graph passes run many short rows per byte moved, so there the
@@ -710,7 +733,7 @@ __device__ __forceinline__ void medium_wave(const PassArgs& A, QEnt* qw, int64_t
     if constexpr (Q)
       acc = gather_wave_q<B>(A, qw, s, s + deg, lane, gl, grp, lanes_below(lane), got, c);
     else
-      acc = gather<B>(A, s + grp, s + deg, W, gl, got, c);
+      acc = gather<B>(A, s + grp, s + deg, W, gl, row, got, c);
     if (lane == 0) c.arcs += (uint32_t)deg;
 #pragma unroll
     for (int o = G; o < 64; o <<= 1) acc = bmax(acc, shfl_xor4(acc, o));
@@ -744,7 +767,7 @@ __device__ __forceinline__ void heavy_chunk(const PassArgs& A, QEnt* qw, int64_t
     const int64_t a1 = a0 + quarter < it.e1 ? a0 + quarter : it.e1;
     acc = gather_wave_q<B>(A, qw, a0, a1, lane, gl, grp, lanes_below(lane), got, c);
   } else {
-    acc = gather<B>(A, it.e0 + wave * W + grp, it.e1, 4 * W, gl, got, c);
+    acc = gather<B>(A, it.e0 + wave * W + grp, it.e1, 4 * W, gl, it.row, got, c);
   }
   if (lane == 0 && wave == 0) c.arcs += (uint32_t)(it.e1 - it.e0);
 #pragma unroll
@@ -1883,7 +1906,7 @@ __global__ HB_EXPAND_ATTR void k_pair_expand(PassArgs A, const int32_t* vals, co
     if (whole) pre = preload<B, FL>(A, pi.row, gl);
     bool got = false;
     const uint32_t g0 = c.gath;
-    const uint4 acc = gather<B>(L, pi.start, pi.start + pi.len, 1, gl, got, c);
+    const uint4 acc = gather<B, true>(L, pi.start, pi.start + pi.len, 1, gl, pi.row, got, c);
     if (gl == 0) c.arcs += c.gath - g0;
     if (whole)
       (void)finish_row<B, false, FL>(A, pi.row, acc, got, pre, bit_of(A.mod_prev, pi.row), gl, grp, c);
