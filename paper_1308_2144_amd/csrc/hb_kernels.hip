@@ -405,24 +405,23 @@ __device__ __forceinline__ int scan_chunk(const PassArgs& A, QEnt* q, int64_t k,
 }
 
 // Phase 2: entries first, first+step, ... < nh of the queue, U in flight.
+// As in the direct gather, slots past the queue's end and slices the entry
+// does not need load the row's own counter (own) instead, unconditionally.
 template <int B>
 __device__ __forceinline__ void drain(const PassArgs& A, const QEnt* q, int first, int nh, int step, int gl,
-                                      SplitAcc& acc, Counts& c) {
+                                      uint32_t own, SplitAcc& acc, Counts& c) {
   constexpr int P = 1 << B;
   const uint8_t* base = A.cur + gl * 16;
   for (int i = first; i < nh; i += step * U) {
     uint4 v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      v[u] = zero4();
       const int j = i + u * step;
-      if (j < nh) {
-        const QEnt ent = q[j];
-        if ((ent.msk >> gl) & 1u) {
-          v[u] = *reinterpret_cast<const uint4*>(base + (size_t)ent.w * P);
-          c.slices += 1u;
-        }
-      }
+      const bool in = j < nh;
+      const QEnt ent = q[in ? j : i];
+      const bool hit = in && ((ent.msk >> gl) & 1u) != 0u;
+      c.slices += hit ? 1u : 0u;
+      v[u] = *reinterpret_cast<const uint4*>(base + (size_t)(hit ? (uint32_t)ent.w : own) * P);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) fold(acc, v[u]);
@@ -432,7 +431,7 @@ __device__ __forceinline__ void drain(const PassArgs& A, const QEnt* q, int firs
 // Queued gather of one row's arcs [s, e) by one lane group (light rows).
 template <int B>
 __device__ __forceinline__ uint4 gather_group_q(const PassArgs& A, QEnt* q, int64_t s, int64_t e, int gl,
-                                                uint64_t gmask, uint64_t below, bool& got, Counts& c) {
+                                                uint64_t gmask, uint64_t below, int64_t own, bool& got, Counts& c) {
   constexpr int G = (1 << B) / 16;
   SplitAcc acc{zero4(), zero4()};
   for (int64_t k = s; k < e; k += (int64_t)G * U) {
@@ -440,7 +439,7 @@ __device__ __forceinline__ uint4 gather_group_q(const PassArgs& A, QEnt* q, int6
     __builtin_amdgcn_wave_barrier();
     if (gl == 0) c.gath += (uint32_t)nh;
     got |= nh > 0;
-    drain<B>(A, q, 0, nh, 1, gl, acc, c);
+    drain<B>(A, q, 0, nh, 1, gl, (uint32_t)own, acc, c);
     __builtin_amdgcn_wave_barrier();
   }
   return unsplit(acc);
@@ -450,7 +449,7 @@ __device__ __forceinline__ uint4 gather_group_q(const PassArgs& A, QEnt* q, int6
 // entries grp, grp+W, ...  Returns the group's partial maximum.
 template <int B>
 __device__ __forceinline__ uint4 gather_wave_q(const PassArgs& A, QEnt* q, int64_t s, int64_t e, int lane,
-                                               int gl, int grp, uint64_t below, bool& got, Counts& c) {
+                                               int gl, int grp, uint64_t below, int64_t own, bool& got, Counts& c) {
   constexpr int G = (1 << B) / 16;
   constexpr int W = 64 / G;
   SplitAcc acc{zero4(), zero4()};
@@ -459,7 +458,7 @@ __device__ __forceinline__ uint4 gather_wave_q(const PassArgs& A, QEnt* q, int64
     __builtin_amdgcn_wave_barrier();
     if (lane == 0) c.gath += (uint32_t)nh;
     got |= nh > 0;
-    drain<B>(A, q, grp, nh, W, gl, acc, c);
+    drain<B>(A, q, grp, nh, W, gl, (uint32_t)own, acc, c);
     __builtin_amdgcn_wave_barrier();
   }
   return unsplit(acc);
@@ -692,7 +691,7 @@ __device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, int64_t 
         bool got = false;
         uint4 acc;
         if constexpr (Q)
-          acc = gather_group_q<B>(A, q, rs, rs + rd, gl, gmask, lanes_below(lane), got, c);
+          acc = gather_group_q<B>(A, q, rs, rs + rd, gl, gmask, lanes_below(lane), rrow, got, c);
         else
           acc = gather<B>(A, rs, rs + rd, 1, gl, rrow, got, c);
         if (gl == 0) c.arcs += (uint32_t)rd;
@@ -731,7 +730,7 @@ __device__ __forceinline__ void medium_wave(const PassArgs& A, QEnt* qw, int64_t
     bool got = false;
     uint4 acc;
     if constexpr (Q)
-      acc = gather_wave_q<B>(A, qw, s, s + deg, lane, gl, grp, lanes_below(lane), got, c);
+      acc = gather_wave_q<B>(A, qw, s, s + deg, lane, gl, grp, lanes_below(lane), row, got, c);
     else
       acc = gather<B>(A, s + grp, s + deg, W, gl, row, got, c);
     if (lane == 0) c.arcs += (uint32_t)deg;
@@ -765,7 +764,7 @@ __device__ __forceinline__ void heavy_chunk(const PassArgs& A, QEnt* qw, int64_t
     const int64_t quarter = (it.e1 - it.e0 + 3) / 4;
     const int64_t a0 = it.e0 + wave * quarter;
     const int64_t a1 = a0 + quarter < it.e1 ? a0 + quarter : it.e1;
-    acc = gather_wave_q<B>(A, qw, a0, a1, lane, gl, grp, lanes_below(lane), got, c);
+    acc = gather_wave_q<B>(A, qw, a0, a1, lane, gl, grp, lanes_below(lane), it.row, got, c);
   } else {
     acc = gather<B>(A, it.e0 + wave * W + grp, it.e1, 4 * W, gl, it.row, got, c);
   }
