@@ -299,18 +299,49 @@ __device__ __forceinline__ PassArgs resolve(const PassArgs& A) {
 
 // Direct gather-max (dense passes) over the arcs k, k+st, k+2st, ... < e of
 // a row: every lane of the group loads its 16-byte slice of each successor
-// counter, U successors in flight.  Slots past the end (and, with NEG,
-// negative ids, which mark no successor) load the row's own counter instead:
-// the row's result is the maximum with its own counter anyway, so the extra
-// operand changes nothing, and every load is unconditional (no zeroing, no
-// exec masking).  Only real successors count as gathered; without NEG their
-// number is known from the range, so the loop keeps no tally.
+// counter, U successors in flight.
+//
+// For p >= 64, slots past the end (and, with NEG, negative ids, which mark
+// no successor) load the row's own counter instead: the row's result is the
+// maximum with its own counter anyway, so the extra operand changes nothing;
+// every load is unconditional (no zeroing, no exec masking), offsets are 32
+// bits, and without NEG the number of gathered successors is known from the
+// range, so the loop keeps no tally (R-MAT s24 dense pass 5.83 -> 5.45 ms).
+// For p <= 32 rows are short relative to a round of U slots and the padding
+// loads cost more than they save (4096-graph batch: 2 % slower), so slots
+// past the end are zeroed and their loads skipped.
 template <int B, bool NEG = false>
 __device__ __forceinline__ uint4 gather(const PassArgs& A, int64_t k, int64_t e, int64_t st, int gl, int64_t own,
                                         bool& got, Counts& c) {
   constexpr int P = 1 << B;
   SplitAcc acc{zero4(), zero4()};
   const uint8_t* base = A.cur + gl * 16;
+  if constexpr (B <= 5) {
+    (void)own;
+    for (; k < e; k += st * U) {
+      int32_t w[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t kk = k + u * st;
+        w[u] = kk < e ? ld_stream(A.idx + kk) : -1;
+      }
+      uint4 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        v[u] = zero4();
+        if (w[u] >= 0) v[u] = *reinterpret_cast<const uint4*>(base + (size_t)w[u] * P);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        fold(acc, v[u]);
+        const uint32_t hit = w[u] >= 0 ? 1u : 0u;
+        got |= hit != 0u;
+        c.slices += hit;
+        if (gl == 0) c.gath += hit;
+      }
+    }
+    return unsplit(acc);
+  }
   const uint32_t own32 = (uint32_t)own;  // node ids fit 31 bits
   const int32_t st32 = (int32_t)st;
   if constexpr (!NEG) {
