@@ -275,6 +275,18 @@ def test_sparse_pair_lists_long_runs(b):
             assert paths == [0] * len(paths)
 
 
+def test_sparse_passes_mix_stamps_and_pair_lists():
+    """R-MAT scale 15 (m + n > 2^16, so the pair lists hold (m + n) / 16
+    pairs) with every pass after the first sparse: the early passes have
+    more pairs than fit and run from activation stamps, the later ones from
+    pair lists; the run equals the oracle pass by pass."""
+    off, idx = gg.rmat(15, 16, seed=35, transpose=True, relabel=True)
+    got, _ = check(off, idx, 6, 41, "rmat15 sparse", dense_pct=101, sparse_pct=101)
+    paths = [p["path"] for p in got["pass_stats"][1:]]
+    assert 0 in paths and 2 in paths, paths
+    assert paths.index(2) > paths.index(0)
+
+
 def test_validation_rejects_bad_indices():
     import paper_1308_2144_amd as hb
 
