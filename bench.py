@@ -562,7 +562,7 @@ def main():
                     help="also run a plain 1 GiB device copy (torch) 3 times, to scale HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "one GPU per run: sharding a graph over several GPUs is not implemented, so --gpus must be 1"}))
         sys.exit(2)
 
     import torch
