@@ -445,7 +445,7 @@ hb_status get_engine(hb_server* s, int b, Engine** out) {
 }
 
 // Enqueues the upload and admission of a placed request.
-hb_status enqueue_admit(hb_server* s, Engine* e, Req* r) {
+hb_status enqueue_admit(Engine* e, Req* r) {
   hb_ctx* c = e->c;
   hipStream_t st = c->stream;
   const hb_csr& g = r->rq.graph;
@@ -697,7 +697,7 @@ hb_status serve_step(hb_server* s, bool* progress) {
       r->admitting = false;
       break;
     }
-    st = enqueue_admit(s, e, r);
+    st = enqueue_admit(e, r);
     if (st != HB_OK) return st;
     s->pending.pop_front();
     s->resident_bytes += r->bytes;
