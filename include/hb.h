@@ -261,8 +261,9 @@ hb_status hb_batch_passes(hb_ctx* c, int32_t* passes);
  * sorted by size, evenly spaced) and picks, by coordinate descent from *opt:
  * light_max (rows up to this many arcs go to one lane group, longer ones to
  * a wavefront), heavy_min / chunk (rows from heavy_min arcs are cut into
- * workgroup tiles of chunk arcs), wgs_per_cu, graph_passes, dense_pct,
- * sparse_pct and qdense.  The options never change results; the tuner checks
+ * workgroup tiles of chunk arcs), push (reverse CSR and sparse passes, or
+ * edge passes only), wgs_per_cu, graph_passes, dense_pct, sparse_pct and
+ * qdense.  The options never change results; the tuner checks
  * that every candidate gives the same per-graph pass counts.  *opt receives
  * the winner.  cache_path (nullable): a text file of earlier winners keyed
  * by a signature of the batch (log2m, sizes, degree histogram) and the

@@ -80,7 +80,7 @@ std::string signature(const hb_csr* graphs, int32_t k, int32_t log2m, const hb_o
   return key;
 }
 
-const char* CACHE_TAG = "hbtune1";
+const char* CACHE_TAG = "hbtune2";
 
 bool cache_lookup(const char* path, const std::string& key, hb_options* opt, double* ms) {
   if (!path || !*path) return false;
@@ -94,7 +94,7 @@ bool cache_lookup(const char* path, const std::string& key, hb_options* opt, dou
     double t = 0.0;
     if (!(ls >> tag >> k) || tag != CACHE_TAG || k != key) continue;
     if (ls >> o.light_max >> o.heavy_min >> o.chunk >> o.wgs_per_cu >> o.graph_passes >> o.dense_pct >> o.sparse_pct >>
-        o.qdense >> t) {
+        o.qdense >> o.push >> t) {
       *opt = o;  // the last matching line wins
       *ms = t;
       found = true;
@@ -107,7 +107,8 @@ void cache_store(const char* path, const std::string& key, const hb_options& o, 
   if (!path || !*path) return;
   std::ofstream out(path, std::ios::app);
   out << CACHE_TAG << " " << key << " " << o.light_max << " " << o.heavy_min << " " << o.chunk << " " << o.wgs_per_cu
-      << " " << o.graph_passes << " " << o.dense_pct << " " << o.sparse_pct << " " << o.qdense << " " << ms << "\n";
+      << " " << o.graph_passes << " " << o.dense_pct << " " << o.sparse_pct << " " << o.qdense << " " << o.push << " "
+      << ms << "\n";
 }
 
 struct Sample {
@@ -237,6 +238,18 @@ hb_status hb_batch_autotune(const hb_csr* graphs, int32_t k, int32_t log2m, cons
     hb_options o = best;
     o.heavy_min = t[0];
     o.chunk = t[1];
+    double ms = 0.0;
+    st = time_structural(s, o, reps, ref, &ms, stream);
+    if (st != HB_OK) return st;
+    rep.candidates++;
+    if (ms < best_ms) best_ms = ms, best = o;
+  }
+  // The reverse CSR (push): sparse passes from activation stamps, or edge
+  // passes only (in a batch whose converged graphs are skipped cheaply, the
+  // edge passes can win, and init skips the sort of every arc).
+  {
+    hb_options o = best;
+    o.push = best.push ? 0 : 1;
     double ms = 0.0;
     st = time_structural(s, o, reps, ref, &ms, stream);
     if (st != HB_OK) return st;
