@@ -242,7 +242,7 @@ def bench_batch(args, torch, hb, plain_sample: int = 512):
             "plain_cold_graphs_per_s": k / cdt, "plain_cold_sample": int(len(cold)),
             "speedup_vs_plain": pdt / bdt, "identical_on_sample": bool(identical),
             "autotune": {"options": {k: tuned[k] for k in ("light_max", "heavy_min", "chunk", "wgs_per_cu",
-                                                            "graph_passes", "dense_pct", "sparse_pct", "qdense")},
+                                                            "graph_passes", "dense_pct", "sparse_pct", "qdense", "push")},
                          **tune},
             "mismatches_on_sample": mismatch}
 
