@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <sys/mman.h>
 #include <new>
 #include <string>
 #include <thread>
@@ -25,6 +26,28 @@ constexpr int DEFAULT_HEAVY_MIN = 8192;
 constexpr int DEFAULT_CHUNK = 4096;
 constexpr int DEFAULT_DENSE_PCT = 60;
 constexpr int DEFAULT_SPARSE_PCT = 20;
+
+// Anonymous host mapping for the batch arena: uninitialised, released on
+// scope exit, huge pages advised.
+template <class T>
+struct HostArena {
+  T* p = nullptr;
+  size_t bytes = 0;
+  explicit HostArena(size_t count) : bytes(count * sizeof(T)) {
+    void* m = mmap(nullptr, bytes, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS, -1, 0);
+    if (m == MAP_FAILED) return;
+    (void)madvise(m, bytes, MADV_HUGEPAGE);
+    p = static_cast<T*>(m);
+  }
+  ~HostArena() {
+    if (p) (void)munmap(p, bytes);
+  }
+  HostArena(const HostArena&) = delete;
+  HostArena& operator=(const HostArena&) = delete;
+  explicit operator bool() const { return p != nullptr; }
+  T& operator[](size_t i) { return p[i]; }
+  T* get() { return p; }
+};
 
 }  // namespace
 
@@ -1048,8 +1071,13 @@ hb_status hb_batch_init(hb_ctx** out, const hb_csr* graphs, int32_t k, int32_t l
     packed += g.n;
   }
   if (nodes > 0x7fffffffLL) return fail(HB_EINVAL, "batch too large for int32 node ids");
-  std::vector<int64_t> off((size_t)nodes + 1);
-  std::vector<int32_t> idx((size_t)(arcs > 0 ? arcs : 1));
+  // Left uninitialised: the fill threads write every entry, so the pages are
+  // first touched in parallel (zeroing 6.9 GB on one thread cost about as
+  // much as the whole fill on the 4096-graph batch), and backed by huge pages
+  // where the kernel allows it (fewer page faults).
+  HostArena<int64_t> off((size_t)nodes + 1);
+  HostArena<int32_t> idx((size_t)(arcs > 0 ? arcs : 1));
+  if (!off || !idx) return fail(HB_ENOMEM, "cannot allocate the host arena");
   std::vector<int32_t> blk((size_t)(nodes / 64));
   std::vector<int64_t> abase((size_t)k + 1, 0);
   for (int32_t i = 0; i < k; ++i) abase[(size_t)i + 1] = abase[(size_t)i] + graphs[i].m;
@@ -1139,9 +1167,9 @@ hb_status hb_batch_init(hb_ctx** out, const hb_csr* graphs, int32_t k, int32_t l
   hb_csr arena;
   arena.n = nodes;
   arena.m = arcs;
-  arena.offsets = off.data();
+  arena.offsets = off.get();
   arena.offsets_bits = 64;
-  arena.indices = idx.data();
+  arena.indices = idx.get();
   arena.on_device = 0;
   const hb_status st = init_impl(c, &arena, log2m, 0, opt, s, &blk);
   if (st != HB_OK) {
