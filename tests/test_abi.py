@@ -130,3 +130,24 @@ def test_distance_stats_equal_oracle():
     assert hb.hb_distance_stats([5.0]) == oracle.distance_stats([5.0])
     with pytest.raises(hb.HBError):
         hb.hb_distance_stats([])
+
+
+def test_batch_argument_errors():
+    """Malformed graphs of a batch are refused while the host arena is filled,
+    before any device work, with the index of the first bad graph."""
+    import paper_1308_2144_amd as hb
+
+    good = (np.array([0, 1, 2], dtype=np.int64), np.array([1, 0], dtype=np.int32))
+    bad_idx = (np.array([0, 1, 2], dtype=np.int64), np.array([1, 2], dtype=np.int32))     # id 2 >= n
+    bad_off = (np.array([0, 2, 1], dtype=np.int32), np.array([1, 0], dtype=np.int32))     # decreasing
+    for graphs, msg in (([good, bad_idx], "graph 1: index outside"), ([bad_off, good], "graph 0: malformed offsets"),
+                        ([good] * 40 + [bad_idx], "graph 40: index outside")):
+        with pytest.raises(hb.HBError) as e:
+            hb.hb_batch_init(graphs, 5, np.arange(len(graphs), dtype=np.uint64))
+        assert e.value.status == hb.HB_EINVAL and msg in str(e.value), str(e.value)
+    for b in (3, 9):
+        with pytest.raises(hb.HBError) as e:
+            hb.hb_batch_init([good], b, [1])
+        assert e.value.status == hb.HB_EINVAL
+    with pytest.raises(ValueError):
+        hb.hb_batch_init([good, good], 5, [1])       # one seed per graph (checked by the binding)
