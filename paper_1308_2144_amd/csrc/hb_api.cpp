@@ -1110,7 +1110,9 @@ hb_status hb_batch_init(hb_ctx** out, const hb_csr* graphs, int32_t k, int32_t l
           return 1;
         }
         prev = o;
-        off[(size_t)(base + v)] = a + o;
+        // entry n belongs to the next graph (or is the arena's last) when n
+        // is a multiple of 64: it gets the same value there, written once
+        if (v < npad) off[(size_t)(base + v)] = a + o;
       }
       for (int64_t v = g.n + 1; v < npad; ++v) off[(size_t)(base + v)] = a + g.m;
       for (int64_t e = 0; e < g.m; ++e) {
