@@ -235,7 +235,8 @@ hb_status hb_pass_stats(hb_ctx* c, int32_t pass, hb_pass_info* info);
  * device (mode, pass index and convergence live in device memory), run
  * persistent kernels over all unconverged graphs at once, and hb_run replays
  * them as a captured hipGraph with one small readback per replay.
- * log2m in [4, 8].  With stream NULL the context creates its own stream.
+ * log2m in [4, 8].  Graphs may be empty (n = 0), but not all of them
+ * (HB_EINVAL).  With stream NULL the context creates its own stream.
  * On a batched context: hb_run runs until every graph converged (or the
  * engine pass cap); hb_iterate runs one pass over all graphs; outputs of
  * hb_centralities / hb_get_accumulators / hb_get_registers are packed: graph

@@ -1071,6 +1071,7 @@ hb_status hb_batch_init(hb_ctx** out, const hb_csr* graphs, int32_t k, int32_t l
     packed += g.n;
   }
   if (nodes > 0x7fffffffLL) return fail(HB_EINVAL, "batch too large for int32 node ids");
+  if (nodes == 0) return fail(HB_EINVAL, "a batch needs at least one graph with nodes");
   // Left uninitialised: the fill threads write every entry, so the pages are
   // first touched in parallel (zeroing 6.9 GB on one thread cost about as
   // much as the whole fill on the 4096-graph batch), and backed by huge pages

@@ -204,6 +204,11 @@ hb_status hb_batch_autotune(const hb_csr* graphs, int32_t k, int32_t log2m, cons
     s.graphs.push_back(graphs[i]);
     s.seeds.push_back(seeds[i]);
   }
+  // a batch needs nodes: a sample of empty graphs only takes the largest one
+  if (std::none_of(s.graphs.begin(), s.graphs.end(), [](const hb_csr& g) { return g.n > 0; })) {
+    s.graphs.back() = graphs[order[(size_t)k - 1]];
+    s.seeds.back() = seeds[order[(size_t)k - 1]];
+  }
   hipStream_t stream = nullptr;
   HB_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
   struct StreamGuard {

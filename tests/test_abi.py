@@ -151,3 +151,7 @@ def test_batch_argument_errors():
         assert e.value.status == hb.HB_EINVAL
     with pytest.raises(ValueError):
         hb.hb_batch_init([good, good], 5, [1])       # one seed per graph (checked by the binding)
+    empty = (np.zeros(1, dtype=np.int64), np.zeros(0, dtype=np.int32))
+    with pytest.raises(hb.HBError) as e:
+        hb.hb_batch_init([empty, empty], 5, [1, 2])  # nothing to compute
+    assert e.value.status == hb.HB_EINVAL and "at least one graph with nodes" in str(e.value)

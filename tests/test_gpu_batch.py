@@ -169,3 +169,17 @@ def test_autotune_picks_candidates_and_caches(tmp_path):
     tuned = hb.options_dict(opt)
     compare_batch(graphs, 5, seeds, **{k: tuned[k] for k in ("light_max", "heavy_min", "chunk", "wgs_per_cu",
                                                             "graph_passes", "dense_pct", "sparse_pct", "qdense")})
+
+
+def test_mostly_empty_batches():
+    """Empty graphs beside one non-empty graph: the batch equals solo runs, and
+    an autotune sample of one graph takes the non-empty graph (a batch of empty
+    graphs only is refused at init)."""
+    import paper_1308_2144_amd as hb
+
+    graphs = [gg.empty(0), gg.empty(0), gg.empty(5), gg.directed_cycle(70), gg.empty(0)]
+    seeds = np.arange(len(graphs), dtype=np.uint64) + 11
+    compare_batch(graphs, 5, seeds)
+    opt, rep = hb.hb_batch_autotune([gg.empty(0)] * 6 + [gg.star(40)], 5, np.arange(7, dtype=np.uint64), sample=1)
+    _log("autotune:", rep)
+    assert rep["sample_graphs"] == 1
