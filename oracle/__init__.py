@@ -48,14 +48,55 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
+_FLAGS = ["-O3", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+_lib_omp = None
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle (gcc, -O2, no FMA contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
+    """Compile the oracle (gcc -O3, no FMA contraction, no fast-math), and the
+    OpenMP build of the same file that only the all-core CPU baseline uses."""
+    for out, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(out):
+            tmp = out + ".tmp"
+            subprocess.check_call(["gcc"] + _FLAGS + extra + [_SRC, "-o", tmp, "-lm"])
+            os.replace(tmp, out)
     return _LIB
+
+
+def _declare(L):
+    vp, i64, u64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int
+    L.hbo_hash.argtypes = [u64, u64]
+    L.hbo_hash.restype = u64
+    L.hbo_rho.argtypes = [u64, ci]
+    L.hbo_rho.restype = ci
+    L.hbo_add.argtypes = [vp, ci, u64, u64]
+    L.hbo_add.restype = None
+    L.hbo_alpha.argtypes = [ci]
+    L.hbo_alpha.restype = ctypes.c_double
+    L.hbo_register_sum.argtypes = [vp, ci]
+    L.hbo_register_sum.restype = ctypes.c_double
+    L.hbo_size.argtypes = [vp, ci]
+    L.hbo_size.restype = ctypes.c_double
+    L.hbo_run.argtypes = [i64, vp, vp, ci, u64, ci, vp, vp, vp, vp, vp]
+    L.hbo_run.restype = ci
+    L.hbo_run_ext.argtypes = [i64, vp, vp, ci, u64, ci, vp, vp, ci, vp, vp, vp, vp, vp, i64, vp, vp]
+    L.hbo_run_ext.restype = ci
+    L.hbo_finalize.argtypes = [i64, vp, ci, vp, vp, vp, vp, vp, vp]
+    L.hbo_finalize.restype = None
+    L.hbo_node.argtypes = [i64, vp, vp, ci, u64, i64, ci, vp, vp, vp, vp, vp]
+    L.hbo_node.restype = ci
+    L.hbo_node_ext.argtypes = [i64, vp, vp, ci, u64, i64, ci, vp, vp, ci, vp, vp, vp, vp, vp, vp]
+    L.hbo_node_ext.restype = ci
+    L.hbo_run_full.argtypes = [i64, vp, vp, ci, u64, ci, vp, vp, ci, vp, vp, vp, vp, vp, i64, vp, vp, vp]
+    L.hbo_run_full.restype = ci
+    L.hbo_init_counters.argtypes = [i64, ci, u64, vp, vp]
+    L.hbo_init_counters.restype = None
+    L.hbo_pass.argtypes = [vp, vp, ci, ci, vp, vp, vp, vp, ctypes.c_double, vp, vp, i64, i64]
+    L.hbo_pass.restype = i64
+    L.hbo_threads.argtypes = []
+    L.hbo_threads.restype = ci
+    return L
 
 
 def _load():
@@ -63,32 +104,17 @@ def _load():
     if _lib is None:
         if not os.path.exists(_LIB):
             build(force=False)
-        L = ctypes.CDLL(_LIB)
-        vp, i64, u64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int
-        L.hbo_hash.argtypes = [u64, u64]
-        L.hbo_hash.restype = u64
-        L.hbo_rho.argtypes = [u64, ci]
-        L.hbo_rho.restype = ci
-        L.hbo_add.argtypes = [vp, ci, u64, u64]
-        L.hbo_add.restype = None
-        L.hbo_alpha.argtypes = [ci]
-        L.hbo_alpha.restype = ctypes.c_double
-        L.hbo_register_sum.argtypes = [vp, ci]
-        L.hbo_register_sum.restype = ctypes.c_double
-        L.hbo_size.argtypes = [vp, ci]
-        L.hbo_size.restype = ctypes.c_double
-        L.hbo_run.argtypes = [i64, vp, vp, ci, u64, ci, vp, vp, vp, vp, vp]
-        L.hbo_run.restype = ci
-        L.hbo_run_ext.argtypes = [i64, vp, vp, ci, u64, ci, vp, vp, ci, vp, vp, vp, vp, vp, i64, vp, vp]
-        L.hbo_run_ext.restype = ci
-        L.hbo_finalize.argtypes = [i64, vp, ci, vp, vp, vp, vp, vp, vp]
-        L.hbo_finalize.restype = None
-        L.hbo_node.argtypes = [i64, vp, vp, ci, u64, i64, ci, vp, vp, vp, vp, vp]
-        L.hbo_node.restype = ci
-        L.hbo_node_ext.argtypes = [i64, vp, vp, ci, u64, i64, ci, vp, vp, ci, vp, vp, vp, vp, vp, vp]
-        L.hbo_node_ext.restype = ci
-        _lib = L
+        _lib = _declare(ctypes.CDLL(_LIB))
     return _lib
+
+
+def _load_omp():
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(_LIB_OMP):
+            build(force=False)
+        _lib_omp = _declare(ctypes.CDLL(_LIB_OMP))
+    return _lib_omp
 
 
 def _p(a):
@@ -141,10 +167,12 @@ def _csr(offsets, indices):
     return o, i
 
 
-def run(offsets, indices, b: int, seed: int, max_passes: int = 0):
+def run(offsets, indices, b: int, seed: int, max_passes: int = 0, lastmod: bool = False):
     """Algorithm 2 to stabilisation (or max_passes passes).
 
-    Returns dict(regs (n, p) uint8, S, H float64, nmod int64 per pass, passes).
+    Returns dict(regs (n, p) uint8, S, H float64, nmod int64 per pass, passes),
+    and with lastmod=True also lastmod (n int32: 1 + the last pass that
+    changed the node's counter, 0 if none did).
     """
     o, i = _csr(offsets, indices)
     n = o.shape[0] - 1
@@ -152,15 +180,54 @@ def run(offsets, indices, b: int, seed: int, max_passes: int = 0):
     regs = np.zeros((max(n, 1), p), dtype=np.uint8)
     S = np.zeros(max(n, 1))
     H = np.zeros(max(n, 1))
+    lm = np.zeros(max(n, 1), dtype=np.int32) if lastmod else None
     cap = max_passes if max_passes > 0 else n + 2
     nmod = np.zeros(cap + 1, dtype=np.int64)
     passes = ctypes.c_int(0)
-    rc = _load().hbo_run(n, _p(o), _p(i), b, seed, max_passes, _p(regs), _p(S), _p(H), _p(nmod),
-                         ctypes.byref(passes))
+    rc = _load().hbo_run_full(n, _p(o), _p(i), b, seed, max_passes, None, None, 0, _p(regs), _p(S), _p(H),
+                              None, None, 0, _p(nmod), _p(lm), ctypes.byref(passes))
     if rc != 0:
         raise RuntimeError("oracle run failed")
     t = passes.value
-    return dict(regs=regs[:n], S=S[:n], H=H[:n], nmod=nmod[:t].copy(), passes=t)
+    out = dict(regs=regs[:n], S=S[:n], H=H[:n], nmod=nmod[:t].copy(), passes=t)
+    if lastmod:
+        out["lastmod"] = lm[:n]
+    return out
+
+
+def threads(all_cores: bool = False) -> int:
+    """Threads a pass uses: 1 for the oracle proper; with all_cores, those of
+    the OpenMP build of the same source (OMP_NUM_THREADS, else every core)."""
+    return (_load_omp() if all_cores else _load()).hbo_threads()
+
+
+def first_pass_rows(offsets, indices, b: int, seed: int, v_begin: int, v_end: int, all_cores: bool = False):
+    """Pass 0 of ``run`` over the rows [v_begin, v_end) only, timed: the
+    counters of every node are set to radius 0 first (not timed), then the
+    pass's node loop runs over the range (the same function ``run`` calls,
+    from the plain or, with all_cores, the OpenMP build).  Used for the CPU
+    baseline on a bounded sample of a large graph.
+
+    Returns dict(seconds, changed, next (rows of the range, radius-1
+    counters), S, H over the range, threads)."""
+    import time
+
+    L = _load_omp() if all_cores else _load()
+    o, i = _csr(offsets, indices)
+    n = o.shape[0] - 1
+    p = 1 << b
+    if not (0 <= v_begin <= v_end <= n):
+        raise ValueError("row range outside the graph")
+    c = np.empty(max(n, 1) * p, dtype=np.uint8)
+    L.hbo_init_counters(n, b, seed, None, _p(c))
+    nxt = np.zeros(max(n, 1) * p, dtype=np.uint8)
+    S = np.zeros(max(n, 1))
+    H = np.zeros(max(n, 1))
+    t0 = time.perf_counter()
+    changed = L.hbo_pass(_p(o), _p(i), b, 0, _p(c), _p(nxt), _p(S), _p(H), 0.0, None, None, v_begin, v_end)
+    dt = time.perf_counter() - t0
+    return dict(seconds=dt, changed=int(changed), next=nxt[v_begin * p:v_end * p].reshape(-1, p).copy(),
+                S=S[v_begin:v_end].copy(), H=H[v_begin:v_end].copy(), threads=L.hbo_threads())
 
 
 def replica_item(x: int, j: int) -> int:

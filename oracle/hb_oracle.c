@@ -39,6 +39,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef unsigned __int128 u128;
 
@@ -62,7 +65,9 @@ int hbo_rho(uint64_t h, int b) {
   return zeros + 1;
 }
 
-/* Algorithm 1, function add: i <- h_b(x); M[i] <- max(M[i], rho+(h^b(x))). */
+/* Adding an item to a counter (Algorithm 1): the leftmost b bits of its hash
+ * select a register, which keeps the larger of its value and rho+ of the
+ * other 64-b bits. */
 void hbo_add(uint8_t* M, int b, uint64_t item, uint64_t seed) {
   uint64_t h = hbo_hash(item, seed);
   uint64_t i = h >> (64 - b);
@@ -102,42 +107,98 @@ double hbo_size(const uint8_t* M, int b) {
   return E;
 }
 
-/* Register-wise maximum (Algorithm 2, function union): M <- max(M, N). */
+/* Register-wise maximum: the counter of a union of sets (Sec. 4.2). */
 static void hbo_union(uint8_t* M, const uint8_t* N, int p) {
   for (int i = 0; i < p; ++i)
     if (N[i] > M[i]) M[i] = N[i];
 }
 
-/*
- * Algorithm 2 on the CSR (offsets: n+1 int64, indices: m int32; row v lists
- * the arcs v->w).  Runs passes until one leaves every counter unchanged, or
- * until max_passes passes have run (max_passes <= 0: no cap).
- *
- * Outputs (each may be NULL): regs (n*p bytes, node-major) holds the counters
- * after the last pass, S and H the two accumulators, nmod[t] the number of
- * counters changed by pass t (room for the cap, or for n+2 entries when
- * uncapped).  *passes receives the number of passes run, the last unchanged
- * one included.  Returns 0, or -1 on bad arguments / allocation failure.
- */
 /* Item of replica j of node x (Sec. 6 simulates an integer weight w(x) by
  * w(x) distinct replicas): x itself for j = 0, x + j * 2^32 for j > 0, which
  * no node id (< 2^31) and no other replica can equal. */
 static uint64_t replica_item(int64_t x, int64_t j) { return (uint64_t)x + ((uint64_t)j << 32); }
 
-/* Algorithm 2 to stabilisation (or max_passes passes), with the Sec. 5
- * accumulators and, optionally:
- *   weights  (nullable) w(x) >= 1: counter x starts as the HyperLogLog of the
- *            w(x) replicas of x (Sec. 6), so the sizes and accumulators
- *            count weighted nodes;
- *   disc     (nullable) a discount table f(1..disc_len): D[v] accumulates
- *            f(t+1) * delta in pass t (Sec. 7), f(d) = f(disc_len) beyond
- *            the table;
+/* Number of threads a pass may use: 1 in the plain build; the OpenMP build of
+ * this same file (used only to time the all-core CPU baseline) runs the node
+ * loop of hbo_pass over all its threads.  Nodes of one pass are independent
+ * (each reads only the old counters and writes only its own entries), so both
+ * builds give the same results. */
+int hbo_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* Counters of radius 0 (Sec. 4.2: B(x, 0) = {x}): c (n*p bytes, node-major)
+ * receives, for every node x, the HyperLogLog counter of x alone, or of its
+ * w(x) replicas when weights are given (Sec. 6). */
+void hbo_init_counters(int64_t n, int b, uint64_t seed, const int32_t* weights, uint8_t* c) {
+  int p = 1 << b;
+  memset(c, 0, (size_t)n * (size_t)p);
+  for (int64_t v = 0; v < n; ++v) {
+    const int64_t w = weights ? weights[v] : 1;
+    for (int64_t j = 0; j < w; ++j) hbo_add(c + (size_t)v * p, b, replica_item(v, j), seed);
+  }
+}
+
+/*
+ * Pass t of the computation (Sec. 4.2 and Algorithm 2), restricted to the
+ * nodes in [v_begin, v_end): the counter of radius t+1 of v is the union of
+ * v's own counter of radius t with those of its successors, because
+ * B(v, t+1) = B(v, t) u U_{v->w} B(w, t).  Old counters are read from c, new
+ * ones written to next (never the same array: the update is synchronous).
+ * With delta = |B(v,t+1)| - |B(v,t)| as estimated by the two counters, the
+ * Sec. 5 accumulators receive S[v] += (t+1)*delta and H[v] += delta/(t+1),
+ * and, with a discount (Sec. 7), D[v] += f*delta.  lastmod (nullable)
+ * receives t+1 for every node whose registers changed.  Returns the number
+ * of such nodes.
+ */
+int64_t hbo_pass(const int64_t* offsets, const int32_t* indices, int b, int t, const uint8_t* c, uint8_t* next,
+                 double* S, double* H, double f, double* D, int32_t* lastmod, int64_t v_begin, int64_t v_end) {
+  const int p = 1 << b;
+  const double d = (double)(t + 1);
+  int64_t changed = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : changed)
+#endif
+  for (int64_t v = v_begin; v < v_end; ++v) {
+    const uint8_t* old = c + (size_t)v * p;
+    uint8_t* a = next + (size_t)v * p;
+    memcpy(a, old, (size_t)p);
+    for (int64_t e = offsets[v]; e < offsets[v + 1]; ++e) hbo_union(a, c + (size_t)indices[e] * p, p);
+    double delta = hbo_size(a, b) - hbo_size(old, b);
+    S[v] = S[v] + d * delta;
+    H[v] = H[v] + delta / d;
+    if (D) D[v] = D[v] + f * delta;
+    if (memcmp(a, old, (size_t)p) != 0) {
+      ++changed;
+      if (lastmod) lastmod[v] = t + 1;
+    }
+  }
+  return changed;
+}
+
+/* The whole computation (Algorithm 2 with the Sec. 5 accumulators): passes
+ * t = 0, 1, ... until one leaves every counter unchanged (that pass is
+ * counted) or max_passes passes have run (max_passes <= 0: no cap).
+ *   weights  (nullable) w(x) >= 1: counters start as the HyperLogLog of the
+ *            replicas (Sec. 6), so sizes and accumulators count weighted nodes;
+ *   disc     (nullable) a discount table f(1..disc_len): pass t adds
+ *            f(t+1) * delta to D[v] (Sec. 7), f(d) = f(disc_len) beyond it;
  *   etrace   (nullable) (trace_rows * n) doubles: row t receives the size
  *            estimate of every counter after t passes (row 0: before pass 0),
- *            for the rows the run reaches. */
-int hbo_run_ext(int64_t n, const int64_t* offsets, const int32_t* indices, int b, uint64_t seed, int max_passes,
-                const int32_t* weights, const double* disc, int disc_len, uint8_t* regs, double* S, double* H,
-                double* D, double* etrace, int64_t trace_rows, int64_t* nmod, int* passes) {
+ *            for the rows the run reaches;
+ *   lastmod  (nullable) n int32: the largest t+1 such that pass t changed the
+ *            node's counter, 0 if no pass did.
+ * Outputs regs (n*p bytes, node-major: the final counters), S, H, D, and
+ * nmod[t] (counters changed by pass t; room for the cap, or n+2 entries when
+ * uncapped) may each be NULL.  *passes receives the number of passes run.
+ * Returns 0, or -1 on bad arguments / allocation failure. */
+int hbo_run_full(int64_t n, const int64_t* offsets, const int32_t* indices, int b, uint64_t seed, int max_passes,
+                 const int32_t* weights, const double* disc, int disc_len, uint8_t* regs, double* S, double* H,
+                 double* D, double* etrace, int64_t trace_rows, int64_t* nmod, int32_t* lastmod, int* passes) {
   if (n < 0 || b < 4 || b > 16) return -1;
   if (disc && disc_len < 1) return -1;
   int p = 1 << b;
@@ -152,35 +213,16 @@ int hbo_run_ext(int64_t n, const int64_t* offsets, const int32_t* indices, int b
     free(c); free(next); free(s); free(h); free(dsum);
     return -1;
   }
-  /* Algorithm 2: every counter starts empty and is fed its own node (or the
-   * node's replicas). */
-  for (int64_t v = 0; v < n; ++v) {
-    const int64_t w = weights ? weights[v] : 1;
-    for (int64_t j = 0; j < w; ++j) hbo_add(c + (size_t)v * p, b, replica_item(v, j), seed);
-  }
+  hbo_init_counters(n, b, seed, weights, c);
+  if (lastmod && n > 0) memset(lastmod, 0, (size_t)n * sizeof(int32_t));
   if (etrace && trace_rows > 0)
     for (int64_t v = 0; v < n; ++v) etrace[v] = hbo_size(c + (size_t)v * p, b);
   int t = 0;
   int64_t changed;
   do {
-    changed = 0;
     const double f = disc ? disc[t + 1 <= disc_len ? t : disc_len - 1] : 0.0;
-    for (int64_t v = 0; v < n; ++v) {
-      uint8_t* a = next + (size_t)v * p;
-      const uint8_t* cv = c + (size_t)v * p;
-      memcpy(a, cv, (size_t)p);                               /* a <- c[v] */
-      for (int64_t e = offsets[v]; e < offsets[v + 1]; ++e)   /* foreach v->w */
-        hbo_union(a, c + (size_t)indices[e] * p, p);          /* a <- union(c[w], a) */
-      /* "do something with a and c[v]": a estimates |B(v,t+1)|, c[v] |B(v,t)|. */
-      double delta = hbo_size(a, b) - hbo_size(cv, b);
-      double d = (double)(t + 1);
-      s[v] = s[v] + d * delta;
-      h[v] = h[v] + delta / d;
-      if (disc) dsum[v] = dsum[v] + f * delta;
-      if (memcmp(a, cv, (size_t)p) != 0) ++changed;
-    }
-    /* Apply all pairs <v,a> at once (synchronous update). */
-    uint8_t* tmp = c; c = next; next = tmp;
+    changed = hbo_pass(offsets, indices, b, t, c, next, s, h, f, disc ? dsum : NULL, lastmod, 0, n);
+    uint8_t* tmp = c; c = next; next = tmp; /* the new counters become the current ones */
     if (nmod) nmod[t] = changed;
     ++t;
     if (etrace && t < trace_rows)
@@ -193,6 +235,13 @@ int hbo_run_ext(int64_t n, const int64_t* offsets, const int32_t* indices, int b
   if (passes) *passes = t;
   free(c); free(next); free(s); free(h); free(dsum);
   return 0;
+}
+
+int hbo_run_ext(int64_t n, const int64_t* offsets, const int32_t* indices, int b, uint64_t seed, int max_passes,
+                const int32_t* weights, const double* disc, int disc_len, uint8_t* regs, double* S, double* H,
+                double* D, double* etrace, int64_t trace_rows, int64_t* nmod, int* passes) {
+  return hbo_run_full(n, offsets, indices, b, seed, max_passes, weights, disc, disc_len, regs, S, H, D, etrace,
+                      trace_rows, nmod, NULL, passes);
 }
 
 int hbo_run(int64_t n, const int64_t* offsets, const int32_t* indices, int b, uint64_t seed,
@@ -225,13 +274,10 @@ void hbo_finalize(int64_t n, const uint8_t* regs, int b, const double* S, const 
  * those of the whole reachable set.  S, H: accumulators of x after the run.
  * last_change: the largest t+1 such that pass t changed x's counter (0 if no
  * pass does).  ecc: the eccentricity of x (largest finite distance).
+ * With weights, the balls hold the replicas of their nodes; weights and disc
+ * are as in hbo_run_full (nullable), and D receives the discounted sum.
  * Returns 0, or -1 on bad arguments / allocation failure.
  */
-/* One node from breadth-first balls: the counter of x after t passes is the
- * HyperLogLog state of B(x, t) (of the replicas of its nodes when weights
- * are given), so S, H and D follow from the ball sizes layer by layer.
- * weights / disc as in hbo_run_ext (nullable).  regs_at receives the
- * registers at `radius` (< 0: at convergence). */
 int hbo_node_ext(int64_t n, const int64_t* offsets, const int32_t* indices, int b, uint64_t seed, int64_t x,
                  int radius, const int32_t* weights, const double* disc, int disc_len, uint8_t* regs_at, double* S,
                  double* H, double* D, int* last_change, int* ecc) {
