@@ -11,11 +11,15 @@ One step = one whole HyperBall computation on that graph: reset (counters of
 radius 0), passes until a pass changes no counter, and the centralities
 written to device memory.  The graph is resident in HBM before timing starts.
 
-Printed (one JSON line): edge visits per second per iteration (arcs scanned
-per pass, summed over the passes of a step, divided by the step time), the
-roofline of the dominant kernel (the expand kernel: algorithmic bytes per
-launch / mean launch time from HIP events, against 8 TB/s), and the CPU
-oracle timed on one pass of the same graph.
+Printed (one JSON line): `value` = edge visits per second, counting the arcs
+each pass actually scans (a pass of the frontier skips rows none of whose
+successors changed), summed over the passes of a step and divided by the step
+time; beside it `nominal_edge_visits_per_s` = m x passes / step time, the
+paper's time-per-arc convention (every arc counted in every pass).  Also the
+roofline of the dominant kernel (algorithmic bytes per launch / mean launch
+time from HIP events, against 8 TB/s; measured HBM traffic from committed
+rocprofv3 counters, raw and scaled), and the CPU oracle timed on a sample of
+the same graph (one core, and all cores).
 """
 from __future__ import annotations
 
@@ -74,9 +78,11 @@ def kernel_hash():
 
 
 def read_traffic(kname, workload):
-    """HBM bytes per launch of `kname` from the committed rocprofv3 counter
-    summary (FETCH_SIZE x fetch scale + WRITE_SIZE x write scale), or None if
-    there is none for this kernel and workload or the kernel has changed."""
+    """HBM traffic per launch of `kname` from the committed rocprofv3 counter
+    summary: the raw FETCH_SIZE and WRITE_SIZE (KiB per dispatch), the scale
+    factors a plain device copy of known size gives them, and the scaled
+    total in bytes; None if there is no summary for this kernel and workload
+    or the kernel sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
     if not os.path.exists(path):
         return None
@@ -87,7 +93,9 @@ def read_traffic(kname, workload):
             rec[k.strip()] = v.strip()
     if rec.get("kernel_hash") != kernel_hash() or rec.get("kernel") != kname:
         return None
-    return int(rec["hbm_bytes_per_launch"])
+    return {"bytes": int(rec["hbm_bytes_per_launch"]), "fetch_kib": float(rec["fetch_kib_per_launch"]),
+            "write_kib": float(rec["write_kib_per_launch"]), "fetch_scale": float(rec["fetch_scale"]),
+            "write_scale": float(rec["write_scale"])}
 
 
 def kernel_of(ps, b):
@@ -126,25 +134,74 @@ def pass_bytes(ps, listed, p):
             + p * ps["rows_written"] + 26 * ps["rows_changed"])
 
 
-def cpu_baseline(w, seed):
-    """The oracle on a bounded sample of the workload: pass 0 (every arc
-    gathered) of the same generator at scale-2 (a quarter of the nodes and
-    arcs), single-threaded.  Edge visits per second are comparable because a
-    pass costs the same per arc; the full scale-24 pass takes ~100 s."""
-    import graphgen
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(off, idx, w, seed, target_s: float = 20.0):
+    """The oracle on a bounded sample of the benchmark graph itself: pass 0
+    (every arc of a row gathered) over a contiguous range of rows, timed in a
+    child process pinned to one core, then the OpenMP build of the same pass
+    loop over the same rows on every core the process may use, checked equal
+    to the single-core result.  Rows are in a random order (the graph is
+    relabelled), so a range of rows is a uniform sample of them; the range is
+    sized from a short calibration run to about target_s seconds on one
+    core."""
+    import subprocess
+    import tempfile
+
+    d = "/dev/shm" if os.path.isdir("/dev/shm") else None
+    with tempfile.TemporaryDirectory(dir=d) as tmp:
+        np.save(os.path.join(tmp, "off.npy"), np.asarray(off, dtype=np.int64))
+        np.save(os.path.join(tmp, "idx.npy"), np.asarray(idx, dtype=np.int32))
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", tmp,
+                            "--child-log2m", str(w["log2m"]), "--child-seed", str(seed),
+                            "--child-target-s", str(target_s)],
+                           stdout=subprocess.PIPE, check=True, text=True)
+    res = json.loads(r.stdout.strip().splitlines()[-1])
+    res["sample"] = (f"pass 0 of the {w.get('name', 'benchmark')} graph itself (log2m={w['log2m']}, hash seed {seed}) "
+                     f"over rows [0, {res.pop('rows')}) of {res.pop('n')} ({res['arcs']} of {res.pop('m')} arcs), "
+                     "C oracle built with gcc -O3 (no contraction, no fast-math); counters of every node set "
+                     "to radius 0 first (not timed)")
+    return res
+
+
+def cpu_baseline_child(args):
+    """Child process of cpu_baseline (no GPU use)."""
     import oracle
 
-    scale = max(w["scale"] - 2, 8)
-    sw = dict(w, scale=scale)
-    off, idx = make_graph(sw)
-    t = time.time()
-    r = oracle.run(off, idx, w["log2m"], seed, max_passes=1)
-    dt = time.time() - t
-    m = len(idx)
-    return {"value": m / dt, "unit": "edge visits/s", "cores": 1, "kind": "oracle",
-            "sample": f"pass 0 of R-MAT scale {scale} (same generator and options, n={len(off) - 1}, "
-                      f"m={m}, log2m={w['log2m']}), single-threaded C oracle: {dt:.1f}s",
-            "seconds": round(dt, 2)}
+    off = np.load(os.path.join(args.cpu_baseline_child, "off.npy"))
+    idx = np.load(os.path.join(args.cpu_baseline_child, "idx.npy"))
+    n, m = len(off) - 1, len(idx)
+    b, seed = args.child_log2m, args.child_seed
+    allowed = sorted(os.sched_getaffinity(0))
+    os.sched_setaffinity(0, {allowed[0]})
+    cal_rows = max(1, n // 512)
+    cal = oracle.first_pass_rows(off, idx, b, seed, 0, cal_rows)
+    rate = max(int(off[cal_rows]), 1) / max(cal["seconds"], 1e-6)
+    want_arcs = rate * args.child_target_s
+    rows = int(np.searchsorted(off, min(want_arcs, m), side="left"))
+    rows = min(max(rows, cal_rows), n)
+    one = oracle.first_pass_rows(off, idx, b, seed, 0, rows)
+    arcs = int(off[rows])
+    os.sched_setaffinity(0, set(allowed))
+    allc = oracle.first_pass_rows(off, idx, b, seed, 0, rows, all_cores=True)
+    same = (one["changed"] == allc["changed"] and np.array_equal(one["next"], allc["next"])
+            and np.array_equal(one["S"], allc["S"]) and np.array_equal(one["H"], allc["H"]))
+    print(json.dumps({
+        "value": arcs / one["seconds"], "unit": "edge visits/s", "cores": 1, "kind": "oracle",
+        "seconds": round(one["seconds"], 2), "arcs": arcs, "rows": rows, "n": n, "m": m,
+        "pinned_cpu": allowed[0], "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+        "usable_cpus": len(allowed),
+        "all_cores": {"value": arcs / allc["seconds"], "unit": "edge visits/s", "cores": allc["threads"],
+                      "seconds": round(allc["seconds"], 2), "identical_to_single_core": bool(same)}}),
+        flush=True)
 
 
 def bench_batch(args, torch, hb, plain_sample: int = 512):
@@ -428,8 +485,10 @@ def bench_serve(args, torch, hb, n_requests: int = 2000, rate: float = 500.0, po
     which = rng.integers(0, pool_size, size=n_requests)
     classes = rng.choice([4, 6, 8], size=n_requests)
     hseeds = rng.integers(0, 1 << 40, size=n_requests)
-    arena = PinnedArena(torch, 2 << 30)
-    check_ids = set(rng.choice(n_requests, size=24, replace=False).tolist())
+    arena = PinnedArena(torch, 4 << 30)
+    # requests whose registers and finalized outputs are compared bit for bit
+    # with a solo run (the pass counts of all of them are compared)
+    check_ids = set(rng.choice(n_requests, size=min(200, n_requests), replace=False).tolist())
 
     def run_stream(times, tag):
         srv = hb.Server(validate=0)
@@ -454,7 +513,7 @@ def bench_serve(args, torch, hb, n_requests: int = 2000, rate: float = 500.0, po
                     return
                 i, req, alloc = item
                 infos[i] = srv.wait(req)
-                if tag == "poisson" and i in check_ids:
+                if i in check_ids:
                     kept[i] = {k: v.copy() for k, v in req.outputs.items()}
                 with lock:
                     arena.release(*alloc)
@@ -465,15 +524,18 @@ def bench_serve(args, torch, hb, n_requests: int = 2000, rate: float = 500.0, po
         for i in range(n_requests):
             g = pool[which[i]]
             n = g["n"]
+            rbytes = n << int(classes[i]) if i in check_ids else 0
             while True:
                 with lock:
-                    a = arena.alloc(24 * n)
+                    a = arena.alloc(24 * n + rbytes)
                 if a is not None:
                     break
                 time.sleep(0.0005)
             base = a[0]
             outs = {k: arena.np[base + 8 * n * j: base + 8 * n * (j + 1)].view(np.float64)
                     for j, k in enumerate(SERVE_OUTS)}
+            if rbytes:
+                outs["registers"] = arena.np[base + 24 * n: base + 24 * n + rbytes].reshape(n, -1)
             if times is not None:
                 dt = times[i] - (time.perf_counter() - t0)
                 if dt > 0.002:
@@ -506,31 +568,55 @@ def bench_serve(args, torch, hb, n_requests: int = 2000, rate: float = 500.0, po
         return res, infos, kept
 
     poisson, infos, kept = run_stream(arrivals, "poisson")
-    burst, _, _ = run_stream(None, "burst")
+    burst, binfos, bkept = run_stream(None, "burst")
     # Plain: the same requests one after another through hb_init / hb_run /
     # hb_centralities / hb_free (host CSR, outputs to host), on a sample.
-    sample = sorted(set(range(0, n_requests, max(1, n_requests // 100))) | check_ids)
-    mism = 0
+    sample = sorted(set(range(0, n_requests, max(1, n_requests // 100))))
     plain_t = 0.0
     for i in sample:
         g = pool[which[i]]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         with hb.HyperBall(g["off"], g["idx"], int(classes[i]), int(hseeds[i]), validate=0) as ctx:
-            passes = ctx.run()
-            cen = ctx.centralities()
+            ctx.run()
+            ctx.centralities()
         plain_t += time.perf_counter() - t0
-        if i in kept:
-            same = passes == infos[i]["passes"] and all(np.array_equal(cen[k], kept[i][k]) for k in SERVE_OUTS)
-            mism += int(not same)
     plain_gps = len(sample) / plain_t
+    # Every request solo (one plain context per pool graph and log2m, reset
+    # to the request's seed): its pass count against both served streams,
+    # and for the checked requests registers and outputs bit for bit.
+    mism = {"passes": 0, "registers": 0, "outputs": 0}
+    t0 = time.perf_counter()
+    order = sorted(range(n_requests), key=lambda i: (which[i], classes[i]))
+    ctx, key = None, None
+    for i in order:
+        g = pool[which[i]]
+        if key != (which[i], classes[i]):
+            if ctx is not None:
+                ctx.close()
+            key = (which[i], classes[i])
+            ctx = hb.HyperBall(g["off"], g["idx"], int(classes[i]), int(hseeds[i]), validate=0)
+        ctx.reset(int(hseeds[i]))
+        passes = ctx.run()
+        mism["passes"] += int(passes != infos[i]["passes"]) + int(passes != binfos[i]["passes"])
+        if i in check_ids:
+            regs = ctx.registers()
+            cen = ctx.centralities()
+            for kk in (kept[i], bkept[i]):
+                mism["registers"] += int(not np.array_equal(regs, kk["registers"]))
+                mism["outputs"] += int(not all(np.array_equal(cen[k], kk[k]) for k in SERVE_OUTS))
+    if ctx is not None:
+        ctx.close()
+    solo_s = time.perf_counter() - t0
     return {"workload": f"Poisson arrivals {rate:g}/s (seed 5), {n_requests} requests over a pool of "
                         f"{pool_size} directed R-MAT graphs (scale U{{10..20}}, edge factor U{{4..32}}, "
                         "transposed, int32 CSR, pinned host memory), log2m U{4,6,8}, budget 64 GiB",
             "poisson": poisson, "burst": burst,
             "plain_graphs_per_s": plain_gps, "plain_sample": len(sample),
             "burst_speedup_vs_plain": burst["graphs_per_s"] / plain_gps,
-            "identical_on_sample": mism == 0, "checked": len(kept), "mismatches": mism}
+            "checked_pass_counts": 2 * n_requests, "checked_registers_and_outputs": 2 * len(check_ids),
+            "solo_check_s": round(solo_s, 1), "mismatches": mism,
+            "identical": not any(mism.values())}
 
 
 def main():
@@ -560,7 +646,14 @@ def main():
     ap.add_argument("--serve-only", action="store_true", help="only the serving measurement (its own line)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (torch) 3 times, to scale HBM counters")
+    ap.add_argument("--cpu-baseline-child", default="", help=argparse.SUPPRESS)
+    ap.add_argument("--child-log2m", type=int, default=7, help=argparse.SUPPRESS)
+    ap.add_argument("--child-seed", type=int, default=42, help=argparse.SUPPRESS)
+    ap.add_argument("--child-target-s", type=float, default=20.0, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_baseline_child:
+        cpu_baseline_child(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU per run: sharding a graph over several GPUs is not implemented, so --gpus must be 1"}))
         sys.exit(2)
@@ -610,12 +703,14 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     step_passes = []
+    scanned = 0
     per_kernel = {}  # kernel name -> [ms, algorithmic bytes, launches]
     first = None
     for k in range(args.steps):
         passes = step()
         step_passes.append(passes)
         infos = [g.pass_stats(t) for t in range(passes)]
+        scanned += sum(ps["arcs_scanned"] for ps in infos)
         for ps in infos:
             kname = kernel_of(ps, w["log2m"])
             acc = per_kernel.setdefault(kname, [0.0, 0, 0])
@@ -628,8 +723,8 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = 1e3 * dt / args.steps
-    visits = m * sum(step_passes)  # every arc of every pass, as the paper counts time per arc
-    value = visits / dt
+    scanned_per_s = scanned / dt
+    nominal = m * sum(step_passes)  # every arc of every pass, as the paper counts time per arc
 
     for t, ps in enumerate(first):
         log(f"  pass {t:2d} mode {ps['mode']}: arcs={ps['arcs_scanned']:>10d} "
@@ -644,9 +739,11 @@ def main():
     kname, (k_ms, k_bytes, launches) = max(per_kernel.items(), key=lambda kv: kv[1][0])
     mean_ms = k_ms / launches
     achieved = k_bytes / launches / (mean_ms * 1e-3) / 1e9
-    traffic = read_traffic(kname, args.workload)
+    tr = read_traffic(kname, args.workload)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None if tr is None else tr["bytes"],
+            "traffic_counters": None if tr is None else {k: tr[k] for k in ("fetch_kib", "write_kib",
+                                                                            "fetch_scale", "write_scale")},
             "kernel": kname, "launches": launches, "mean_launch_ms": round(mean_ms, 4),
             "algorithmic_bytes_per_launch": k_bytes // launches}
     others = {kn: {"launches": v[2], "mean_launch_ms": round(v[0] / v[2], 4),
@@ -654,7 +751,7 @@ def main():
               for kn, v in per_kernel.items() if kn != kname}
     p0 = first[0]
     out = {
-        "metric": METRIC, "value": value, "unit": "edge visits/s", "n_gpus": 1,
+        "metric": METRIC, "value": scanned_per_s, "unit": "edge visits/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
         "data": "synthetic",
@@ -665,7 +762,8 @@ def main():
         "first_pass": {"ms": p0["expand_ms"] + p0["merge_ms"],
                        "edge_visits_per_s": m / ((p0["expand_ms"] + p0["merge_ms"]) * 1e-3),
                        "GBps": pass_bytes(p0, listed, p) / (p0["expand_ms"] * 1e6)},
-        "arcs_scanned_per_s": sum(ps["arcs_scanned"] for ps in first) * len(step_passes) / dt,
+        "nominal_edge_visits_per_s": nominal / dt,
+        "arcs_scanned_per_step": scanned // args.steps,
         "roofline": roof,
         "other_kernels": others,
     }
@@ -701,9 +799,9 @@ def main():
                              "GBps_rw": 2 * (1 << 30) / cdt / 1e9}
         del src, dst
     if not args.no_cpu_baseline:
-        log("cpu baseline: oracle pass 0 ...")
-        del off, idx
-        out["cpu_baseline"] = cpu_baseline(w, seed)
+        log("cpu baseline: oracle pass 0 on a sample of rows ...")
+        out["cpu_baseline"] = cpu_baseline(off, idx, dict(w, name=args.workload), seed)
+        log(f"cpu baseline: {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
 
 

@@ -417,6 +417,16 @@ hb_status hb_set_weights(hb_ctx* c, const int32_t* weights, int32_t on_device);
  * Needs 2^log2m <= 256 and a single-graph, single-seed context.  The
  * computation restarts from pass 0. */
 hb_status hb_set_discount(hb_ctx* c, const double* f, int32_t len);
+/* The discount functions Sec. 7 names, f(1..len) into f (host, len >= 1),
+ * logarithms in base 2 as everywhere in the paper:
+ *   HB_DISCOUNT_HARMONIC     f(d) = 1/d (gives harmonic centrality),
+ *   HB_DISCOUNT_QUADRATIC    f(d) = 1/d^2,
+ *   HB_DISCOUNT_LOGARITHMIC  f(d) = 1/log2(d+1),
+ *   HB_DISCOUNT_CONSTANT     f(d) = 1 (gives the coreachable-set size minus one).
+ * HB_EINVAL for an unknown kind, a NULL output or len < 1.  Host arithmetic
+ * only (no context, no device); pass the table to hb_set_discount. */
+enum { HB_DISCOUNT_HARMONIC = 0, HB_DISCOUNT_QUADRATIC = 1, HB_DISCOUNT_LOGARITHMIC = 2, HB_DISCOUNT_CONSTANT = 3 };
+hb_status hb_discount_table(int32_t kind, int32_t len, double* f);
 /* The discounted sums (n doubles). */
 hb_status hb_get_discounted(hb_ctx* c, double* D, int32_t dst_on_device);
 

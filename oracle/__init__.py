@@ -27,6 +27,8 @@ Parity status of every function (pins live in ``tests/test_oracle_*.py``):
 * ``neighbourhood``          - N(t) = correctly rounded sum over nodes of the
   estimates after t passes (``math.fsum`` of the trace); pinned: exact-regime
   ball sizes from breadth-first search.
+* ``discount_table``         - the Sec. 7 discounts; pinned: exact values
+  (1/d, 1/d^2, log2(d+1) at d = 2^k - 1, constant 1).
 * ``distance_stats``         - average distance and interpolated effective
   diameter from N(t); pinned: closed forms on paths and cycles.
 * ``ensemble``               - K independent runs (Sec. 5: several runs of
@@ -38,7 +40,6 @@ from __future__ import annotations
 
 import ctypes
 import os
-import subprocess
 
 import numpy as np
 
@@ -48,7 +49,6 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
-_FLAGS = ["-O3", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
 _LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 _lib_omp = None
 
@@ -56,12 +56,9 @@ _lib_omp = None
 def build(force: bool = True) -> str:
     """Compile the oracle (gcc -O3, no FMA contraction, no fast-math), and the
     OpenMP build of the same file that only the all-core CPU baseline uses."""
-    for out, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
-        if force or not os.path.exists(out):
-            tmp = out + ".tmp"
-            subprocess.check_call(["gcc"] + _FLAGS + extra + [_SRC, "-o", tmp, "-lm"])
-            os.replace(tmp, out)
-    return _LIB
+    from oracle.build import build as _build
+
+    return _build(force)
 
 
 def _declare(L):
@@ -94,6 +91,8 @@ def _declare(L):
     L.hbo_init_counters.restype = None
     L.hbo_pass.argtypes = [vp, vp, ci, ci, vp, vp, vp, vp, ctypes.c_double, vp, vp, i64, i64]
     L.hbo_pass.restype = i64
+    L.hbo_discount.argtypes = [ci, ci]
+    L.hbo_discount.restype = ctypes.c_double
     L.hbo_threads.argtypes = []
     L.hbo_threads.restype = ci
     return L
@@ -275,6 +274,16 @@ def run_ext(offsets, indices, b: int, seed: int, max_passes: int = 0, weights=No
     if trace:
         out["etrace"] = et[: t + 1, :n].copy()
     return out
+
+
+DISCOUNTS = {"harmonic": 0, "quadratic": 1, "logarithmic": 2, "constant": 3}
+
+
+def discount_table(kind: str, length: int = 64) -> np.ndarray:
+    """f(1..length) of the discounts Sec. 7 names: harmonic 1/d, quadratic
+    1/d^2, logarithmic 1/log2(d+1), constant 1."""
+    L = _load()
+    return np.array([L.hbo_discount(DISCOUNTS[kind], d) for d in range(1, length + 1)], dtype=np.float64)
 
 
 def neighbourhood(etrace) -> np.ndarray:

@@ -250,6 +250,20 @@ int hbo_run(int64_t n, const int64_t* offsets, const int32_t* indices, int b, ui
                      passes);
 }
 
+/* The discount functions of Sec. 7 at distance d >= 1 (logarithms in base 2,
+ * the paper's convention): kind 0 harmonic 1/d, 1 quadratic 1/d^2,
+ * 2 logarithmic 1/log2(d+1), 3 constant 1.  NaN for an unknown kind. */
+double hbo_discount(int kind, int d) {
+  const double x = (double)d;
+  switch (kind) {
+    case 0: return 1.0 / x;
+    case 1: return 1.0 / (x * x);
+    case 2: return 1.0 / log2(x + 1.0);
+    case 3: return 1.0;
+    default: return NAN;
+  }
+}
+
 void hbo_finalize(int64_t n, const uint8_t* regs, int b, const double* S, const double* H,
                   double* closeness, double* lin, double* harmonic, double* coreach) {
   int p = 1 << b;

@@ -141,6 +141,7 @@ def _declare(L):
         "hb_get_discounted": (ctypes.c_int, [vp, vp, i32]),
         "hb_neighbourhood": (ctypes.c_int, [vp, vp, i32, P(i32)]),
         "hb_distance_stats": (ctypes.c_int, [vp, i32, ctypes.c_double, P(hb_distance_stats_t)]),
+        "hb_discount_table": (ctypes.c_int, [i32, i32, vp]),
         "hb_ensemble_init": (ctypes.c_int, [P(vp), P(hb_csr), i32, vp, i32, P(hb_options), vp]),
         "hb_ensemble_reset": (ctypes.c_int, [vp, vp]),
         "hb_ensemble_passes": (ctypes.c_int, [vp, vp]),
@@ -290,19 +291,17 @@ def hb_distance_stats(N, alpha: float = 0.9) -> dict:
     return {k: getattr(st, k) for k, _ in hb_distance_stats_t._fields_}
 
 
+DISCOUNTS = {"harmonic": 0, "quadratic": 1, "logarithmic": 2, "constant": 3}
+
+
 def discount_table(kind: str, length: int = 64) -> np.ndarray:
-    """f(1..length) for the discounts Sec. 7 names: "harmonic" 1/d,
-    "quadratic" 1/d^2, "logarithmic" 1/log2(d+1), "constant" 1."""
-    d = np.arange(1, length + 1, dtype=np.float64)
-    if kind == "harmonic":
-        return 1.0 / d
-    if kind == "quadratic":
-        return 1.0 / (d * d)
-    if kind == "logarithmic":
-        return 1.0 / np.log2(d + 1.0)
-    if kind == "constant":
-        return np.ones_like(d)
-    raise ValueError(f"unknown discount {kind}")
+    """f(1..length) of a discount Sec. 7 names ("harmonic", "quadratic",
+    "logarithmic", "constant"), computed by hb_discount_table."""
+    if kind not in DISCOUNTS:
+        raise ValueError(f"unknown discount {kind}")
+    f = np.empty(int(length), dtype=np.float64)
+    _check(lib().hb_discount_table(DISCOUNTS[kind], int(length), f.ctypes.data))
+    return f
 
 
 def hb_ensemble_init(offsets, indices, log2m: int, seeds, options: hb_options | None = None, stream=None):

@@ -1280,6 +1280,21 @@ hb_status hb_set_discount(hb_ctx* c, const double* f, int32_t len) {
   return st;
 }
 
+hb_status hb_discount_table(int32_t kind, int32_t len, double* f) {
+  if (!f || len < 1) return fail(HB_EINVAL, "need an output of at least one entry");
+  for (int32_t i = 0; i < len; ++i) {
+    const double d = (double)(i + 1);
+    switch (kind) {
+      case HB_DISCOUNT_HARMONIC: f[i] = 1.0 / d; break;
+      case HB_DISCOUNT_QUADRATIC: f[i] = 1.0 / (d * d); break;
+      case HB_DISCOUNT_LOGARITHMIC: f[i] = 1.0 / std::log2(d + 1.0); break;
+      case HB_DISCOUNT_CONSTANT: f[i] = 1.0; break;
+      default: return fail(HB_EINVAL, "unknown discount kind");
+    }
+  }
+  return HB_OK;
+}
+
 hb_status hb_get_discounted(hb_ctx* c, double* D, int32_t dst_on_device) {
   hb_status st = check_ctx(c);
   if (st != HB_OK) return st;

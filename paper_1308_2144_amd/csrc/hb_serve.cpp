@@ -260,10 +260,7 @@ void release_engine(Engine* e) {
     if (t.ev) (void)hipEventDestroy(t.ev);
     if (t.snap) (void)hipHostFree(t.snap);
   }
-  if (e->stage) {
-    (void)hipFreeAsync(e->stage, e->c->stream);
-    (void)hipStreamSynchronize(e->c->stream);
-  }
+  if (e->stage) (void)hipFree(e->stage);  // the stream was synchronised above
   if (e->c) release(e->c);
   delete e;
 }
@@ -330,6 +327,12 @@ hb_status make_engine(hb_server* s, int b, Engine** out) {
   ENG_ALLOC(c->graphs, e->n_slots);
   ENG_ALLOC(c->blk_graph, N / 64);
   ENG_ALLOC(c->ctl, 1);
+  // Staging for one request at a time, in stream order on the engine stream:
+  // its offsets before the rebase (<= 8 (N+1) bytes) and its four finalized
+  // outputs before their copies to the host (32 N bytes).  Allocated once,
+  // here, so that no allocation or free is ever ordered on a stream.
+  e->stage_bytes = std::max((size_t)8 * (size_t)(N + 1), (size_t)32 * (size_t)N);
+  ENG_ALLOC(e->stage, e->stage_bytes);
 
   hipStream_t st = c->stream;
   ENG_HIP(hb::launch_fill_zero(c->off, sizeof(int64_t) * (size_t)(N + 1), st));
@@ -385,15 +388,10 @@ hb_status make_engine(hb_server* s, int b, Engine** out) {
   return HB_OK;
 }
 
+// The engine's stage holds what one request needs (sized in make_engine for
+// the largest request the node pool admits).
 hb_status ensure_stage(Engine* e, size_t bytes) {
-  if (bytes <= e->stage_bytes) return HB_OK;
-  size_t want = std::max(bytes, e->stage_bytes * 2);
-  want = (want + 4095) / 4096 * 4096;
-  if (e->stage) HB_HIP(hipFreeAsync(e->stage, e->c->stream));
-  e->stage = nullptr;
-  e->stage_bytes = 0;
-  HB_HIP(hipMallocAsync(reinterpret_cast<void**>(&e->stage), want, e->c->stream));
-  e->stage_bytes = want;
+  if (bytes > e->stage_bytes) return fail(HB_EINVAL, "request larger than the engine's staging buffer");
   return HB_OK;
 }
 

@@ -1,5 +1,8 @@
 """Shared helpers of the GPU parity tests: run the HIP library and the oracle
 on the same seeded input and compare them element by element."""
+import hashlib
+import os
+
 import numpy as np
 
 import oracle
@@ -57,3 +60,70 @@ def check(off, idx, b, seed, what="", max_passes=0, **opt):
     ref = run_oracle(off, idx, b, seed, max_passes=max_passes)
     compare(got, ref, what)
     return got, ref
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def sha256_of(a) -> str:
+    """Digest of an array's raw bytes (float64 as little-endian), the form
+    tests/golden/make_fullsize.py writes."""
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.float64:
+        a = a.astype("<f8", copy=False)
+    return hashlib.sha256(a.tobytes()).hexdigest()
+
+
+def seq_sha256(xs) -> str:
+    return hashlib.sha256(",".join(str(int(x)) for x in xs).encode()).hexdigest()
+
+
+def load_golden_single(name):
+    """A single-graph golden file: scalar lines, nmod, sha256 digests, and
+    node lines (id lastmod S H closeness lin harmonic coreach, hex floats)."""
+    out = {"sha256": {}, "nodes": {}}
+    for line in open(os.path.join(GOLDEN, name)):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        if f[0] == "sha256":
+            out["sha256"][f[1]] = f[2]
+        elif f[0] == "nmod":
+            out["nmod"] = [int(x) for x in f[1:]]
+        elif f[0] == "node":
+            vals = [float.fromhex(x) for x in f[3:]]
+            out["nodes"][int(f[1])] = dict(lastmod=int(f[2]), S=vals[0], H=vals[1],
+                                           **dict(zip(CENTRALITIES, vals[2:])))
+        else:
+            out[f[0]] = int(f[1])
+    return out
+
+
+def load_golden_batch(name):
+    """Per-graph lines: g n m passes and 16-hex digests of registers, S, H and
+    the per-pass change counts."""
+    rows = {}
+    for line in open(os.path.join(GOLDEN, name)):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        rows[int(f[0])] = dict(n=int(f[1]), m=int(f[2]), passes=int(f[3]), regs=f[4], S=f[5], H=f[6], nmod=f[7])
+    return rows
+
+
+def load_golden_targets(name):
+    """Served targets: `target j sc ef b n m passes`, then its nmod and
+    sha256 lines."""
+    out, cur = [], None
+    for line in open(os.path.join(GOLDEN, name)):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        if f[0] == "target":
+            cur = dict(zip(("j", "sc", "ef", "b", "n", "m", "passes"), (int(x) for x in f[1:])), sha256={})
+            out.append(cur)
+        elif f[0] == "nmod":
+            cur["nmod"] = [int(x) for x in f[1:]]
+        elif f[0] == "sha256":
+            cur["sha256"][f[1]] = f[2]
+    return out

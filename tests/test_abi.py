@@ -155,3 +155,19 @@ def test_batch_argument_errors():
     with pytest.raises(hb.HBError) as e:
         hb.hb_batch_init([empty, empty], 5, [1, 2])  # nothing to compute
     assert e.value.status == hb.HB_EINVAL and "at least one graph with nodes" in str(e.value)
+
+
+def test_discount_table_is_host_only_and_matches_the_oracle():
+    """hb_discount_table needs no device; its values equal the oracle's own
+    Sec. 7 tables bit for bit (both evaluate the definitions with the host
+    libm), and unknown kinds are refused."""
+    import oracle
+    import paper_1308_2144_amd as hb
+
+    for kind in ("harmonic", "quadratic", "logarithmic", "constant"):
+        assert np.array_equal(hb.discount_table(kind, 100), oracle.discount_table(kind, 100)), kind
+    L = hb.lib()
+    f = np.zeros(4)
+    assert L.hb_discount_table(9, 4, f.ctypes.data) == hb.HB_EINVAL
+    assert L.hb_discount_table(0, 0, f.ctypes.data) == hb.HB_EINVAL
+    assert L.hb_discount_table(0, 4, None) == hb.HB_EINVAL

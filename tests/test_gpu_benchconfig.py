@@ -4,9 +4,15 @@ counter of x after t passes is the HyperLogLog state of the ball B(x, t)),
 plus properties that hold at any size.
 
 * batched: the 4096-graph Barabasi-Albert / Watts-Strogatz batch, log2m 5,
-  hash seeds 42+i, options from the committed autotuner cache;
+  hash seeds 42+i, options from the committed autotuner cache: every graph's
+  pass count and the digests of its registers, S and H against the whole
+  oracle run of that graph (tests/golden/fullsize_batch-4096.txt, written by
+  tests/golden/make_fullsize.py from the oracle alone);
 * serving: the largest, smallest and a middle request of the served R-MAT
-  pool (scale 10..20, edge factor 4..32, log2m 4/6/8) in a mix;
+  pool (scale 10..20, edge factor 4..32, log2m 4/6/8) in a mix: pass counts,
+  and digests of registers, S, H and the finalized outputs against the whole
+  oracle runs in tests/golden/fullsize_serve-targets.txt; the plain path's
+  per-pass change counts against the same runs;
 * ensemble: R-MAT scale 20, 8 seeds 42..49, log2m 4;
 * weights + logarithmic discount + neighbourhood function: R-MAT scale 20,
   log2m 6, weights uniform in 1..4 (PCG64 seed 9).
@@ -19,7 +25,7 @@ import pytest
 
 import graphgen as gg
 import oracle
-from hbcheck import assert_fp
+from hbcheck import CENTRALITIES, assert_fp, load_golden_batch, load_golden_targets, sha256_of
 
 pytestmark = pytest.mark.gpu
 
@@ -72,6 +78,21 @@ def test_batch_bench_config():
         bounds = bt.bounds
     assert np.all(passes > 0)
     sizes = np.array([len(o) - 1 for o, _ in graphs])
+    gold = load_golden_batch("fullsize_batch-4096.txt")
+    assert len(gold) == k
+    bad = {"passes": [], "registers": [], "S": [], "H": []}
+    regs_h, S_h, H_h = regs.cpu().numpy(), S.cpu().numpy(), H.cpu().numpy()
+    for g in range(k):
+        base, n = int(bounds[g]), int(sizes[g])
+        ref = gold[g]
+        assert (ref["n"], ref["m"]) == (n, len(graphs[g][1])), f"graph {g}: input differs from the golden's"
+        if int(passes[g]) != ref["passes"]:
+            bad["passes"].append(g)
+        for key, arr in (("registers", regs_h), ("S", S_h), ("H", H_h)):
+            if sha256_of(arr[base:base + n])[:16] != ref["regs" if key == "registers" else key]:
+                bad[key].append(g)
+    assert not any(bad.values()), {k: v[:10] for k, v in bad.items()}
+    _log("batch: all", k, "graphs equal the oracle runs (pass counts, registers, S, H)")
     half = k // 2
     ba, ws = np.arange(half), np.arange(half, k)
     chosen = {int(ba[np.argmin(sizes[ba])]), int(ba[np.argmax(sizes[ba])]), int(ws[np.argmin(sizes[ws])]),
@@ -120,13 +141,21 @@ def test_serving_bench_config():
         tr = []
         for (sc, ef, j), b in targets:
             tr.append((j, b, srv.submit(*graphs[j], b, 42 + j, registers=True)))
+        gold = {(t["j"], t["b"]): t for t in load_golden_targets("fullsize_serve-targets.txt")}
         for j, b, r in tr:
             info = srv.wait(r, 300.0)
             assert info["state_name"] == "done"
             off, idx = graphs[j]
             what = f"served pool graph {j} (n={len(off) - 1}, m={len(idx)}, log2m={b})"
-            with hb.HyperBall(off, idx, b, 42 + j) as g:          # pass count of the plain path
-                assert g.run() == info["passes"], what
+            ref = gold[(j, b)]
+            assert (ref["n"], ref["m"]) == (len(off) - 1, len(idx)), what
+            assert info["passes"] == ref["passes"], (what, info["passes"], ref["passes"])
+            out = r.outputs
+            for key in ("registers", "S", "H") + CENTRALITIES:
+                assert sha256_of(out[key]) == ref["sha256"][key], f"{what}: {key} differs from the oracle run"
+            with hb.HyperBall(off, idx, b, 42 + j) as g:          # the plain path's per-pass changes
+                assert g.run() == ref["passes"], what
+                assert [g.pass_stats(t)["rows_changed"] for t in range(ref["passes"])] == ref["nmod"], what
             for x in _pick(off, 4, j):
                 _check_node(off, idx, b, 42 + j, x, r.outputs["registers"][x], r.outputs["S"][x],
                             r.outputs["H"][x], what)
@@ -141,7 +170,7 @@ def test_ensemble_bench_config():
 
     import paper_1308_2144_amd as hb
 
-    off, idx = gg.rmat(20, 16, seed=2, transpose=True)
+    off, idx = gg.rmat(20, 16, seed=2, transpose=True, relabel=True)     # the benchmark's graph
     seeds = [42 + k for k in range(8)]
     o = torch.from_numpy(off.astype(np.int32)).cuda()
     i = torch.from_numpy(idx).cuda()
@@ -169,10 +198,11 @@ def test_extensions_bench_config():
 
     import paper_1308_2144_amd as hb
 
-    off, idx = gg.rmat(20, 16, seed=2, transpose=True)
+    off, idx = gg.rmat(20, 16, seed=2, transpose=True, relabel=True)     # the benchmark's graph
     n = len(off) - 1
     w = np.random.default_rng(9).integers(1, 5, size=n).astype(np.int32)
     table = hb.discount_table("logarithmic", 64)
+    otable = oracle.discount_table("logarithmic", 64)
     o = torch.from_numpy(off.astype(np.int32)).cuda()
     i = torch.from_numpy(idx).cuda()
     with hb.HyperBall(o, i, 6, 42, neighbourhood=1) as g:
@@ -186,7 +216,7 @@ def test_extensions_bench_config():
         N = g.neighbourhood()
     last = 0
     for x in _pick(off, 6, 21):
-        q = _check_node(off, idx, 6, 42, x, regs[x], S[x], H[x], "extensions", D=D[x], weights=w, discount=table)
+        q = _check_node(off, idx, 6, 42, x, regs[x], S[x], H[x], "extensions", D=D[x], weights=w, discount=otable)
         last = max(last, q["last_change"])
         fin = oracle.finalize(q["regs"][None, :], 6, np.array([q["S"]]), np.array([q["H"]]))
         for key in ("closeness", "lin", "harmonic", "coreach"):

@@ -18,9 +18,21 @@ def _log(*a):
     print(*a, flush=True)
 
 
+def _tables(table):
+    """A discount given as (kind, length) is computed on each side on its own
+    (hb_discount_table for the library, the oracle's for the oracle); an
+    explicit list of values goes to both."""
+    import paper_1308_2144_amd as hb
+
+    if isinstance(table, tuple):
+        return hb.discount_table(*table), oracle.discount_table(*table)
+    return table, table
+
+
 def run_gpu(off, idx, b, seed, weights=None, table=None, **opt):
     import paper_1308_2144_amd as hb
 
+    table = _tables(table)[0]
     with hb.HyperBall(off, idx, b, seed, neighbourhood=1, **opt) as g:
         if weights is not None:
             g.set_weights(weights)
@@ -37,7 +49,7 @@ def run_gpu(off, idx, b, seed, weights=None, table=None, **opt):
 
 def check(off, idx, b, seed, what, weights=None, table=None, **opt):
     got = run_gpu(off, idx, b, seed, weights=weights, table=table, **opt)
-    ref = oracle.run_ext(off, idx, b, seed, weights=weights, discount=table, trace=True)
+    ref = oracle.run_ext(off, idx, b, seed, weights=weights, discount=_tables(table)[1], trace=True)
     ref.update(oracle.finalize(ref["regs"], b, ref["S"], ref["H"]))
     assert got["passes"] == ref["passes"], (what, got["passes"], ref["passes"])
     assert np.array_equal(got["regs"], ref["regs"]), what + ": registers"
@@ -77,12 +89,8 @@ def test_weights_equal_oracle(name, b):
 @pytest.mark.parametrize("kind", ["quadratic", "logarithmic", "constant", "short", "identity"])
 @pytest.mark.parametrize("name", ["rmat8t", "rmat9u", "star", "cycle", "isolated"])
 def test_discounts_equal_oracle(name, kind):
-    import paper_1308_2144_amd as hb
-
     off, idx = GRAPHS[name]()
-    table = {"short": [1.0, 0.5, 0.25], "identity": list(np.arange(1.0, 200.0))}.get(kind)
-    if table is None:
-        table = hb.discount_table(kind, 48)
+    table = {"short": [1.0, 0.5, 0.25], "identity": list(np.arange(1.0, 200.0))}.get(kind, (kind, 48))
     w = np.random.default_rng(3).integers(1, 4, size=len(off) - 1).astype(np.int32)
     got = check(off, idx, 6, 11, f"{name} {kind}", weights=w, table=table)
     if kind == "identity":                      # f(d) = d is S's own weighting
@@ -92,11 +100,9 @@ def test_discounts_equal_oracle(name, kind):
 @pytest.mark.parametrize("opt", [dict(frontier=0), dict(qdense=1), dict(push=0), dict(slice=1),
                                  dict(light_max=4, heavy_min=40, chunk=16), dict(dense_pct=101)])
 def test_extensions_in_every_mode(opt):
-    import paper_1308_2144_amd as hb
-
     off, idx = gg.rmat(10, 12, seed=43, transpose=True)
     w = np.random.default_rng(5).integers(1, 9, size=len(off) - 1).astype(np.int32)
-    check(off, idx, 5, 3, f"opts {opt}", weights=w, table=hb.discount_table("quadratic", 30), **opt)
+    check(off, idx, 5, 3, f"opts {opt}", weights=w, table=("quadratic", 30), **opt)
 
 
 def test_unit_weights_change_nothing_and_device_weights():
@@ -150,9 +156,7 @@ def test_refusals():
 def test_extensions_at_scale_18():
     """R-MAT scale 18 with weights 1..4, the logarithmic discount and N(t),
     whole oracle run."""
-    import paper_1308_2144_amd as hb
-
     off, idx = gg.rmat(18, 8, seed=45, transpose=True, relabel=True)
     w = np.random.default_rng(7).integers(1, 5, size=len(off) - 1).astype(np.int32)
-    got = check(off, idx, 6, 13, "s18", weights=w, table=hb.discount_table("logarithmic", 64))
+    got = check(off, idx, 6, 13, "s18", weights=w, table=("logarithmic", 64))
     _log("s18 passes", got["passes"], "N", got["N"][:4], "...", got["N"][-1])

@@ -3,17 +3,21 @@
 * R-MAT scale 20, edge factor 16, transposed, int32 CSR, log2m = 6: the whole
   oracle run (about 30 s of CPU) against the GPU, element by element.
 * R-MAT scale 24, edge factor 16, transposed, int64 offsets, log2m = 7 (the
-  benchmark workload, same launch configuration as bench.py): sampled nodes
-  evaluated one by one by the oracle's breadth-first path (the counter of x
-  after t passes is the HyperLogLog state of the ball B(x, t)), plus the
-  properties that hold at any size.
+  benchmark workload, same launch configuration as bench.py), against the
+  whole oracle run stored in tests/golden/fullsize_rmat-s24.txt (written by
+  tests/golden/make_fullsize.py from the oracle alone): the pass count and
+  the counters changed by every pass exactly, the sha256 digests of all
+  registers, of S and H and of the four finalized outputs (bit-identity),
+  and the exact values at about 1400 nodes (every node changed in the last
+  two passes among them) to the 1e-12 bar; plus sampled nodes evaluated one
+  by one by the oracle's breadth-first path at radii 1, 3 and at the end.
 """
 import numpy as np
 import pytest
 
 import graphgen as gg
 import oracle
-from hbcheck import assert_fp, check
+from hbcheck import CENTRALITIES, assert_fp, check, load_golden_single, sha256_of
 
 pytestmark = pytest.mark.gpu
 
@@ -49,7 +53,7 @@ def _sample(off, idx, k, seed):
 
 
 @pytest.mark.timeout(900)
-def test_rmat_s24_sampled(s24):
+def test_rmat_s24_against_oracle_run(s24):
     import torch
 
     import paper_1308_2144_amd as hb
@@ -57,10 +61,13 @@ def test_rmat_s24_sampled(s24):
     off, idx = s24
     n = len(off) - 1
     b, seed = 7, 42
+    gold = load_golden_single("fullsize_rmat-s24.txt")
+    assert (gold["n"], gold["m"], gold["log2m"], gold["seed"]) == (n, len(idx), b, seed)
     o = torch.from_numpy(off).cuda()
     i = torch.from_numpy(idx).cuda()
     xs = _sample(off, idx, 12, 5)
-    with hb.HyperBall(o, i, b, seed, stream=torch.cuda.current_stream().cuda_stream) as g:
+    # the benchmark's launch configuration: default options, pass timing on
+    with hb.HyperBall(o, i, b, seed, stream=torch.cuda.current_stream().cuda_stream, timing=1) as g:
         # intermediate radii first
         snaps = {}
         for t in (1, 3):
@@ -74,21 +81,26 @@ def test_rmat_s24_sampled(s24):
         cen = g.centralities()
         assert g.iterate() == 0
     _log("s24 passes", passes, "modes", modes, "changed", nmod)
-    assert nmod[-1] == 0 and all(c > 0 for c in nmod[:-1])
     assert 1 in modes and 2 in modes        # both dense and sparse passes ran
-    last = 0
+    assert passes == gold["passes"], (passes, gold["passes"])
+    assert nmod == gold["nmod"], (nmod, gold["nmod"])
+    assert sha256_of(regs) == gold["sha256"]["registers"], "registers differ from the oracle run"
+    got = dict(S=S, H=H, **cen)
+    for k, v in gold["nodes"].items():
+        for key in ("S", "H") + CENTRALITIES:
+            assert_fp([got[key][k]], [v[key]], f"{key}[{k}]")
+    for key in ("S", "H") + CENTRALITIES:      # bit-identity over all nodes
+        assert sha256_of(got[key]) == gold["sha256"][key], f"{key} not bit-identical to the oracle run"
+    late = [k for k, v in gold["nodes"].items() if v["lastmod"] >= passes - 1]
+    assert len(late) == gold["nmod"][-2] + gold["nmod"][-1]
+    _log("s24 golden ok:", len(gold["nodes"]), "nodes,", len(late), "changed in the last two passes")
     for k, x in enumerate(xs):
         q = oracle.node(off, idx, b, seed, x)
-        last = max(last, q["last_change"])
         assert np.array_equal(regs[x], q["regs"]), x
         assert_fp([S[x]], [q["S"]], f"S[{x}]")
         assert_fp([H[x]], [q["H"]], f"H[{x}]")
-        fin = oracle.finalize(q["regs"][None, :], b, np.array([q["S"]]), np.array([q["H"]]))
-        for key in ("closeness", "lin", "harmonic", "coreach"):
-            assert_fp([cen[key][x]], fin[key], f"{key}[{x}]")
         for t in (1, 3):
             assert np.array_equal(snaps[t][k], oracle.node(off, idx, b, seed, x, radius=t)["regs"])
-    assert passes >= last + 1
     # invariants over all nodes: registers never exceed the largest initial
     # rank (a union creates no new values), empty rows keep their singleton
     deg = np.diff(off)

@@ -335,3 +335,21 @@ def test_node_ext_matches_run_ext_bitwise(orc, gg):
             q = orc.node(o, i, 6, 21, x, weights=w, discount=table)
             assert np.array_equal(q["regs"], r["regs"][x]), (name, x)
             assert q["S"] == r["S"][x] and q["H"] == r["H"][x] and q["D"] == r["D"][x], (name, x)
+
+
+def test_discount_tables_exact_values(orc):
+    """Sec. 7 discounts at distances where they are exact in binary: 1/d and
+    1/d^2 at powers of two, 1/log2(d+1) at d = 2^k - 1 (= 1/k), constant 1;
+    and everywhere non-increasing with f(1) = 1."""
+    L = 64
+    h, q, lg, c = (orc.discount_table(k, L) for k in ("harmonic", "quadratic", "logarithmic", "constant"))
+    for k in range(0, 6):
+        d = 1 << k
+        assert h[d - 1] == 1.0 / d and q[d - 1] == 1.0 / (d * d)
+    for k in range(1, 7):
+        assert lg[(1 << k) - 2] == 1.0 / k
+    assert np.all(c == 1.0)
+    for f in (h, q, lg, c):
+        assert f[0] == 1.0 and np.all(np.diff(f) <= 0.0)
+    with pytest.raises(KeyError):
+        orc.discount_table("exponential", 4)
