@@ -447,6 +447,27 @@ typedef struct {
  * arithmetic, sums in t order; no context needed). */
 hb_status hb_distance_stats(const double* N, int32_t len, double alpha, hb_distance_stats_t* out);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid allocation): hb_init + hb_run + hb_centralities of
+ * one graph in one call that allocates nothing.  All device state lives in
+ * a fixed 64 MiB scratch array that the library holds on every GPU it runs
+ * on until the process ends; a graph needs about n * (2 * 2^log2m + 29)
+ * bytes of it (n up to about 1.1 M nodes at log2m 4, 120 k at log2m 8), and
+ * a larger one is refused with HB_ENOMEM before any device work.
+ *   g          device CSR (on_device must be 1), int32 or int64 offsets;
+ *              read only.
+ *   log2m      in [4, 8]; seed: the hash seed.
+ *   closeness, lin, harmonic, coreach: device arrays of n doubles, each
+ *              nullable; registers: device array of n * 2^log2m bytes
+ *              (node-major final counters), nullable.
+ *   passes     host int32 (nullable): the pass count, as hb_run reports it.
+ *   stream     hipStream_t or NULL (default stream); the call synchronises it.
+ * Results equal hb_init + hb_run + hb_centralities on the same graph, bit for
+ * bit.  Every call on a GPU shares that GPU's scratch: calls that overlap on
+ * one GPU (two threads, or two streams) race and give wrong results. */
+hb_status hb_run_static(const hb_csr* g, int32_t log2m, uint64_t seed, double* closeness, double* lin,
+                        double* harmonic, double* coreach, uint8_t* registers, int32_t* passes, void* stream);
+
 /* Releases everything the context owns (never borrowed memory).  NULL-safe. */
 void hb_free(hb_ctx* c);
 

@@ -142,6 +142,7 @@ def _declare(L):
         "hb_neighbourhood": (ctypes.c_int, [vp, vp, i32, P(i32)]),
         "hb_distance_stats": (ctypes.c_int, [vp, i32, ctypes.c_double, P(hb_distance_stats_t)]),
         "hb_discount_table": (ctypes.c_int, [i32, i32, vp]),
+        "hb_run_static": (ctypes.c_int, [P(hb_csr), i32, ctypes.c_uint64, vp, vp, vp, vp, vp, P(i32), vp]),
         "hb_ensemble_init": (ctypes.c_int, [P(vp), P(hb_csr), i32, vp, i32, P(hb_options), vp]),
         "hb_ensemble_reset": (ctypes.c_int, [vp, vp]),
         "hb_ensemble_passes": (ctypes.c_int, [vp, vp]),
@@ -289,6 +290,22 @@ def hb_distance_stats(N, alpha: float = 0.9) -> dict:
     st = hb_distance_stats_t()
     _check(lib().hb_distance_stats(a.ctypes.data, a.shape[0], float(alpha), ctypes.byref(st)))
     return {k: getattr(st, k) for k, _ in hb_distance_stats_t._fields_}
+
+
+def hb_run_static(offsets, indices, log2m: int, seed: int, closeness=None, lin=None, harmonic=None,
+                  coreach=None, registers=None, stream=None) -> int:
+    """hb_run_static: device CSR (torch tensors) in, results into the given
+    device tensors (each may be None); returns the pass count."""
+    if not (_is_torch(offsets) and offsets.is_cuda and _is_torch(indices) and indices.is_cuda):
+        raise TypeError("hb_run_static takes a device CSR (CUDA tensors)")
+    g, keep = _csr(offsets, indices)
+    passes = ctypes.c_int32(0)
+    ptr = [None if a is None else ctypes.c_void_p(a.data_ptr()) for a in (closeness, lin, harmonic, coreach,
+                                                                          registers)]
+    _check(lib().hb_run_static(ctypes.byref(g), int(log2m), int(seed), *ptr, ctypes.byref(passes),
+                               ctypes.c_void_p(stream) if stream else None))
+    del keep
+    return passes.value
 
 
 DISCOUNTS = {"harmonic": 0, "quadratic": 1, "logarithmic": 2, "constant": 3}

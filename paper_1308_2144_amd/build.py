@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhb.so")
-SOURCES = ["hb_kernels.hip", "hb_api.cpp", "hb_serve.cpp", "hb_tune.cpp"]
+SOURCES = ["hb_kernels.hip", "hb_api.cpp", "hb_serve.cpp", "hb_tune.cpp", "hb_static.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -ffp-contract=off: the FP64 accumulators must round exactly as written.
