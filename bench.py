@@ -204,6 +204,65 @@ def cpu_baseline_child(args):
         flush=True)
 
 
+def bench_streamed(args, torch, hb, off, idx, w, seed, resident_ms, steps: int = 3,
+                   budget: int = 512 << 20):
+    """The same workload with the CSR kept in pinned host memory and streamed
+    to the device in row chunks every pass (graph budget `budget` bytes: two
+    staging buffers of budget/2), against the resident run: each step =
+    reset + passes to convergence + centralities into device memory.  Also a
+    plain pinned-host-to-device copy of 1 GiB, the host link's reference
+    rate."""
+    n, m = len(off) - 1, len(idx)
+    dev = torch.device("cuda:0")
+    outs = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(4)]
+    stream = torch.cuda.current_stream().cuda_stream
+    t = time.perf_counter()
+    g = hb.HyperBall(off, idx, w["log2m"], seed, stream=stream, stream_graph=1, graph_budget=budget, timing=1)
+    init_s = time.perf_counter() - t
+    st = g.stats()
+
+    def step():
+        g.reset(seed)
+        p = g.run()
+        hb.hb_centralities(g._ctx, *outs, True)
+        return p
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    host = 0
+    scanned = 0
+    for _ in range(steps):
+        passes = step()
+        ps = [g.pass_stats(t) for t in range(passes)]
+        host += sum(p["host_bytes"] for p in ps)
+        scanned += sum(p["arcs_scanned"] for p in ps)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    g.close()
+    del outs
+    src = torch.empty(1 << 30, dtype=torch.uint8).pin_memory()
+    dst = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    dst.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        dst.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    h2d = 3 * (1 << 30) / (time.perf_counter() - t0) / 1e9
+    del src, dst
+    return {"workload": f"{args.workload} with the CSR in pinned host memory, streamed in row chunks "
+                        f"(graph budget {budget >> 20} MiB: two staging buffers of {budget >> 21} MiB)",
+            "chunks": st["chunks"], "init_s": round(init_s, 2), "passes": passes,
+            "chunks_run_per_pass": [p["chunks_run"] for p in ps],
+            "ms_per_step": dt * 1e3, "resident_ms_per_step": resident_ms,
+            "slowdown_vs_resident": dt * 1e3 / resident_ms,
+            "edge_visits_per_s": scanned / steps / dt,
+            "host_bytes_per_step": host // steps, "host_link_GBps": host / steps / dt / 1e9,
+            "h2d_copy_GBps": h2d,
+            "pass_ms": [round(p["expand_ms"] + p["push_ms"], 3) for p in ps]}
+
+
 def bench_batch(args, torch, hb, plain_sample: int = 512):
     """Batched form on the 4096-graph workload: graphs/s of one batched
     context (reset + passes to convergence for every graph + centralities,
@@ -636,6 +695,7 @@ def main():
     ap.add_argument("--qdense", type=int, default=0)
     ap.add_argument("--slice", type=int, default=0)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
+    ap.add_argument("--no-streamed", action="store_true", help="skip the host-streamed graph measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the multi-seed ensemble measurement")
     ap.add_argument("--ensemble-only", action="store_true", help="only the ensemble measurement (its own line)")
@@ -770,6 +830,11 @@ def main():
     g.close()
     del o_d, i_d, outs
     torch.cuda.empty_cache()
+    if not args.no_streamed:
+        log("streamed graph ...")
+        out["streamed"] = bench_streamed(args, torch, hb, off, idx, w, seed, ms_per_step)
+        log(f"streamed: {out['streamed']}")
+        torch.cuda.empty_cache()
     if not args.no_batch:
         log("batched form ...")
         out["batched"] = bench_batch(args, torch, hb)
@@ -798,6 +863,25 @@ def main():
         out["copy_calib"] = {"bytes_read": 1 << 30, "bytes_written": 1 << 30, "ms": cdt * 1e3,
                              "GBps_rw": 2 * (1 << 30) / cdt / 1e9}
         del src, dst
+        # Random row gathers of known size (torch index_select over 2 GiB of
+        # 128-byte and 32-byte rows, 2^23 uniform row ids, int64): how
+        # FETCH_SIZE counts scattered reads of counter-sized rows.
+        table = torch.empty(1 << 31, dtype=torch.uint8, device=dev).fill_(1)
+        for width in (128, 32):
+            rows = table.view(-1, width)
+            ids = torch.randint(0, rows.shape[0], (1 << 23,), device=dev, generator=torch.Generator(device=dev).manual_seed(11))
+            got = torch.index_select(rows, 0, ids)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                got = torch.index_select(rows, 0, ids)
+            torch.cuda.synchronize()
+            gdt = (time.perf_counter() - t0) / 3
+            out["copy_calib"][f"gather{width}"] = {"rows": 1 << 23, "row_bytes": width,
+                                                   "bytes_read": (1 << 23) * (width + 8),
+                                                   "bytes_written": (1 << 23) * width, "ms": gdt * 1e3}
+            del got, ids
+        del table
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle pass 0 on a sample of rows ...")
         out["cpu_baseline"] = cpu_baseline(off, idx, dict(w, name=args.workload), seed)

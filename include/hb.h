@@ -107,7 +107,20 @@ typedef struct {
  *              source row) instead of activation stamps, when they fit the
  *              list capacity sized at init (about (m + n) / 16 pairs, all of
  *              them for m + n <= 2^16; about 80 bytes of device memory per
- *              pair); 0: activation stamps only. */
+ *              pair); 0: activation stamps only.
+ *   stream_graph  graphs whose arcs do not fit in device memory (Sec. 5.1
+ *              keeps the graph out of core and only the counters in core):
+ *              1 keeps the CSR in library-owned pinned host memory and
+ *              streams it to the device in row chunks every pass (two
+ *              staging buffers, uploads overlapping the previous chunk's
+ *              kernels; passes after the first skip chunks none of whose
+ *              rows has a changed successor or changed itself); 0 does so
+ *              only when the CSR (8 (n+1) + 4 m bytes) exceeds graph_budget;
+ *              -1 never.  Needs a host CSR (on_device = 0), a single-graph,
+ *              single-seed context and log2m <= 8; push, pairs are ignored.
+ *   graph_budget  device bytes for the graph (<= 0: no limit).  A streamed
+ *              graph stages chunks of at most graph_budget / 2 bytes
+ *              (<= 0: 256 MiB each); a row must fit one chunk. */
 typedef struct {
   int32_t frontier;
   int32_t light_max;
@@ -124,6 +137,8 @@ typedef struct {
   int32_t graph_passes;
   int32_t neighbourhood;
   int32_t pairs;
+  int32_t stream_graph;
+  int64_t graph_budget;
 } hb_options;
 
 void hb_default_options(hb_options* opt);
@@ -183,6 +198,9 @@ typedef struct {
   int64_t light_rows;      /* rows handled by one lane group */
   int32_t reverse_built;   /* 1 if the reverse CSR exists (push = 1) */
   double total_kernel_ms;  /* sum of timed pass kernels (timing = 1) */
+  int32_t streamed;        /* 1 if the CSR lives in host memory and is streamed */
+  int32_t chunks;          /* row chunks of a streamed graph */
+  int64_t chunk_bytes;     /* capacity of each of its two staging buffers */
 } hb_stats_t;
 
 hb_status hb_stats(hb_ctx* c, hb_stats_t* s);
@@ -208,7 +226,11 @@ hb_status hb_stats(hb_ctx* c, hb_stats_t* s);
  *                      successor counters recomputed from node hashes, 2
  *                      sparse pass from pair lists (push_ms then includes
  *                      building and sorting them)
- *   push_ms / expand_ms / merge_ms: kernel times from HIP events (timing = 1). */
+ *   push_ms / expand_ms / merge_ms: kernel times from HIP events (timing = 1);
+ *                      in a streamed pass expand_ms spans all its chunks'
+ *                      uploads and kernels, push_ms the chunk selection
+ *   host_bytes         bytes streamed from host memory by the pass
+ *   chunks_run         row chunks the pass streamed and ran (of hb_stats.chunks) */
 typedef struct {
   int64_t arcs_scanned;
   int64_t counters_gathered;
@@ -223,6 +245,8 @@ typedef struct {
   double expand_ms;
   double merge_ms;
   int32_t path;
+  int64_t host_bytes;
+  int32_t chunks_run;
 } hb_pass_info;
 
 hb_status hb_pass_stats(hb_ctx* c, int32_t pass, hb_pass_info* info);

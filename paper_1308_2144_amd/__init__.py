@@ -49,7 +49,8 @@ class hb_options(ctypes.Structure):
                 ("sparse_pct", ctypes.c_int32), ("qdense", ctypes.c_int32),
                 ("slice", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
                 ("graph_passes", ctypes.c_int32), ("neighbourhood", ctypes.c_int32),
-                ("pairs", ctypes.c_int32)]
+                ("pairs", ctypes.c_int32), ("stream_graph", ctypes.c_int32),
+                ("graph_budget", ctypes.c_int64)]
 
 
 class hb_stats_t(ctypes.Structure):
@@ -58,7 +59,8 @@ class hb_stats_t(ctypes.Structure):
                 ("last_modified", ctypes.c_int64), ("heavy_rows", ctypes.c_int64),
                 ("heavy_chunks", ctypes.c_int64), ("medium_rows", ctypes.c_int64),
                 ("light_rows", ctypes.c_int64), ("reverse_built", ctypes.c_int32),
-                ("total_kernel_ms", ctypes.c_double)]
+                ("total_kernel_ms", ctypes.c_double), ("streamed", ctypes.c_int32),
+                ("chunks", ctypes.c_int32), ("chunk_bytes", ctypes.c_int64)]
 
 
 class hb_pass_info(ctypes.Structure):
@@ -68,7 +70,8 @@ class hb_pass_info(ctypes.Structure):
                 ("slices_changed", ctypes.c_int64), ("arcs_to_changed", ctypes.c_int64),
                 ("mode", ctypes.c_int32),
                 ("push_ms", ctypes.c_double), ("expand_ms", ctypes.c_double),
-                ("merge_ms", ctypes.c_double), ("path", ctypes.c_int32)]
+                ("merge_ms", ctypes.c_double), ("path", ctypes.c_int32),
+                ("host_bytes", ctypes.c_int64), ("chunks_run", ctypes.c_int32)]
 
 
 class hb_graph_info(ctypes.Structure):

@@ -56,6 +56,21 @@ namespace hbh {
 
 void release(hb_ctx* c) {
   if (!c) return;
+  if (c->copy_stream) {
+    (void)hipStreamSynchronize(c->copy_stream);
+    (void)hipStreamDestroy(c->copy_stream);
+  }
+  for (int i = 0; i < 2; ++i) {
+    if (c->up_ev[i]) (void)hipEventDestroy(c->up_ev[i]);
+    if (c->done_ev[i]) (void)hipEventDestroy(c->done_ev[i]);
+    (void)hipFree(c->stage[i]);
+  }
+  if (c->host_off) (void)hipHostFree(c->host_off);
+  if (c->host_idx) (void)hipHostFree(c->host_idx);
+  if (c->chunk_act_host) (void)hipHostFree(c->chunk_act_host);
+  (void)hipFree(c->pred_mask);
+  (void)hipFree(c->chunk_rows);
+  (void)hipFree(c->chunk_act);
   if (c->own_off) (void)hipFree(c->off);
   (void)hipFree(c->idx_owned);
   for (int i = 0; i < 2; ++i) {
@@ -386,6 +401,199 @@ hb_status alloc_pairs(hb_ctx* c) {
   return HB_OK;
 }
 
+constexpr int64_t DEFAULT_CHUNK_BYTES = (int64_t)256 << 20;
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Host check of a CSR: 0 if well formed, 1 for bad offsets, 2 for an index
+// outside [0, n).
+template <class T>
+int host_csr_check(const T* off, const int32_t* idx, int64_t n, int64_t m) {
+  if ((int64_t)off[0] != 0 || (int64_t)off[n] != m) return 1;
+  for (int64_t v = 0; v < n; ++v)
+    if (off[v + 1] < off[v]) return 1;
+  for (int64_t e = 0; e < m; ++e)
+    if (idx[e] < 0 || idx[e] >= n) return 2;
+  return 0;
+}
+
+// A streamed graph (paper Sec. 5.1: the graph is read from outside the
+// memory that holds the counters): a pinned host copy of the CSR, row lists
+// built on the host, and row chunks that fit a staging buffer.  Device
+// memory holds the lists, two staging buffers, and per node a mask of the
+// chunks with an arc into it (built while the first pass streams every
+// chunk) for chunk selection in later passes.
+hb_status setup_streamed(hb_ctx* c, const hb_csr* g) {
+  const int64_t n = c->n, m = c->m;
+  if (c->opt.validate) {
+    const int bad = g->offsets_bits == 64
+                        ? host_csr_check(static_cast<const int64_t*>(g->offsets), g->indices, n, m)
+                        : host_csr_check(static_cast<const int32_t*>(g->offsets), g->indices, n, m);
+    if (bad == 1) return fail(HB_EINVAL, "malformed CSR offsets (need offsets[0]=0, nondecreasing, offsets[n]=m)");
+    if (bad == 2) return fail(HB_EINVAL, "CSR index outside [0, n)");
+  }
+  HB_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->host_off), sizeof(int64_t) * (size_t)(n + 1),
+                       hipHostMallocDefault));
+  HB_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->host_idx), sizeof(int32_t) * (size_t)(m > 0 ? m : 1),
+                       hipHostMallocDefault));
+  if (g->offsets_bits == 64) {
+    std::memcpy(c->host_off, g->offsets, sizeof(int64_t) * (size_t)(n + 1));
+  } else {
+    const int32_t* o = static_cast<const int32_t*>(g->offsets);
+    for (int64_t v = 0; v <= n; ++v) c->host_off[v] = o[v];
+  }
+  {  // the arc copy in parallel slices (it is the bulk of the graph)
+    const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(16, m >> 24));
+    std::vector<std::thread> th;
+    for (int k = 0; k < nt; ++k)
+      th.emplace_back([=] {
+        const int64_t a = m * k / nt, b = m * (k + 1) / nt;
+        if (b > a) std::memcpy(c->host_idx + a, g->indices + a, sizeof(int32_t) * (size_t)(b - a));
+      });
+    for (auto& t : th) t.join();
+  }
+  std::vector<int32_t> light, medium;
+  std::vector<hb::HeavyItem> items;
+  std::vector<hb::HeavyRow> hrows;
+  plan_rows_host(c->host_off, n, c->opt.light_max, c->opt.heavy_min, c->opt.chunk, light, medium, items, hrows);
+  // Chunks: consecutive rows while their offsets (256-byte aligned) and arcs
+  // fit one staging buffer.
+  const int64_t cap = (c->opt.graph_budget > 0 ? c->opt.graph_budget / 2 : DEFAULT_CHUNK_BYTES) / 256 * 256;
+  c->chunk_bytes = cap;
+  auto bytes_of = [&](int64_t r0, int64_t r1) {
+    return (int64_t)align256(sizeof(int64_t) * (size_t)(r1 - r0 + 1)) +
+           (int64_t)sizeof(int32_t) * (c->host_off[r1] - c->host_off[r0]);
+  };
+  for (int64_t r0 = 0; r0 < n;) {
+    if (bytes_of(r0, r0 + 1) > cap)
+      return fail(HB_ENOMEM, "row " + std::to_string(r0) + " has " + std::to_string(c->host_off[r0 + 1] - c->host_off[r0]) +
+                                 " arcs, more than a staging buffer of " + std::to_string(cap) + " bytes holds");
+    // largest r1 with bytes_of(r0, r1) <= cap (monotone in r1)
+    int64_t lo = r0 + 1, hi = n;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo + 1) / 2;
+      if (bytes_of(r0, mid) <= cap) lo = mid; else hi = mid - 1;
+    }
+    StreamChunk ch{};
+    ch.r0 = r0;
+    ch.r1 = lo;
+    ch.e0 = c->host_off[r0];
+    ch.e1 = c->host_off[lo];
+    c->chunks.push_back(ch);
+    r0 = lo;
+  }
+  // Each chunk's entries of the (row-sorted) lists; heavy rows name their
+  // first item relative to the chunk's first item, as a chunk's items are
+  // numbered from 0 in its launch.
+  for (StreamChunk& ch : c->chunks) {
+    auto rows_lb = [](const std::vector<int32_t>& v, int64_t r) {
+      return (int64_t)(std::lower_bound(v.begin(), v.end(), r, [](int32_t a, int64_t b) { return a < b; }) - v.begin());
+    };
+    ch.l0 = rows_lb(light, ch.r0);
+    ch.l1 = rows_lb(light, ch.r1);
+    ch.m0 = rows_lb(medium, ch.r0);
+    ch.m1 = rows_lb(medium, ch.r1);
+    auto item_lb = [&](int64_t r) {
+      return (int64_t)(std::lower_bound(items.begin(), items.end(), r,
+                                        [](const hb::HeavyItem& a, int64_t b) { return a.row < b; }) - items.begin());
+    };
+    auto hrow_lb = [&](int64_t r) {
+      return (int64_t)(std::lower_bound(hrows.begin(), hrows.end(), r,
+                                        [](const hb::HeavyRow& a, int64_t b) { return a.row < b; }) - hrows.begin());
+    };
+    ch.i0 = item_lb(ch.r0);
+    ch.i1 = item_lb(ch.r1);
+    ch.h0 = hrow_lb(ch.r0);
+    ch.h1 = hrow_lb(ch.r1);
+    for (int64_t h = ch.h0; h < ch.h1; ++h) hrows[(size_t)h].item0 -= ch.i0;
+  }
+  hb_status st = upload_plan(c, light, medium, items, hrows);
+  if (st != HB_OK) return st;
+  const int32_t nch = (int32_t)c->chunks.size();
+  std::vector<int64_t> first((size_t)nch + 1, n);
+  for (int32_t i = 0; i < nch; ++i) first[(size_t)i] = c->chunks[(size_t)i].r0;
+  HB_HIP(dmalloc(&c->chunk_rows, first.size()));
+  HB_HIP(hipMemcpyAsync(c->chunk_rows, first.data(), sizeof(int64_t) * first.size(), hipMemcpyHostToDevice,
+                        c->stream));
+  HB_HIP(dmalloc(&c->pred_mask, (size_t)(n > 0 ? n : 1)));
+  HB_HIP(hb::launch_fill_zero(c->pred_mask, sizeof(uint32_t) * (size_t)(n > 0 ? n : 1), c->stream));
+  HB_HIP(dmalloc(&c->chunk_act, 1));
+  HB_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->chunk_act_host), sizeof(uint32_t), hipHostMallocDefault));
+  for (int i = 0; i < 2; ++i) {
+    if (dmalloc(&c->stage[i], (size_t)cap) != hipSuccess)
+      return fail(HB_ENOMEM, "cannot allocate a staging buffer of " + std::to_string(cap) + " bytes");
+    HB_HIP(hipEventCreateWithFlags(&c->up_ev[i], hipEventDisableTiming));
+    HB_HIP(hipEventCreateWithFlags(&c->done_ev[i], hipEventDisableTiming));
+    HB_HIP(hipEventRecord(c->done_ev[i], c->stream));
+  }
+  HB_HIP(hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking));
+  HB_HIP(hipStreamSynchronize(c->stream));  // the chunk table above is read from the host
+  c->n_nonempty = c->n_light + c->n_medium + c->n_hrows;
+  return HB_OK;
+}
+
+// One pass of a streamed graph: the chunks that can have work (every chunk in
+// first and dense passes), each uploaded on the copy stream into the staging
+// buffer the chunk before last used, once that chunk's kernels are done, and
+// run on the context stream once its upload is done.  The pass kernels see
+// the chunk's offsets and arcs at their global indices.
+hipError_t streamed_pass(hb_ctx* c, const hb::PassArgs& a, bool timing, hb_pass_info& info) {
+  const int32_t nch = (int32_t)c->chunks.size();
+  const size_t half = (size_t)hb::STAT_SLOTS * hb::STAT_K;
+  hipError_t e = hb::launch_fill_zero(a.stats, sizeof(unsigned long long) * half, c->stream);
+  uint32_t sel = 0xffffffffu;
+  const bool all = a.mode == hb::MODE_FIRST || a.mode == hb::MODE_DENSE || !c->masks_ready;
+  if (!all) {
+    if (e == hipSuccess)
+      e = hb::launch_chunk_activity(a.mod_prev, c->n_blocks, c->pred_mask, c->chunk_rows, nch, c->chunk_act,
+                                    c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->chunk_act_host, c->chunk_act, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return e;
+    sel = *c->chunk_act_host;
+  }
+  if (e == hipSuccess && timing) e = hipEventRecord(c->ev[1], c->stream);
+  const bool build_masks = !c->masks_ready;
+  int k = 0;
+  for (int32_t ci = 0; ci < nch && e == hipSuccess; ++ci) {
+    if (!((sel >> (ci & 31)) & 1u)) continue;
+    const StreamChunk& ch = c->chunks[(size_t)ci];
+    const int s = k & 1;
+    ++k;
+    int64_t* soff = reinterpret_cast<int64_t*>(c->stage[s]);
+    const size_t obytes = sizeof(int64_t) * (size_t)(ch.r1 - ch.r0 + 1);
+    int32_t* sidx = reinterpret_cast<int32_t*>(c->stage[s] + align256(obytes));
+    const size_t ibytes = sizeof(int32_t) * (size_t)(ch.e1 - ch.e0);
+    e = hipStreamWaitEvent(c->copy_stream, c->done_ev[s], 0);
+    if (e == hipSuccess) e = hipMemcpyAsync(soff, c->host_off + ch.r0, obytes, hipMemcpyHostToDevice, c->copy_stream);
+    if (e == hipSuccess && ibytes)
+      e = hipMemcpyAsync(sidx, c->host_idx + ch.e0, ibytes, hipMemcpyHostToDevice, c->copy_stream);
+    if (e == hipSuccess) e = hipEventRecord(c->up_ev[s], c->copy_stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->up_ev[s], 0);
+    hb::PassArgs b = a;
+    b.off = soff - ch.r0;
+    b.idx = sidx - ch.e0;
+    b.light = c->light + ch.l0;
+    b.n_light = ch.l1 - ch.l0;
+    b.medium = c->medium + ch.m0;
+    b.n_medium = ch.m1 - ch.m0;
+    b.items = c->items + ch.i0;
+    b.n_items = ch.i1 - ch.i0;
+    b.hrows = c->hrows + ch.h0;
+    b.n_hrows = ch.h1 - ch.h0;
+    if (e == hipSuccess) e = hb::launch_pass(c->b, b, c->stream, nullptr);
+    if (e == hipSuccess && build_masks)
+      e = hb::launch_pred_masks(sidx, ch.e1 - ch.e0, 1u << (ci & 31), c->pred_mask, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->done_ev[s], c->stream);
+    info.host_bytes += (int64_t)(obytes + ibytes);
+    info.chunks_run += 1;
+  }
+  if (e == hipSuccess && build_masks) c->masks_ready = true;
+  if (e == hipSuccess && timing) e = hipEventRecord(c->ev[2], c->stream);
+  return e;
+}
+
 hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, const hb_options* opt,
                     void* stream, const std::vector<int32_t>* blk_graph = nullptr) {
   c->n = g->n;
@@ -407,8 +615,22 @@ hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, co
   const int64_t n = c->n, m = c->m;
   c->n_blocks = (n + 63) / 64;
 
+  // A host CSR is streamed on request, or when it exceeds the graph budget.
+  const int64_t csr_bytes = 8 * (n + 1) + 4 * m;
+  if (c->opt.stream_graph > 0 ||
+      (c->opt.stream_graph == 0 && !g->on_device && c->opt.graph_budget > 0 && csr_bytes > c->opt.graph_budget)) {
+    if (g->on_device) return fail(HB_EINVAL, "a streamed graph needs a host CSR (on_device = 0)");
+    if (c->n_seeds != 1 || blk_graph) return fail(HB_EINVAL, "graph streaming needs a single-graph, single-seed context");
+    if (c->p > 256) return fail(HB_EINVAL, "graph streaming needs log2m <= 8");
+    c->streamed = true;
+    const hb_status st = setup_streamed(c, g);
+    if (st != HB_OK) return st;
+  }
+
   // Graph arrays (int32 offsets are widened on the device).
-  if (!g->on_device) {
+  if (c->streamed) {
+    // the arcs stay in host memory (setup_streamed)
+  } else if (!g->on_device) {
     HB_HIP(dmalloc(&c->off, (size_t)n + 1));
     c->own_off = true;
     if (g->offsets_bits == 64) {
@@ -440,7 +662,7 @@ hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, co
     c->idx = g->indices;
   }
 
-  if (c->opt.validate) {
+  if (c->opt.validate && !c->streamed) {
     HB_HIP(dmalloc(&c->bad, 1));
     HB_HIP(hipMemsetAsync(c->bad, 0, sizeof(int), c->stream));
     HB_HIP(hb::launch_validate(c->off, c->idx, n, m, c->bad, c->stream));
@@ -450,7 +672,9 @@ hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, co
     if (bad & 1) return fail(HB_EINVAL, "malformed CSR offsets (need offsets[0]=0, nondecreasing, offsets[n]=m)");
     if (bad & 2) return fail(HB_EINVAL, "CSR index outside [0, n)");
   }
-  if (n <= HOST_PLAN_MAX) {
+  if (c->streamed) {
+    // row lists made by setup_streamed
+  } else if (n <= HOST_PLAN_MAX) {
     // Small graphs: one pass over the offsets on the host costs less than the
     // device planner's scratch allocation and readbacks.
     std::vector<int64_t> oh((size_t)n + 1);
@@ -469,7 +693,7 @@ hb_status init_impl(hb_ctx* c, const hb_csr* g, int32_t log2m, uint64_t seed, co
   c->n_nonempty = c->n_light + c->n_medium + c->n_hrows;
 
   // Reverse CSR for push activation of sparse passes (lane-group kernels only).
-  if (c->opt.frontier && c->opt.push && c->p <= 256 && n > 0) {
+  if (c->opt.frontier && c->opt.push && c->p <= 256 && n > 0 && !c->streamed) {
     if (dmalloc(&c->roff, (size_t)n + 1) != hipSuccess || dmalloc(&c->ridx, (size_t)m) != hipSuccess ||
         dmalloc(&c->act, (size_t)n) != hipSuccess ||
         dmalloc(&c->push_items, (size_t)n + (size_t)(m / hb::PUSH_CHUNK) + 1) != hipSuccess ||
@@ -675,6 +899,8 @@ void hb_default_options(hb_options* opt) {
   opt->graph_passes = 4;
   opt->neighbourhood = 0;
   opt->pairs = 1;
+  opt->stream_graph = 0;
+  opt->graph_budget = 0;
 }
 
 hb_status hb_init(hb_ctx** out, const hb_csr* g, int32_t log2m, uint64_t seed, const hb_options* opt,
@@ -826,17 +1052,26 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
   if (use_pairs) a.act = nullptr;
   hipError_t e = hipSuccess;
   if (timing) e = hipEventRecord(c->ev[0], c->stream);
-  if (e == hipSuccess && a.act)
+  if (c->streamed) {
+    if (e == hipSuccess) e = hb::launch_fill_zero(a.mod_cur, sizeof(uint64_t) * (size_t)c->n_blocks, c->stream);
+    if (e == hipSuccess && a.dmask_cur)
+      e = hb::launch_fill_zero(a.dmask_cur, sizeof(uint16_t) * (size_t)c->n, c->stream);
+    if (e == hipSuccess) e = streamed_pass(c, a, timing, info);
+  }
+  if (!c->streamed && e == hipSuccess && a.act)
     e = hb::launch_push(a.mod_prev, c->n_blocks, c->n, c->roff, c->ridx, c->push_items, c->push_count, c->act,
                         a.epoch, c->stream);
-  if (e == hipSuccess && use_pairs) e = hb::launch_pair_build(a, c->pb, pairs, c->push_items, c->push_count, c->stream);
-  if (e == hipSuccess) e = hb::launch_fill_zero(a.mod_cur, sizeof(uint64_t) * (size_t)c->n_blocks, c->stream);
-  if (e == hipSuccess && a.dmask_cur)
-    e = hb::launch_fill_zero(a.dmask_cur, sizeof(uint16_t) * (size_t)c->n, c->stream);
-  if (e == hipSuccess && timing) e = hipEventRecord(c->ev[1], c->stream);
-  if (e == hipSuccess)
-    e = use_pairs ? hb::launch_pair_pass(c->b, a, c->pb, pairs, c->stream, timing ? c->ev[2] : nullptr)
-                  : hb::launch_pass(c->b, a, c->stream, timing ? c->ev[2] : nullptr);
+  if (!c->streamed) {
+    if (e == hipSuccess && use_pairs)
+      e = hb::launch_pair_build(a, c->pb, pairs, c->push_items, c->push_count, c->stream);
+    if (e == hipSuccess) e = hb::launch_fill_zero(a.mod_cur, sizeof(uint64_t) * (size_t)c->n_blocks, c->stream);
+    if (e == hipSuccess && a.dmask_cur)
+      e = hb::launch_fill_zero(a.dmask_cur, sizeof(uint16_t) * (size_t)c->n, c->stream);
+    if (e == hipSuccess && timing) e = hipEventRecord(c->ev[1], c->stream);
+    if (e == hipSuccess)
+      e = use_pairs ? hb::launch_pair_pass(c->b, a, c->pb, pairs, c->stream, timing ? c->ev[2] : nullptr)
+                    : hb::launch_pass(c->b, a, c->stream, timing ? c->ev[2] : nullptr);
+  }
   if (e == hipSuccess && use_pairs)
     e = hipMemcpyAsync(c->npairs_host, c->pb.npairs, sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess && timing) e = hipEventRecord(c->ev[3], c->stream);
@@ -1034,6 +1269,9 @@ hb_status hb_stats(hb_ctx* c, hb_stats_t* s) {
   s->light_rows = c->n_light;
   s->reverse_built = c->roff ? 1 : 0;
   s->total_kernel_ms = c->total_ms;
+  s->streamed = c->streamed ? 1 : 0;
+  s->chunks = (int32_t)c->chunks.size();
+  s->chunk_bytes = c->streamed ? c->chunk_bytes : 0;
   return HB_OK;
 }
 

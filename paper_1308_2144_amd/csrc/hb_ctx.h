@@ -73,6 +73,15 @@ inline double alpha_for(int p) {
 
 }  // namespace hbh
 
+// One row chunk of a streamed graph: rows [r0, r1), arcs [e0, e1), and its
+// entries of the row lists (light [l0, l1), medium [m0, m1), heavy items
+// [i0, i1), heavy rows [h0, h1); the lists are sorted by row, so a chunk's
+// entries are contiguous).
+struct StreamChunk {
+  int64_t r0, r1, e0, e1;
+  int64_t l0, l1, m0, m1, i0, i1, h0, h1;
+};
+
 struct hb_ctx {
   int64_t n = 0, m = 0;
   int b = 0, p = 0;              // row width: p = 2^b bytes
@@ -158,6 +167,22 @@ struct hb_ctx {
   std::vector<hb_pass_info> hist;
   double total_ms = 0.0;
   bool failed = false;
+  // Streamed graphs (opt.stream_graph): the CSR stays in pinned host memory
+  // and is uploaded chunk by chunk into two staging buffers every pass.
+  bool streamed = false;
+  int64_t* host_off = nullptr;   // pinned, n+1
+  int32_t* host_idx = nullptr;   // pinned, m
+  std::vector<StreamChunk> chunks;
+  int64_t chunk_bytes = 0;       // capacity of each staging buffer
+  uint8_t* stage[2] = {nullptr, nullptr};
+  hipStream_t copy_stream = nullptr;
+  hipEvent_t up_ev[2] = {nullptr, nullptr};
+  hipEvent_t done_ev[2] = {nullptr, nullptr};
+  uint32_t* pred_mask = nullptr;      // n words: chunks (mod 32) holding an arc into the node
+  int64_t* chunk_rows = nullptr;      // first row of every chunk (device)
+  uint32_t* chunk_act = nullptr;      // chunk selection of a pass (device word)
+  uint32_t* chunk_act_host = nullptr; // pinned
+  bool masks_ready = false;
 };
 
 namespace hbh {

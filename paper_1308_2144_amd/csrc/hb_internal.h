@@ -211,6 +211,15 @@ hipError_t launch_chunk_graph(const int32_t* light, int64_t n_light, const int32
 hipError_t launch_set_slot(GraphDev* graphs, int32_t slot, const GraphDev& val, hipStream_t s);
 hipError_t launch_pack_u8(const uint8_t* src, uint8_t* dst, int64_t n_arena, int p, const int32_t* blk_graph,
                           const GraphDev* graphs, hipStream_t s);
+// Streamed graphs: sets bit `bit` of mask[w] for every successor w in
+// idx[0..count) (one chunk's arcs).
+hipError_t launch_pred_masks(const int32_t* idx, int64_t count, uint32_t bit, uint32_t* mask, hipStream_t s);
+// *act (zeroed here) receives the OR over the nodes whose bit is set in
+// mod_prev of mask[node] and the bit (chunk % 32) of the chunk holding the
+// node's own row; chunk_rows holds the first row of each of the n_chunks
+// chunks.
+hipError_t launch_chunk_activity(const uint64_t* mod_prev, int64_t n_words, const uint32_t* mask,
+                                 const int64_t* chunk_rows, int32_t n_chunks, uint32_t* act, hipStream_t s);
 // ev_mid (nullable) is recorded between the expand and merge kernels.
 hipError_t launch_pass(int log2m, const PassArgs& a, hipStream_t s, hipEvent_t ev_mid);
 hipError_t launch_finalize(int64_t n, const double* S, const double* H, const double* E,

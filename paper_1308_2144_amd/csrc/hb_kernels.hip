@@ -1364,6 +1364,49 @@ __global__ void k_fill_zero(uint4* p, size_t n16, uint8_t* tail, size_t ntail) {
     for (size_t i = threadIdx.x; i < ntail; i += blockDim.x) tail[i] = 0;
 }
 
+// --- streamed graphs ----------------------------------------------------------
+//
+// A streamed graph's arcs are uploaded in row chunks every pass.  While its
+// first pass streams every chunk, k_pred_masks records for every node w which
+// chunks hold an arc into w (bit c % 32 of mask[w] for chunk c).  A later
+// pass only needs the chunks that hold a row with a changed successor or a
+// row that changed itself (its write-back): k_chunk_activity ORs, over the
+// nodes changed in the previous pass, their masks and the bit of their own
+// chunk.  With more than 32 chunks a bit stands for every 32nd chunk, so the
+// selection is a superset of the chunks that have work.
+
+__global__ void k_pred_masks(const int32_t* __restrict__ idx, int64_t count, uint32_t bit, uint32_t* mask) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += stride) {
+    const int32_t w = idx[e];
+    if ((__ldg(mask + w) & bit) == 0u) atomicOr(mask + w, bit);
+  }
+}
+
+__global__ void k_chunk_activity(const uint64_t* __restrict__ mod_prev, int64_t n_words, const uint32_t* __restrict__ mask,
+                                 const int64_t* __restrict__ chunk_rows, int32_t n_chunks, uint32_t* act) {
+  uint32_t acc = 0u;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += stride) {
+    uint64_t word = mod_prev[i];
+    while (word) {
+      const int b = __ffsll((long long)word) - 1;
+      word &= word - 1ull;
+      const int64_t w = i * 64 + b;
+      // own chunk: the last c with chunk_rows[c] <= w
+      int32_t lo = 0, hi = n_chunks - 1;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (chunk_rows[mid] <= w) lo = mid; else hi = mid - 1;
+      }
+      acc |= mask[w] | (1u << (lo & 31));
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) acc |= __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0 && acc) atomicOr(act, acc);
+}
+
 // Algorithm 2 initialisation: c[v] = add(empty counter, v) written into both
 // buffers, one thread per 16-byte chunk of a counter (coalesced stores, no
 // separate zero fill); the first chunk's thread also zeroes S and H and
@@ -2196,6 +2239,21 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
   const size_t tail = bytes - n16 * 16;
   hipLaunchKernelGGL(k_fill_zero, dim3(grid_for((int64_t)n16, 256 * 8, 65536)), dim3(256), 0, s,
                      reinterpret_cast<uint4*>(p), n16, reinterpret_cast<uint8_t*>(p) + n16 * 16, tail);
+  return hipGetLastError();
+}
+
+hipError_t launch_pred_masks(const int32_t* idx, int64_t count, uint32_t bit, uint32_t* mask, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pred_masks, dim3(grid_for(count, 256 * 4, 65536)), dim3(256), 0, s, idx, count, bit, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_chunk_activity(const uint64_t* mod_prev, int64_t n_words, const uint32_t* mask,
+                                 const int64_t* chunk_rows, int32_t n_chunks, uint32_t* act, hipStream_t s) {
+  hipError_t e = launch_fill_zero(act, sizeof(uint32_t), s);
+  if (e != hipSuccess || n_words == 0) return e;
+  hipLaunchKernelGGL(k_chunk_activity, dim3(grid_for(n_words, 256, 8192)), dim3(256), 0, s, mod_prev, n_words, mask,
+                     chunk_rows, n_chunks, act);
   return hipGetLastError();
 }
 
