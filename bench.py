@@ -263,6 +263,36 @@ def bench_streamed(args, torch, hb, off, idx, w, seed, resident_ms, steps: int =
             "pass_ms": [round(p["expand_ms"] + p["push_ms"], 3) for p in ps]}
 
 
+def batch_roofline(recs, b):
+    """Roofline of the batched dense passes (persistent k_expand_p<b, false>)
+    from a pass-by-pass run: algorithmic bytes of each dense pass over the
+    rows it ran (list entry, offsets and change word: 28 B; own counter and
+    E, S, H: p + 24 B) and arcs scanned (id 4 B + successor counter p B),
+    plus p B per counter written and 26 B per changed row, divided by the
+    pass time (every kernel of the device pass, so a lower bound on the
+    expand kernel's rate).  Measured HBM traffic per dispatch from the
+    committed counters, when they match the kernel sources."""
+    p = 1 << b
+    dense = [r for r in recs if r["mode"] == 1]
+    if not dense:
+        return None
+    byts = [(28 + p + 24) * r["rows_loaded"] + (4 + p) * r["arcs_scanned"] + p * r["rows_written"]
+            + 26 * r["rows_changed"] for r in dense]
+    ms = [r["expand_ms"] for r in dense]
+    achieved = sum(byts) / (sum(ms) * 1e-3) / 1e9
+    kname = f"k_expand_p<{b}, false>"
+    tr = read_traffic(kname, "batch-4096")
+    return {"bound": "hbm", "kernel": kname, "launches": len(dense), "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "algorithmic_bytes_per_launch": sum(byts) // len(dense), "mean_pass_ms": round(sum(ms) / len(ms), 4),
+            "traffic": None if tr is None else tr["bytes"],
+            "traffic_counters": None if tr is None else {k: tr[k] for k in ("fetch_kib", "write_kib", "fetch_scale",
+                                                                            "write_scale")},
+            "traffic_over_algorithmic": None if tr is None else round(tr["bytes"] / (sum(byts) / len(dense)), 3),
+            "passes": [{"mode": r["mode"], "ms": round(r["expand_ms"], 3), "rows": r["rows_loaded"],
+                        "arcs": r["arcs_scanned"], "changed": r["rows_changed"]} for r in recs]}
+
+
 def bench_batch(args, torch, hb, plain_sample: int = 512):
     """Batched form on the 4096-graph workload: graphs/s of one batched
     context (reset + passes to convergence for every graph + centralities,
@@ -283,6 +313,7 @@ def bench_batch(args, torch, hb, plain_sample: int = 512):
     log(f"batch: autotune {tune} -> {tuned} in {time.time() - t:.1f}s")
     torch.cuda.synchronize()
     t = time.perf_counter()
+    opt.timing = 1  # pass times for hb_iterate passes (no effect on hb_run's graph replays)
     bt = hb.Batch(graphs, b, seeds, options=opt)
     torch.cuda.synchronize()
     init_s = time.perf_counter() - t
@@ -306,6 +337,14 @@ def bench_batch(args, torch, hb, plain_sample: int = 512):
     passes = bt.passes()
     regs = bt.split(bt.registers())
     harm = bt.split(outs[2].cpu().numpy())
+    # One more run pass by pass (hb_iterate): every pass's work counts over
+    # all graphs and its time (all kernels of the device pass, HIP events on
+    # the batch's stream), for the roofline of the dense passes.
+    bt.reset()
+    while not hb.hb_stats(bt._ctx)["converged"]:
+        hb.hb_iterate(bt._ctx)
+    recs = [hb.hb_pass_stats(bt._ctx, t) for t in range(hb.hb_stats(bt._ctx)["passes"])]
+    broof = batch_roofline(recs, b)
     bt.close()
     del outs
     row_opts = {}  # plain contexts keep the single-graph defaults (faster for them than the batch's tuning)
@@ -338,7 +377,7 @@ def bench_batch(args, torch, hb, plain_sample: int = 512):
         g.close()
     identical = not any(mismatch.values())
     # Cold plain runs (init, passes, centralities, free) on a smaller sample.
-    cold = sample[:64]
+    cold = sample[:min(64, len(sample))]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in cold:
@@ -360,7 +399,7 @@ def bench_batch(args, torch, hb, plain_sample: int = 512):
             "autotune": {"options": {k: tuned[k] for k in ("light_max", "heavy_min", "chunk", "wgs_per_cu",
                                                             "graph_passes", "dense_pct", "sparse_pct", "qdense", "push")},
                          **tune},
-            "mismatches_on_sample": mismatch}
+            "mismatches_on_sample": mismatch, "roofline": broof}
 
 
 def bench_ensemble(args, torch, hb, K: int = 8, b: int = 4, steps: int = 3):
@@ -696,6 +735,8 @@ def main():
     ap.add_argument("--slice", type=int, default=0)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
     ap.add_argument("--no-streamed", action="store_true", help="skip the host-streamed graph measurement")
+    ap.add_argument("--plain-sample", type=int, default=512,
+                    help="graphs of the batch also run one by one through plain contexts")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the multi-seed ensemble measurement")
     ap.add_argument("--ensemble-only", action="store_true", help="only the ensemble measurement (its own line)")
@@ -726,7 +767,7 @@ def main():
         print(json.dumps({"serving": bench_serve(args, torch, hb)}), flush=True)
         return
     if args.batch_only:
-        print(json.dumps({"batched": bench_batch(args, torch, hb)}), flush=True)
+        print(json.dumps({"batched": bench_batch(args, torch, hb, plain_sample=args.plain_sample)}), flush=True)
         return
     if args.ensemble_only:
         print(json.dumps({"ensemble": bench_ensemble(args, torch, hb)}), flush=True)
@@ -837,7 +878,7 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_batch:
         log("batched form ...")
-        out["batched"] = bench_batch(args, torch, hb)
+        out["batched"] = bench_batch(args, torch, hb, plain_sample=args.plain_sample)
         torch.cuda.empty_cache()
     if not args.no_extensions:
         log("weights, discount, neighbourhood function ...")

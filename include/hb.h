@@ -265,7 +265,9 @@ hb_status hb_pass_stats(hb_ctx* c, int32_t pass, hb_pass_info* info);
  * engine pass cap); hb_iterate runs one pass over all graphs; outputs of
  * hb_centralities / hb_get_accumulators / hb_get_registers are packed: graph
  * 0's n_0 nodes, then graph 1's, ... (sum n_i entries); hb_reset restarts with
- * the same seeds (hb_batch_reset changes them); hb_pass_stats is not kept. */
+ * the same seeds (hb_batch_reset changes them); hb_pass_stats is kept for
+ * passes run with hb_iterate (its work counts summed over all graphs; with
+ * opt.timing, expand_ms is the whole device pass), not for hb_run. */
 typedef struct {
   int64_t n;              /* nodes of the graph */
   int64_t packed_offset;  /* its first entry in packed outputs */

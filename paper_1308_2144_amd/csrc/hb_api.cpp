@@ -954,20 +954,44 @@ hb_status hb_iterate(hb_ctx* c, int64_t* n_modified) {
   if (n_modified) *n_modified = 0;
   if (c->converged) return HB_OK;
   if (c->n_graphs > 0) {
-    // One device-driven pass over every unconverged graph of the batch.
+    // One device-driven pass over every unconverged graph of the batch (its
+    // mode was planned on the device at the end of the previous pass and read
+    // back with the pass control).
     const int32_t t_before = c->t;
+    const int32_t mode = c->ctl_host->mode;
+    const bool timing = c->opt.timing != 0;
+    if (timing) HB_HIP(hipEventRecord(c->ev[0], c->stream));
     HB_HIP(hb::launch_device_pass(c->b, device_args(c), c->persist_wgs, c->push_items, c->push_count, c->n,
                                   c->stream));
+    if (timing) HB_HIP(hipEventRecord(c->ev[1], c->stream));
     st = read_ctl(c);
     if (st != HB_OK) return st;
     const size_t half = (size_t)hb::STAT_SLOTS * hb::STAT_K;
     HB_HIP(hipMemcpyAsync(c->stats_host, c->stats + (size_t)(t_before & 1) * half,
                           sizeof(unsigned long long) * half, hipMemcpyDeviceToHost, c->stream));
     HB_HIP(hipStreamSynchronize(c->stream));
-    int64_t chg = 0;
-    for (int sl = 0; sl < hb::STAT_SLOTS; ++sl) chg += (int64_t)c->stats_host[sl * hb::STAT_K + 3];
-    c->last_nmod = chg;
-    if (n_modified) *n_modified = chg;
+    unsigned long long sum[hb::STAT_K] = {};
+    for (int sl = 0; sl < hb::STAT_SLOTS; ++sl)
+      for (int k = 0; k < hb::STAT_SEEDS; ++k) sum[k] += c->stats_host[sl * hb::STAT_K + k];
+    hb_pass_info info{};
+    info.counters_gathered = (int64_t)sum[0];
+    info.rows_loaded = (int64_t)sum[1];
+    info.rows_written = (int64_t)sum[2];
+    info.rows_changed = (int64_t)sum[3];
+    info.arcs_scanned = (int64_t)sum[4];
+    info.slices_gathered = (int64_t)sum[5];
+    info.slices_changed = (int64_t)sum[6];
+    info.arcs_to_changed = c->roff ? (int64_t)sum[7] : -1;
+    info.mode = mode;
+    if (timing) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
+      info.expand_ms = ms;
+      c->total_ms += (double)ms;
+    }
+    c->hist.push_back(info);
+    c->last_nmod = info.rows_changed;
+    if (n_modified) *n_modified = info.rows_changed;
     return HB_OK;
   }
   hb_pass_info info{};
@@ -1277,8 +1301,7 @@ hb_status hb_stats(hb_ctx* c, hb_stats_t* s) {
 
 hb_status hb_pass_stats(hb_ctx* c, int32_t pass, hb_pass_info* info) {
   if (!c || !info) return fail(HB_EINVAL, "NULL argument");
-  if (c->n_graphs > 0) return fail(HB_EINVAL, "batched contexts keep no per-pass records");
-  if (pass < 0 || pass >= (int32_t)c->hist.size()) return fail(HB_EINVAL, "no such pass");
+  if (pass < 0 || pass >= (int32_t)c->hist.size()) return fail(HB_EINVAL, "no such pass record");
   *info = c->hist[(size_t)pass];
   return HB_OK;
 }

@@ -183,3 +183,31 @@ def test_mostly_empty_batches():
     opt, rep = hb.hb_batch_autotune([gg.empty(0)] * 6 + [gg.star(40)], 5, np.arange(7, dtype=np.uint64), sample=1)
     _log("autotune:", rep)
     assert rep["sample_graphs"] == 1
+
+
+def test_batch_pass_records_equal_the_oracle_sums():
+    """Passes run one by one (hb_iterate) keep per-pass records on a batched
+    context: pass t's changed counters are the sum over the graphs of the
+    oracle's changes in their pass t, and a dense pass scans every arc of
+    the graphs that have not converged."""
+    import paper_1308_2144_amd as hb
+
+    graphs = mixed_graphs(seed=7, count=16)
+    b = 5
+    seeds = np.arange(len(graphs), dtype=np.uint64) + 3
+    refs = [run_oracle(o, x, b, int(s)) for (o, x), s in zip(graphs, seeds)]
+    with hb.Batch(graphs, b, seeds, timing=1) as bt:
+        while not hb.hb_stats(bt._ctx)["converged"]:
+            hb.hb_iterate(bt._ctx)
+        T = hb.hb_stats(bt._ctx)["passes"]
+        recs = [hb.hb_pass_stats(bt._ctx, t) for t in range(T)]
+        assert list(bt.passes()) == [r["passes"] for r in refs]
+    assert T == max(r["passes"] for r in refs)
+    for t, rec in enumerate(recs):
+        want = sum(int(r["nmod"][t]) for r in refs if t < r["passes"])
+        assert rec["rows_changed"] == want, (t, rec["rows_changed"], want)
+        if rec["mode"] == 1:
+            arcs = sum(len(x) for (o, x), r in zip(graphs, refs) if t < r["passes"])
+            assert rec["arcs_scanned"] == arcs, t
+        assert rec["expand_ms"] > 0.0
+    _log("batch pass records:", [(r["mode"], r["rows_changed"]) for r in recs])
