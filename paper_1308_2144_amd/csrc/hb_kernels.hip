@@ -674,6 +674,124 @@ __device__ __forceinline__ void set_change_bits(uint64_t* mod_cur, int64_t row, 
   }
 }
 
+// Light rows of a single-graph pass that gathers only changed successors,
+// scanned wave-wide before any gather: the wavefront's lanes take the
+// successor ids of all its 64 rows as one run of consecutive arcs (lane j of
+// a round takes arc j; its row is found by a binary search over the rows'
+// arc offsets held in the lanes), look up the change bits, and queue every
+// changed successor with its row's slot, in arc order, so that each row's
+// entries are contiguous.  Then each lane group finishes its rows in turn as
+// in light_wave, issuing the row's own counter and accumulators together with
+// its queued successors: one memory round trip per row instead of three
+// (ids, then change bits, then counters).  Returns false, having written
+// nothing but the queue, when the queue cannot hold all changed successors;
+// the caller then runs the rows one by one.
+template <int B>
+__device__ __forceinline__ bool light_wave_scanned(const PassArgs& A, QEnt* qw, int64_t lw, int lane) {
+  constexpr int P = 1 << B;
+  constexpr int G = P / 16;
+  constexpr int W = 64 / G;
+  const int gl = lane % G;
+  const int grp = lane / G;
+  const int64_t i = lw * 64 + lane;
+  int64_t row = 0, s = 0;
+  int32_t deg = 0;
+  bool own_mod = false, need = false;
+  if (i < A.n_light) {
+    row = A.light[i];
+    s = A.off[row];
+    deg = (int32_t)(A.off[row + 1] - s);
+    row_flags<false>(A, row, own_mod, need);
+  }
+  const uint64_t needs = __ballot(need);
+  const uint64_t mods = __ballot(own_mod);
+  const int32_t dn = need ? deg : 0;
+  int32_t incl = dn;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  const int32_t base = incl - dn;  // first arc of this lane's row in the wave's run
+  const int32_t total = __shfl(incl, 63);
+  const uint64_t below = lanes_below(lane);
+  int nq = 0;
+  for (int32_t k0 = 0; k0 < total; k0 += 64 * U) {
+    int32_t w[U];
+    uint32_t m[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t j = k0 + u * 64 + lane;
+      // row slot of arc j: the last lane whose base is <= j
+      int lo = 0, hi = 63;
+#pragma unroll
+      for (int step = 0; step < 6; ++step) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (__shfl(base, mid) <= j) lo = mid; else hi = mid - 1;
+      }
+      const int64_t rs = __shfl(s, lo);
+      const int32_t rb = __shfl(base, lo);
+      w[u] = j < total ? ld_stream(A.idx + rs + (j - rb)) : -1;
+      m[u] = (uint32_t)lo << 16;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t cm = change_mask<B>(A, w[u]);
+      const bool hit = cm != 0u;
+      const uint64_t hb = __ballot(hit);
+      const int cnt = __popcll(hb);
+      if (nq + cnt > QCAP) return false;  // uniform over the wavefront
+      if (hit) {
+        QEnt ent;
+        ent.w = w[u];
+        ent.msk = cm | m[u];
+        qw[nq + __popcll(hb & below)] = ent;
+      }
+      nq += cnt;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  // Each lane's row: its entries are [qs, qe) (binary search over the
+  // queue's row slots, which are nondecreasing).
+  int qs = 0;
+  {
+    int lo = 0, hi = nq;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((int)(qw[mid].msk >> 16) < lane) lo = mid + 1; else hi = mid;
+    }
+    qs = lo;
+  }
+  int qe = __shfl_down(qs, 1);
+  if (lane == 63) qe = nq;
+  Counts c{};
+  for (int r = 0; r < G; ++r) {
+    const int rl = r * W + grp;
+    // shuffles first, with every lane active (a lane of a group that skips
+    // its row must still supply its values to the group that reads them)
+    const int64_t rrow = __shfl(row, rl);
+    const int32_t rd = __shfl(deg, rl);
+    const int rqs = __shfl(qs, rl);
+    const int rqe = __shfl(qe, rl);
+    if (!((needs >> rl) & 1ull)) continue;  // uniform over the group
+    const bool rmod = ((mods >> rl) & 1ull) != 0ull;
+    const bool got = rqe > rqs;
+    if (gl == 0) {
+      c.arcs += (uint32_t)rd;
+      c.gath += (uint32_t)(rqe - rqs);
+    }
+    // A row without a changed successor that did not change before keeps
+    // its counter (lazy_row): nothing to read or write.
+    if (!got && !rmod) continue;
+    const RowPre pre = preload<B>(A, rrow, gl);
+    SplitAcc acc{zero4(), zero4()};
+    drain<B>(A, qw, rqs, rqe, 1, gl, (uint32_t)rrow, acc, c);
+    (void)finish_row<B, false>(A, rrow, unsplit(acc), got, pre, rmod, gl, grp, c);
+  }
+  flush_counts(A, c, lw, lane);
+  return true;
+}
+
 // 64 consecutive entries of the light-row list per wavefront; entry
 // q*W + grp goes to lane group grp in round q.
 template <int B, bool Q, bool MG, int FL = FL_PLAIN>
@@ -688,6 +806,10 @@ __device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, int64_t 
       const int32_t g = A.chunk_graph[lw];
       if (g >= 0 && A.graphs[g].done) return;
     }
+  }
+  if constexpr (Q && !MG && FL == FL_PLAIN) {
+    if (A.mode != MODE_FIRST && A.mode != MODE_DENSE && light_wave_scanned<B>(A, qw, lw, lane)) return;
+    __builtin_amdgcn_wave_barrier();
   }
   const int64_t i = lw * 64 + lane;
   int64_t row = 0, s = 0, deg = 0;
