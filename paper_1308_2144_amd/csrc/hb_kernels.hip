@@ -792,6 +792,128 @@ __device__ __forceinline__ bool light_wave_scanned(const PassArgs& A, QEnt* qw, 
   return true;
 }
 
+// Row slot (lane) of arc j of a wavefront's run of consecutive arcs, given
+// each lane's first arc `base` (nondecreasing over the lanes): the last lane
+// whose base is <= j.  Needs every lane active.
+__device__ __forceinline__ int arc_slot(int32_t base, int32_t j) {
+  int lo = 0, hi = 63;
+#pragma unroll
+  for (int step = 0; step < 6; ++step) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (__shfl(base, mid) <= j) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Direct gather of one row whose successor ids were staged in LDS
+// (ids[k .. e)), p >= 64: as gather, slots past the end load the row's own
+// counter.
+template <int B>
+__device__ __forceinline__ uint4 gather_staged(const PassArgs& A, const int32_t* ids, int k, int e, int gl,
+                                               uint32_t own, bool& got, Counts& c) {
+  constexpr int P = 1 << B;
+  SplitAcc acc{zero4(), zero4()};
+  const uint8_t* base = A.cur + gl * 16;
+  const uint32_t n = k < e ? (uint32_t)(e - k) : 0u;
+  got |= n > 0u;
+  c.slices += n;
+  if (gl == 0) c.gath += n;
+  for (; k < e; k += U) {
+    const int rem = e - 1 - k;
+    int32_t w[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ok[u] = u <= rem;
+      w[u] = ids[k + (u < rem ? u : rem)];
+    }
+    uint4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t src = ok[u] ? (uint32_t)w[u] : own;
+      v[u] = *reinterpret_cast<const uint4*>(base + (size_t)src * P);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) fold(acc, v[u]);
+  }
+  return unsplit(acc);
+}
+
+// Successor ids a wavefront stages in LDS in dense passes (the queue's bytes).
+constexpr int ID_CAP = 2 * QCAP;
+
+// Light rows of a single-graph pass that gathers every successor (p >= 64):
+// the successor ids of all 64 rows are loaded wave-wide first (consecutive
+// arcs on consecutive lanes, rows found by arc_slot) into LDS, then each lane
+// group gathers its rows' successor counters with the ids taken from LDS,
+// the row's own counter and accumulators issued with them: one memory round
+// trip per row instead of two (ids, then counters).  Returns false, having
+// written nothing but LDS, when the rows have more arcs than the buffer
+// holds; the caller then runs the rows one by one.
+template <int B>
+__device__ __forceinline__ bool light_wave_staged(const PassArgs& A, int32_t* ids, int64_t lw, int lane) {
+  constexpr int G = (1 << B) / 16;
+  constexpr int W = 64 / G;
+  const int gl = lane % G;
+  const int grp = lane / G;
+  const int64_t i = lw * 64 + lane;
+  int64_t row = 0, s = 0;
+  int32_t deg = 0;
+  bool own_mod = false, need = false;
+  if (i < A.n_light) {
+    row = A.light[i];
+    s = A.off[row];
+    deg = (int32_t)(A.off[row + 1] - s);
+    row_flags<false>(A, row, own_mod, need);
+  }
+  const uint64_t needs = __ballot(need);
+  const uint64_t mods = __ballot(own_mod);
+  const int32_t dn = need ? deg : 0;
+  int32_t incl = dn;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  const int32_t base = incl - dn;
+  const int32_t total = __shfl(incl, 63);
+  if (total > ID_CAP) return false;  // uniform over the wavefront
+  for (int32_t k0 = 0; k0 < total; k0 += 64 * U) {
+    int32_t w[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t j = k0 + u * 64 + lane;
+      const int lo = arc_slot(base, j);
+      const int64_t rs = __shfl(s, lo);
+      const int32_t rb = __shfl(base, lo);
+      w[u] = j < total ? ld_stream(A.idx + rs + (j - rb)) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t j = k0 + u * 64 + lane;
+      if (j < total) ids[j] = w[u];
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  Counts c{};
+  for (int r = 0; r < G; ++r) {
+    const int rl = r * W + grp;
+    const int64_t rrow = __shfl(row, rl);
+    const int32_t rb = __shfl(base, rl);
+    const int32_t rd = __shfl(deg, rl);
+    if (((needs >> rl) & 1ull) != 0ull) {  // uniform over the group
+      const bool rmod = ((mods >> rl) & 1ull) != 0ull;
+      const RowPre pre = preload<B>(A, rrow, gl);
+      bool got = false;
+      const uint4 acc = gather_staged<B>(A, ids, rb, rb + rd, gl, (uint32_t)rrow, got, c);
+      if (gl == 0) c.arcs += (uint32_t)rd;
+      (void)finish_row<B, false>(A, rrow, acc, got, pre, rmod, gl, grp, c);
+    }
+  }
+  flush_counts(A, c, lw, lane);
+  return true;
+}
+
 // 64 consecutive entries of the light-row list per wavefront; entry
 // q*W + grp goes to lane group grp in round q.
 template <int B, bool Q, bool MG, int FL = FL_PLAIN>
@@ -809,6 +931,10 @@ __device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, int64_t 
   }
   if constexpr (Q && !MG && FL == FL_PLAIN) {
     if (A.mode != MODE_FIRST && A.mode != MODE_DENSE && light_wave_scanned<B>(A, qw, lw, lane)) return;
+    __builtin_amdgcn_wave_barrier();
+  }
+  if constexpr (!Q && !MG && FL == FL_PLAIN && B >= 6) {
+    if (qw && light_wave_staged<B>(A, reinterpret_cast<int32_t*>(qw), lw, lane)) return;
     __builtin_amdgcn_wave_barrier();
   }
   const int64_t i = lw * 64 + lane;
@@ -1038,7 +1164,12 @@ __device__ __forceinline__ bool queued_mode(const PassArgs& A) {
 
 template <int B, int FL = FL_PLAIN>
 __global__ HB_EXPAND_ATTR void k_expand(PassArgs A) {
-  expand_item<B, false, false, FL>(A, nullptr, blockIdx.x);
+  if constexpr (B >= 6 && FL == FL_PLAIN) {
+    __shared__ QEnt qbuf[4][QCAP];  // successor ids of light rows (light_wave_staged)
+    expand_item<B, false, false, FL>(A, qbuf[threadIdx.x >> 6], blockIdx.x);
+  } else {
+    expand_item<B, false, false, FL>(A, nullptr, blockIdx.x);
+  }
 }
 
 template <int B, int FL = FL_PLAIN>
