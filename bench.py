@@ -209,38 +209,55 @@ def bench_streamed(args, torch, hb, off, idx, w, seed, resident_ms, steps: int =
     """The same workload with the CSR kept in pinned host memory and streamed
     to the device in row chunks every pass (graph budget `budget` bytes: two
     staging buffers of budget/2), against the resident run: each step =
-    reset + passes to convergence + centralities into device memory.  Also a
-    plain pinned-host-to-device copy of 1 GiB, the host link's reference
-    rate."""
+    reset + passes to convergence + centralities into device memory.  Run
+    with the arcs as they are and kept compressed (decoded on the device),
+    and a plain pinned-host-to-device copy of 1 GiB, the host link's
+    reference rate."""
     n, m = len(off) - 1, len(idx)
     dev = torch.device("cuda:0")
     outs = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(4)]
     stream = torch.cuda.current_stream().cuda_stream
-    t = time.perf_counter()
-    g = hb.HyperBall(off, idx, w["log2m"], seed, stream=stream, stream_graph=1, graph_budget=budget, timing=1)
-    init_s = time.perf_counter() - t
-    st = g.stats()
 
-    def step():
-        g.reset(seed)
-        p = g.run()
-        hb.hb_centralities(g._ctx, *outs, True)
-        return p
+    def leg(compress):
+        t = time.perf_counter()
+        g = hb.HyperBall(off, idx, w["log2m"], seed, stream=stream, stream_graph=1, graph_budget=budget,
+                         stream_compress=compress, timing=1)
+        init_s = time.perf_counter() - t
+        st = g.stats()
 
-    step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    host = 0
-    scanned = 0
-    for _ in range(steps):
-        passes = step()
-        ps = [g.pass_stats(t) for t in range(passes)]
-        host += sum(p["host_bytes"] for p in ps)
-        scanned += sum(p["arcs_scanned"] for p in ps)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    g.close()
-    del outs
+        def step():
+            g.reset(seed)
+            p = g.run()
+            hb.hb_centralities(g._ctx, *outs, True)
+            return p
+
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        host = 0
+        scanned = 0
+        for _ in range(steps):
+            passes = step()
+            ps = [g.pass_stats(t) for t in range(passes)]
+            host += sum(p["host_bytes"] for p in ps)
+            scanned += sum(p["arcs_scanned"] for p in ps)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        cen = [o.cpu() for o in outs]
+        g.close()
+        return cen, {"chunks": st["chunks"], "init_s": round(init_s, 2), "passes": passes,
+                     "host_graph_bytes": st["host_graph_bytes"],
+                     "chunks_run_per_pass": [p["chunks_run"] for p in ps],
+                     "ms_per_step": dt * 1e3, "slowdown_vs_resident": dt * 1e3 / resident_ms,
+                     "edge_visits_per_s": scanned / steps / dt,
+                     "host_bytes_per_step": host // steps, "host_link_GBps": host / steps / dt / 1e9,
+                     "pass_ms": [round(p["expand_ms"] + p["push_ms"], 3) for p in ps]}
+
+    raw_cen, raw = leg(0)
+    zip_cen, comp = leg(1)
+    comp["centralities_identical_to_raw"] = all(torch.equal(a, b) for a, b in zip(raw_cen, zip_cen))
+    comp["bytes_per_arc"] = round((comp["host_graph_bytes"] - 8 * (n + 1)) / max(m, 1), 3)
+    del outs, raw_cen, zip_cen
     src = torch.empty(1 << 30, dtype=torch.uint8).pin_memory()
     dst = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
     dst.copy_(src, non_blocking=True)
@@ -253,14 +270,8 @@ def bench_streamed(args, torch, hb, off, idx, w, seed, resident_ms, steps: int =
     del src, dst
     return {"workload": f"{args.workload} with the CSR in pinned host memory, streamed in row chunks "
                         f"(graph budget {budget >> 20} MiB: two staging buffers of {budget >> 21} MiB)",
-            "chunks": st["chunks"], "init_s": round(init_s, 2), "passes": passes,
-            "chunks_run_per_pass": [p["chunks_run"] for p in ps],
-            "ms_per_step": dt * 1e3, "resident_ms_per_step": resident_ms,
-            "slowdown_vs_resident": dt * 1e3 / resident_ms,
-            "edge_visits_per_s": scanned / steps / dt,
-            "host_bytes_per_step": host // steps, "host_link_GBps": host / steps / dt / 1e9,
-            "h2d_copy_GBps": h2d,
-            "pass_ms": [round(p["expand_ms"] + p["push_ms"], 3) for p in ps]}
+            **raw, "resident_ms_per_step": resident_ms, "h2d_copy_GBps": h2d,
+            "compressed": comp}
 
 
 def batch_roofline(recs, b):

@@ -120,7 +120,15 @@ typedef struct {
  *              single-seed context and log2m <= 8; push, pairs are ignored.
  *   graph_budget  device bytes for the graph (<= 0: no limit).  A streamed
  *              graph stages chunks of at most graph_budget / 2 bytes
- *              (<= 0: 256 MiB each); a row must fit one chunk. */
+ *              (<= 0: 256 MiB each); a row must fit one chunk.
+ *   stream_compress  streamed graphs: 1 keeps the arcs in host memory
+ *              compressed (each row's successors sorted, then blocks of 32
+ *              arcs coded as the first id and the differences between
+ *              consecutive ids in 7-bit variable-length bytes) and decodes
+ *              each uploaded chunk on the device: fewer bytes over the host
+ *              link for the same results.  Each staging buffer then has a
+ *              second buffer beside it for the chunk's coded form.  Ignored
+ *              when the graph is not streamed. */
 typedef struct {
   int32_t frontier;
   int32_t light_max;
@@ -139,6 +147,7 @@ typedef struct {
   int32_t pairs;
   int32_t stream_graph;
   int64_t graph_budget;
+  int32_t stream_compress;
 } hb_options;
 
 void hb_default_options(hb_options* opt);
@@ -201,6 +210,8 @@ typedef struct {
   int32_t streamed;        /* 1 if the CSR lives in host memory and is streamed */
   int32_t chunks;          /* row chunks of a streamed graph */
   int64_t chunk_bytes;     /* capacity of each of its two staging buffers */
+  int64_t host_graph_bytes; /* pinned host bytes holding a streamed graph */
+  int32_t compressed;      /* 1 if its arcs are kept compressed */
 } hb_stats_t;
 
 hb_status hb_stats(hb_ctx* c, hb_stats_t* s);

@@ -50,7 +50,7 @@ class hb_options(ctypes.Structure):
                 ("slice", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32),
                 ("graph_passes", ctypes.c_int32), ("neighbourhood", ctypes.c_int32),
                 ("pairs", ctypes.c_int32), ("stream_graph", ctypes.c_int32),
-                ("graph_budget", ctypes.c_int64)]
+                ("graph_budget", ctypes.c_int64), ("stream_compress", ctypes.c_int32)]
 
 
 class hb_stats_t(ctypes.Structure):
@@ -60,7 +60,8 @@ class hb_stats_t(ctypes.Structure):
                 ("heavy_chunks", ctypes.c_int64), ("medium_rows", ctypes.c_int64),
                 ("light_rows", ctypes.c_int64), ("reverse_built", ctypes.c_int32),
                 ("total_kernel_ms", ctypes.c_double), ("streamed", ctypes.c_int32),
-                ("chunks", ctypes.c_int32), ("chunk_bytes", ctypes.c_int64)]
+                ("chunks", ctypes.c_int32), ("chunk_bytes", ctypes.c_int64),
+                ("host_graph_bytes", ctypes.c_int64), ("compressed", ctypes.c_int32)]
 
 
 class hb_pass_info(ctypes.Structure):

@@ -65,6 +65,9 @@ void release(hb_ctx* c) {
     if (c->done_ev[i]) (void)hipEventDestroy(c->done_ev[i]);
     (void)hipFree(c->stage[i]);
   }
+  for (int i = 0; i < 2; ++i) (void)hipFree(c->cstage[i]);
+  if (c->host_cbytes) (void)hipHostFree(c->host_cbytes);
+  if (c->host_boff) (void)hipHostFree(c->host_boff);
   if (c->host_off) (void)hipHostFree(c->host_off);
   if (c->host_idx) (void)hipHostFree(c->host_idx);
   if (c->chunk_act_host) (void)hipHostFree(c->chunk_act_host);
@@ -417,6 +420,83 @@ int host_csr_check(const T* off, const int32_t* idx, int64_t n, int64_t m) {
   return 0;
 }
 
+void put_varint(std::vector<uint8_t>& out, uint32_t v) {
+  while (v >= 0x80u) {
+    out.push_back((uint8_t)(v | 0x80u));
+    v >>= 7;
+  }
+  out.push_back((uint8_t)v);
+}
+
+// Compressed streamed arcs: every row's successors sorted (the union is
+// order-free, so results do not change), then each chunk's arcs coded in
+// blocks of STREAM_BLOCK_ARCS consecutive arcs: the first id, then the
+// zigzag-coded differences to the previous id, all as variable-length
+// integers of 7 bits per byte (small differences inside a sorted row take one
+// or two bytes).  Chunks are coded in parallel; the bytes and block offsets
+// go to pinned memory, the ids stay only as the pinned copy's sorted order.
+hb_status compress_chunks(hb_ctx* c) {
+  const int64_t nch = (int64_t)c->chunks.size();
+  std::vector<std::vector<uint8_t>> bytes((size_t)nch);
+  std::vector<std::vector<uint32_t>> boff((size_t)nch);
+  bool too_big = false;
+  const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(16, nch));
+  std::vector<std::thread> th;
+  for (int k = 0; k < nt; ++k)
+    th.emplace_back([&, k] {
+      for (int64_t ci = k; ci < nch; ci += nt) {
+        const StreamChunk& ch = c->chunks[(size_t)ci];
+        for (int64_t v = ch.r0; v < ch.r1; ++v) std::sort(c->host_idx + c->host_off[v], c->host_idx + c->host_off[v + 1]);
+        std::vector<uint8_t>& out = bytes[(size_t)ci];
+        std::vector<uint32_t>& bo = boff[(size_t)ci];
+        out.reserve((size_t)(ch.e1 - ch.e0) * 3);
+        for (int64_t e = ch.e0; e < ch.e1; e += hb::STREAM_BLOCK_ARCS) {
+          bo.push_back((uint32_t)out.size());
+          const int64_t end = std::min<int64_t>(e + hb::STREAM_BLOCK_ARCS, ch.e1);
+          uint32_t prev = (uint32_t)c->host_idx[e];
+          put_varint(out, prev);
+          for (int64_t a = e + 1; a < end; ++a) {
+            const uint32_t x = (uint32_t)c->host_idx[a];
+            const int32_t d = (int32_t)(x - prev);
+            put_varint(out, ((uint32_t)d << 1) ^ (uint32_t)(d >> 31));
+            prev = x;
+          }
+        }
+        bo.push_back((uint32_t)out.size());
+        if (out.size() > 0xfffff000u) too_big = true;
+      }
+    });
+  for (auto& t : th) t.join();
+  if (too_big) return fail(HB_ENOMEM, "a compressed chunk exceeds 4 GiB; lower graph_budget");
+  int64_t cb = 0, bo = 0, cap = 0;
+  for (int64_t ci = 0; ci < nch; ++ci) {
+    StreamChunk& ch = c->chunks[(size_t)ci];
+    ch.nb = (int64_t)boff[(size_t)ci].size() - 1;
+    ch.bo_at = bo;
+    ch.cb_at = cb;
+    ch.cb_len = (int64_t)bytes[(size_t)ci].size();
+    bo += ch.nb + 1;
+    cb += (ch.cb_len + 3) / 4 * 4;
+    cap = std::max<int64_t>(cap, (int64_t)align256(sizeof(uint32_t) * (size_t)(ch.nb + 1)) + (ch.cb_len + 3) / 4 * 4);
+  }
+  HB_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->host_cbytes), (size_t)std::max<int64_t>(cb, 4), hipHostMallocDefault));
+  HB_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->host_boff), sizeof(uint32_t) * (size_t)std::max<int64_t>(bo, 1),
+                       hipHostMallocDefault));
+  for (int64_t ci = 0; ci < nch; ++ci) {
+    const StreamChunk& ch = c->chunks[(size_t)ci];
+    std::memcpy(c->host_cbytes + ch.cb_at, bytes[(size_t)ci].data(), (size_t)ch.cb_len);
+    std::memset(c->host_cbytes + ch.cb_at + ch.cb_len, 0, (size_t)((ch.cb_len + 3) / 4 * 4 - ch.cb_len));
+    std::memcpy(c->host_boff + ch.bo_at, boff[(size_t)ci].data(), sizeof(uint32_t) * (size_t)(ch.nb + 1));
+  }
+  c->cstage_bytes = std::max<int64_t>(cap, 256);
+  c->compressed = true;
+  c->host_graph_bytes = (int64_t)sizeof(int64_t) * (c->n + 1) + cb + (int64_t)sizeof(uint32_t) * bo;
+  // the raw arcs are no longer needed on the host
+  (void)hipHostFree(c->host_idx);
+  c->host_idx = nullptr;
+  return HB_OK;
+}
+
 // A streamed graph (paper Sec. 5.1: the graph is read from outside the
 // memory that holds the counters): a pinned host copy of the CSR, row lists
 // built on the host, and row chunks that fit a staging buffer.  Device
@@ -509,6 +589,11 @@ hb_status setup_streamed(hb_ctx* c, const hb_csr* g) {
   }
   hb_status st = upload_plan(c, light, medium, items, hrows);
   if (st != HB_OK) return st;
+  c->host_graph_bytes = (int64_t)sizeof(int64_t) * (n + 1) + (int64_t)sizeof(int32_t) * m;
+  if (c->opt.stream_compress) {
+    st = compress_chunks(c);
+    if (st != HB_OK) return st;
+  }
   const int32_t nch = (int32_t)c->chunks.size();
   std::vector<int64_t> first((size_t)nch + 1, n);
   for (int32_t i = 0; i < nch; ++i) first[(size_t)i] = c->chunks[(size_t)i].r0;
@@ -522,6 +607,9 @@ hb_status setup_streamed(hb_ctx* c, const hb_csr* g) {
   for (int i = 0; i < 2; ++i) {
     if (dmalloc(&c->stage[i], (size_t)cap) != hipSuccess)
       return fail(HB_ENOMEM, "cannot allocate a staging buffer of " + std::to_string(cap) + " bytes");
+    if (c->compressed && dmalloc(&c->cstage[i], (size_t)c->cstage_bytes) != hipSuccess)
+      return fail(HB_ENOMEM, "cannot allocate a compressed staging buffer of " + std::to_string(c->cstage_bytes) +
+                                 " bytes");
     HB_HIP(hipEventCreateWithFlags(&c->up_ev[i], hipEventDisableTiming));
     HB_HIP(hipEventCreateWithFlags(&c->done_ev[i], hipEventDisableTiming));
     HB_HIP(hipEventRecord(c->done_ev[i], c->stream));
@@ -567,10 +655,26 @@ hipError_t streamed_pass(hb_ctx* c, const hb::PassArgs& a, bool timing, hb_pass_
     const size_t ibytes = sizeof(int32_t) * (size_t)(ch.e1 - ch.e0);
     e = hipStreamWaitEvent(c->copy_stream, c->done_ev[s], 0);
     if (e == hipSuccess) e = hipMemcpyAsync(soff, c->host_off + ch.r0, obytes, hipMemcpyHostToDevice, c->copy_stream);
-    if (e == hipSuccess && ibytes)
-      e = hipMemcpyAsync(sidx, c->host_idx + ch.e0, ibytes, hipMemcpyHostToDevice, c->copy_stream);
+    size_t sent = obytes;
+    uint32_t* cboff = nullptr;
+    uint8_t* cbytes = nullptr;
+    if (c->compressed) {
+      cboff = reinterpret_cast<uint32_t*>(c->cstage[s]);
+      cbytes = c->cstage[s] + align256(sizeof(uint32_t) * (size_t)(ch.nb + 1));
+      const size_t bbytes = sizeof(uint32_t) * (size_t)(ch.nb + 1);
+      const size_t cb = (size_t)((ch.cb_len + 3) / 4 * 4);
+      if (e == hipSuccess) e = hipMemcpyAsync(cboff, c->host_boff + ch.bo_at, bbytes, hipMemcpyHostToDevice, c->copy_stream);
+      if (e == hipSuccess && cb)
+        e = hipMemcpyAsync(cbytes, c->host_cbytes + ch.cb_at, cb, hipMemcpyHostToDevice, c->copy_stream);
+      sent += bbytes + cb;
+    } else {
+      if (e == hipSuccess && ibytes)
+        e = hipMemcpyAsync(sidx, c->host_idx + ch.e0, ibytes, hipMemcpyHostToDevice, c->copy_stream);
+      sent += ibytes;
+    }
     if (e == hipSuccess) e = hipEventRecord(c->up_ev[s], c->copy_stream);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->up_ev[s], 0);
+    if (e == hipSuccess && c->compressed) e = hb::launch_decode_chunk(cboff, cbytes, ch.e1 - ch.e0, sidx, c->stream);
     hb::PassArgs b = a;
     b.off = soff - ch.r0;
     b.idx = sidx - ch.e0;
@@ -586,7 +690,7 @@ hipError_t streamed_pass(hb_ctx* c, const hb::PassArgs& a, bool timing, hb_pass_
     if (e == hipSuccess && build_masks)
       e = hb::launch_pred_masks(sidx, ch.e1 - ch.e0, 1u << (ci & 31), c->pred_mask, c->stream);
     if (e == hipSuccess) e = hipEventRecord(c->done_ev[s], c->stream);
-    info.host_bytes += (int64_t)(obytes + ibytes);
+    info.host_bytes += (int64_t)sent;
     info.chunks_run += 1;
   }
   if (e == hipSuccess && build_masks) c->masks_ready = true;
@@ -901,6 +1005,7 @@ void hb_default_options(hb_options* opt) {
   opt->pairs = 1;
   opt->stream_graph = 0;
   opt->graph_budget = 0;
+  opt->stream_compress = 0;
 }
 
 hb_status hb_init(hb_ctx** out, const hb_csr* g, int32_t log2m, uint64_t seed, const hb_options* opt,
@@ -1296,6 +1401,8 @@ hb_status hb_stats(hb_ctx* c, hb_stats_t* s) {
   s->streamed = c->streamed ? 1 : 0;
   s->chunks = (int32_t)c->chunks.size();
   s->chunk_bytes = c->streamed ? c->chunk_bytes : 0;
+  s->host_graph_bytes = c->streamed ? c->host_graph_bytes : 0;
+  s->compressed = c->compressed ? 1 : 0;
   return HB_OK;
 }
 

@@ -80,6 +80,9 @@ inline double alpha_for(int p) {
 struct StreamChunk {
   int64_t r0, r1, e0, e1;
   int64_t l0, l1, m0, m1, i0, i1, h0, h1;
+  // compressed chunks (opt.stream_compress): blocks, and where the chunk's
+  // block offsets and bytes start in the pinned host arrays
+  int64_t nb, bo_at, cb_at, cb_len;
 };
 
 struct hb_ctx {
@@ -183,6 +186,15 @@ struct hb_ctx {
   uint32_t* chunk_act = nullptr;      // chunk selection of a pass (device word)
   uint32_t* chunk_act_host = nullptr; // pinned
   bool masks_ready = false;
+  // Compressed streamed arcs (opt.stream_compress): per chunk, blocks of
+  // STREAM_BLOCK_ARCS arcs coded as variable-length deltas, decoded on the
+  // device after the upload.
+  bool compressed = false;
+  uint8_t* host_cbytes = nullptr;   // pinned: every chunk's bytes, each 4-byte aligned
+  uint32_t* host_boff = nullptr;    // pinned: every chunk's block offsets (blocks + 1 each)
+  int64_t cstage_bytes = 0;         // capacity of each compressed staging buffer
+  uint8_t* cstage[2] = {nullptr, nullptr};
+  int64_t host_graph_bytes = 0;     // pinned bytes holding the streamed graph
 };
 
 namespace hbh {

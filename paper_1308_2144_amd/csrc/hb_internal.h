@@ -220,6 +220,13 @@ hipError_t launch_pred_masks(const int32_t* idx, int64_t count, uint32_t bit, ui
 // chunks.
 hipError_t launch_chunk_activity(const uint64_t* mod_prev, int64_t n_words, const uint32_t* mask,
                                  const int64_t* chunk_rows, int32_t n_chunks, uint32_t* act, hipStream_t s);
+// Compressed streamed chunks: arcs in blocks of STREAM_BLOCK_ARCS, each
+// block its first id then zigzag differences, all as 7-bit variable-length
+// integers; boff (blocks + 1 entries) gives each block's first byte.  Decodes
+// n_arcs ids into ids.  The byte buffer must be readable up to boff[blocks]
+// rounded up to 4 bytes.
+constexpr int STREAM_BLOCK_ARCS = 32;
+hipError_t launch_decode_chunk(const uint32_t* boff, const uint8_t* bytes, int64_t n_arcs, int32_t* ids, hipStream_t s);
 // ev_mid (nullable) is recorded between the expand and merge kernels.
 hipError_t launch_pass(int log2m, const PassArgs& a, hipStream_t s, hipEvent_t ev_mid);
 hipError_t launch_finalize(int64_t n, const double* S, const double* H, const double* E,

@@ -1660,6 +1660,54 @@ __global__ void k_chunk_activity(const uint64_t* __restrict__ mod_prev, int64_t 
   if ((threadIdx.x & 63) == 0 && acc) atomicOr(act, acc);
 }
 
+// Compressed streamed chunks: a chunk's arcs are cut into blocks of
+// STREAM_BLOCK_ARCS consecutive arcs (across row boundaries); a block is its first
+// successor id as a variable-length integer (7 bits per byte, low bits first,
+// high bit set on every byte but the last) followed by the zigzag-coded
+// differences between consecutive ids, coded the same way.  boff[b] is the
+// byte offset of block b in the chunk's bytes.  Each workgroup first copies
+// the bytes of its 256 blocks into LDS (one coalesced copy), then each thread
+// decodes one block into ids.
+constexpr int DECODE_LDS = 256 * STREAM_BLOCK_ARCS * 5;  // bytes of 256 blocks at worst (5 per id)
+
+// At most 5 bytes (a 32-bit value), so a damaged stream cannot run on.
+__device__ __forceinline__ uint32_t read_varint(const uint8_t* p, int& at) {
+  uint32_t v = 0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const uint32_t byte = p[at++];
+    v |= (byte & 0x7fu) << (7 * k);
+    if (!(byte & 0x80u)) break;
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_decode_chunk(const uint32_t* __restrict__ boff, const uint8_t* __restrict__ bytes,
+                                                      int64_t n_arcs, int64_t n_blocks, int32_t* __restrict__ ids) {
+  __shared__ uint32_t buf[DECODE_LDS / 4 + 2];  // + the partial words at both ends
+  const int64_t b0 = (int64_t)blockIdx.x * 256;
+  const int64_t b1 = b0 + 256 < n_blocks ? b0 + 256 : n_blocks;
+  const uint32_t lo = boff[b0], hi = boff[b1];
+  // the workgroup's bytes [lo, hi) into LDS, in 4-byte words from lo rounded down
+  const uint32_t w0 = lo >> 2, w1 = (hi + 3) >> 2;
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(bytes);
+  for (uint32_t w = w0 + threadIdx.x; w < w1; w += 256) buf[w - w0] = src[w];
+  __syncthreads();
+  const int64_t b = b0 + threadIdx.x;
+  if (b >= b1) return;
+  const uint8_t* lds = reinterpret_cast<const uint8_t*>(buf);
+  int at = (int)(boff[b] - (w0 << 2));
+  const int64_t a0 = b * STREAM_BLOCK_ARCS;
+  const int64_t a1 = a0 + STREAM_BLOCK_ARCS < n_arcs ? a0 + STREAM_BLOCK_ARCS : n_arcs;
+  uint32_t cur = read_varint(lds, at);
+  ids[a0] = (int32_t)cur;
+  for (int64_t a = a0 + 1; a < a1; ++a) {
+    const uint32_t z = read_varint(lds, at);
+    cur += (z >> 1) ^ (0u - (z & 1u));  // zigzag: 2d for d >= 0, -2d-1 for d < 0
+    ids[a] = (int32_t)cur;
+  }
+}
+
 // Algorithm 2 initialisation: c[v] = add(empty counter, v) written into both
 // buffers, one thread per 16-byte chunk of a counter (coalesced stores, no
 // separate zero fill); the first chunk's thread also zeroes S and H and
@@ -2507,6 +2555,13 @@ hipError_t launch_chunk_activity(const uint64_t* mod_prev, int64_t n_words, cons
   if (e != hipSuccess || n_words == 0) return e;
   hipLaunchKernelGGL(k_chunk_activity, dim3(grid_for(n_words, 256, 8192)), dim3(256), 0, s, mod_prev, n_words, mask,
                      chunk_rows, n_chunks, act);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_chunk(const uint32_t* boff, const uint8_t* bytes, int64_t n_arcs, int32_t* ids, hipStream_t s) {
+  if (n_arcs == 0) return hipSuccess;
+  const int64_t nb = (n_arcs + STREAM_BLOCK_ARCS - 1) / STREAM_BLOCK_ARCS;
+  hipLaunchKernelGGL(k_decode_chunk, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, boff, bytes, n_arcs, nb, ids);
   return hipGetLastError();
 }
 

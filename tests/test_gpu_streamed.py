@@ -20,16 +20,22 @@ def _streamed(off, idx, b, seed, budget, **opt):
     got = run_hb(off, idx, b, seed, stream_graph=1, graph_budget=budget, timing=1, **opt)
     st = got["stats"]
     assert st["streamed"] == 1 and st["chunk_bytes"] == budget // 2 // 256 * 256
+    assert st["compressed"] == int(bool(opt.get("stream_compress", 0)))
     return got
 
 
+@pytest.fixture(scope="module")
+def s20():
+    off, idx = gg.rmat(20, 16, seed=2, transpose=True, relabel=True)
+    return off, idx, run_oracle(off, idx, 6, 42)
+
+
 @pytest.mark.timeout(600)
-def test_streamed_rmat_s20_against_oracle():
+def test_streamed_rmat_s20_against_oracle(s20):
     """R-MAT scale 20 (edge factor 16, relabelled, transposed), log2m 6, in
     chunks of 4 MiB (about 18 chunks), against the whole oracle run."""
-    off, idx = gg.rmat(20, 16, seed=2, transpose=True, relabel=True)
+    off, idx, ref = s20
     got = _streamed(off, idx, 6, 42, 8 << 20)
-    ref = run_oracle(off, idx, 6, 42)
     compare(got, ref, "streamed s20")
     ps = got["pass_stats"]
     chunks = got["stats"]["chunks"]
@@ -40,6 +46,22 @@ def test_streamed_rmat_s20_against_oracle():
     # first and dense passes stream every chunk: the whole CSR once, plus the
     # 256-byte alignment of each chunk's offsets
     assert ps[0]["chunks_run"] == chunks and csr <= ps[0]["host_bytes"] <= csr + 8 * chunks
+
+
+@pytest.mark.timeout(600)
+def test_streamed_compressed_rmat_s20_against_oracle(s20):
+    """The same graph with the streamed arcs kept compressed (rows sorted,
+    blocks of 32 arcs coded as differences) and decoded on the device: the
+    oracle's results, fewer bytes over the host link."""
+    off, idx, ref = s20
+    got = _streamed(off, idx, 6, 42, 8 << 20, stream_compress=1)
+    compare(got, ref, "streamed compressed s20")
+    st = got["stats"]
+    csr = 8 * len(off) + 4 * len(idx)
+    ps = got["pass_stats"]
+    _log("compressed s20: host bytes", st["host_graph_bytes"], "of", csr, "; first pass sent", ps[0]["host_bytes"])
+    assert st["host_graph_bytes"] < 0.9 * csr
+    assert ps[0]["chunks_run"] == st["chunks"] and ps[0]["host_bytes"] < 0.9 * csr
 
 
 @pytest.mark.timeout(600)
@@ -54,6 +76,7 @@ def test_streamed_skips_chunks_in_sparse_passes():
     off, idx = gg.directed_path(3000)        # pass t changes nodes 0 .. n-t-2 only
     got = _streamed(off, idx, 4, 3, 16 << 10)
     compare(got, run_oracle(off, idx, 4, 3), "streamed path")
+    compare(_streamed(off, idx, 4, 3, 16 << 10, stream_compress=1), run_oracle(off, idx, 4, 3), "compressed path")
     ps = got["pass_stats"]
     assert got["stats"]["chunks"] >= 4
     assert min(p["chunks_run"] for p in ps[1:]) <= 2, [p["chunks_run"] for p in ps]
@@ -75,6 +98,24 @@ def test_streamed_equals_resident(b):
             assert np.array_equal(got[k], res[k]), k
         assert [p["rows_changed"] for p in got["pass_stats"]] == [p["rows_changed"] for p in res["pass_stats"]]
     check(off, idx, b, 5, "streamed rmat14", stream_graph=1, graph_budget=256 << 10, **opt)
+    check(off, idx, b, 5, "compressed rmat14", stream_graph=1, graph_budget=256 << 10, stream_compress=1, **opt)
+
+
+def test_streamed_compressed_unsorted_rows_and_duplicates():
+    """Compression sorts each row's successors and codes differences, zero
+    for repeated arcs and negative across row and block boundaries: rows
+    given in shuffled order with duplicate arcs and self-loops, and ids near
+    2^31 / 64 apart, give the oracle's results."""
+    rng = np.random.default_rng(17)
+    n = 5000
+    off, idx = gg.random_digraph(n, 14 * n, seed=18, self_loops=True, dedup=False)
+    idx = idx.copy()
+    for v in range(0, n, 3):                       # shuffle some rows in place
+        a, b_ = off[v], off[v + 1]
+        idx[a:b_] = rng.permutation(idx[a:b_])
+    for cmp in (0, 1):
+        got = _streamed(off, idx, 5, 2, 64 << 10, stream_compress=cmp)
+        compare(got, run_oracle(off, idx, 5, 2), f"unsorted compress={cmp}")
 
 
 def test_streamed_budget_decides_and_refusals():
