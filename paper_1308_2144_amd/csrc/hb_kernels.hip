@@ -1397,6 +1397,112 @@ __device__ __forceinline__ void light_codes(const PassArgs& A, uint32_t* lds, in
   flush_counts(A, c, lw, lane);
 }
 
+// What a round leaves for a row's own lane to finish: the row's register
+// sum in two exact parts, its empty registers and its mask of changed slices
+// (0: the row did not change).
+struct RowSum {
+  double big, small;
+  int32_t zeros;
+  uint32_t msk;
+};
+
+// Light rows of a single-graph first pass: as light_codes, with the work that
+// is per row rather than per register done once per wavefront instead of
+// once per round.  Each lane hashes its own row's node and loads the row's
+// estimate and accumulators up front (consecutive list entries); each round's
+// lane groups fold, pack, compare and sum their row's registers and leave a
+// RowSum in LDS; then every lane finishes its own row at once (estimator,
+// accumulators, slice mask, change bit).  Same values, in the same order, as
+// finish_row.
+template <int B>
+__device__ __forceinline__ void light_codes_1(const PassArgs& A, uint32_t* lds, RowSum* sums, int64_t lw, int lane) {
+  constexpr int P = 1 << B;
+  constexpr int G = P / 16;
+  constexpr int W = 64 / G;
+  const int gl = lane % G;
+  const int grp = lane / G;
+  const int64_t i = lw * 64 + lane;
+  const bool valid = i < A.n_light;
+  int64_t row = 0, s = 0, deg = 0;
+  uint32_t code = 0u;
+  double e0 = 0.0, s0 = 0.0, h0 = 0.0;
+  if (valid) {
+    row = A.light[i];
+    s = A.off[row];
+    deg = A.off[row + 1] - s;
+    e0 = ld_stream(A.E + row);
+    s0 = ld_stream(A.S + row);
+    h0 = ld_stream(A.H + row);
+    code = singleton_code<B>((uint64_t)row, A.seed);
+  }
+  const uint64_t live = __ballot(valid);
+  uint32_t* regs = lds + grp * P;
+  const GraphKey key{0, A.seed};
+  Counts c{};
+  for (int r = 0; r < G; ++r) {
+    const int rl = r * W + grp;
+    const int64_t rrow = __shfl(row, rl);
+    const int64_t rs = __shfl(s, rl);
+    const int64_t rd = __shfl(deg, rl);
+    const uint32_t rcode = __shfl(code, rl);
+    const bool on = ((live >> rl) & 1ull) != 0ull;
+    if (on) fold_codes<B>(A, regs, rs + gl, rs + rd, G, key);
+    wave_sync();
+    if (on) {
+      const uint4 own = code_slice(rcode, gl);
+      const uint4 acc = take_slice(regs, gl);
+      const bool got = rd > 0;
+      const uint4 a = got ? bmax(acc, own) : own;
+      const bool diff = got && differs(a, own);
+      const uint64_t bal = __ballot(diff);
+      const uint32_t msk = (uint32_t)((bal >> (grp * G)) & ((1ull << G) - 1ull));
+      RowSum out{0.0, 0.0, 0, msk};
+      if (msk != 0u) {  // uniform over the group
+        st_stream(reinterpret_cast<uint4*>(A.nxt + (size_t)rrow * P + (size_t)gl * 16), a);
+        const Parts pr = reg_parts(a);
+        double big = pr.big, small = pr.small;
+        int V = pr.zeros;
+#pragma unroll
+        for (int o = 1; o < G; o <<= 1) {
+          big += __shfl_xor(big, o);
+          small += __shfl_xor(small, o);
+          V += __shfl_xor(V, o);
+        }
+        out.big = big;
+        out.small = small;
+        out.zeros = V;
+      }
+      if (gl == 0) {
+        sums[rl] = out;
+        c.gath += (uint32_t)rd;
+        c.arcs += (uint32_t)rd;
+      }
+    }
+    wave_sync();
+  }
+  bool chg = false;
+  if (valid) {
+    const RowSum rs = sums[lane];
+    c.load += 1u;
+    chg = rs.msk != 0u;
+    if (chg) {
+      c.write += 1u;
+      c.chg += 1u;
+      c.sch += (uint32_t)__popc(rs.msk);
+      if (A.roff) c.pairs += (uint32_t)(A.roff[row + 1] - A.roff[row]);
+      const double En = estimate(rs.big, rs.small, rs.zeros, A.alpha_pp, (double)P, A.lc);
+      const double delta = En - e0;
+      const double d = A.d;
+      st_stream(A.S + row, s0 + d * delta);
+      st_stream(A.H + row, h0 + delta / d);
+      st_stream(A.E + row, En);
+      if (A.dmask_cur) A.dmask_cur[row] = (uint16_t)rs.msk;
+    }
+  }
+  set_change_bits(A.mod_cur, row, chg, lane);
+  flush_counts(A, c, lw, lane);
+}
+
 // One medium row per wavefront: all 64 lanes fold its arcs.
 template <int B, bool MG>
 __device__ __forceinline__ void medium_codes(const PassArgs& A, uint32_t* lds, int64_t mi, int lane) {
@@ -1454,8 +1560,8 @@ __device__ __forceinline__ void heavy_codes(const PassArgs& A, uint32_t* lds, in
 
 // One work item, numbered as in expand_item: [heavy chunks][medium rows][light rows].
 template <int B, bool MG>
-__device__ __forceinline__ void codes_item(const PassArgs& A, uint32_t (*regs)[CODE_WORDS], int64_t b, int lane,
-                                           int wave) {
+__device__ __forceinline__ void codes_item(const PassArgs& A, uint32_t (*regs)[CODE_WORDS], RowSum (*sums)[64],
+                                           int64_t b, int lane, int wave) {
   if (b == 0)
     for (int i = threadIdx.x; i < STAT_SLOTS * STAT_K; i += blockDim.x) A.stats_next[i] = 0ull;
   if (b < A.n_items) {
@@ -1471,16 +1577,22 @@ __device__ __forceinline__ void codes_item(const PassArgs& A, uint32_t (*regs)[C
   }
   b -= med_wgs;
   const int64_t lw = b * 4 + wave;
-  if (lw * 64 < A.n_light) light_codes<B, MG>(A, regs[wave], lw, lane);
+  if (lw * 64 < A.n_light) {
+    if constexpr (MG)
+      light_codes<B, MG>(A, regs[wave], lw, lane);
+    else
+      light_codes_1<B>(A, regs[wave], sums[wave], lw, lane);
+  }
 }
 
 template <int B>
 __global__ HB_EXPAND_ATTR void k_expand_codes(PassArgs A) {
   __shared__ uint32_t regs[4][CODE_WORDS];
+  __shared__ RowSum sums[4][64];
   uint4* z = reinterpret_cast<uint4*>(&regs[0][0]);
   for (int i = threadIdx.x; i < CODE_WORDS; i += 256) z[i] = zero4();  // 4 waves x CODE_WORDS words
   __syncthreads();
-  codes_item<B, false>(A, regs, blockIdx.x, threadIdx.x & 63, threadIdx.x >> 6);
+  codes_item<B, false>(A, regs, sums, blockIdx.x, threadIdx.x & 63, threadIdx.x >> 6);
 }
 
 // Persistent form for the first device-driven pass of a batched context (a
@@ -1505,7 +1617,7 @@ __global__ HB_PERSIST_ATTR void k_expand_codes_p(PassArgs A0) {
     if (k >= tk.count) break;
     int64_t b0, b1;
     ticket_items(tk, K, k, &b0, &b1);
-    for (int64_t b = b0; b < b1; ++b) codes_item<B, true>(A, regs, b, threadIdx.x & 63, threadIdx.x >> 6);
+    for (int64_t b = b0; b < b1; ++b) codes_item<B, true>(A, regs, nullptr, b, threadIdx.x & 63, threadIdx.x >> 6);
   }
 }
 
