@@ -641,6 +641,12 @@ __device__ __forceinline__ void flush_counts(const PassArgs& A, Counts c, int64_
 
 __device__ __forceinline__ uint64_t lanes_below(int lane) { return (1ull << lane) - 1ull; }
 
+// Makes a wavefront's LDS writes visible to its other lanes.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Whether a row reads its own counter only after its gather found a changed
 // successor: in the queued passes that gather changed successors only, for
 // rows whose counter did not change in the previous pass (such a row with no
@@ -674,6 +680,78 @@ __device__ __forceinline__ void set_change_bits(uint64_t* mod_cur, int64_t row, 
   }
 }
 
+// Light rows of single-graph passes finish in two steps.  Per round, the
+// row's lane group does what is per register: the write-back rule, change
+// detection and the register sum (finish_group), and leaves a RowSum in LDS;
+// after the rounds every lane finishes its own row, all 64 at once: the
+// estimator, the accumulators, the slice mask, the change bit and the counts
+// (finish_lane).  Same values in the same order as finish_row, with the
+// per-row work run once per wavefront instead of once per round by the
+// groups' leader lanes.
+struct RowSum {
+  double big, small;
+  int32_t zeros;
+  uint32_t msk;  // changed slices; 0: the row did not change
+};
+
+template <int B>
+__device__ __forceinline__ void finish_group(const PassArgs& A, int64_t row, uint4 acc, bool got, uint4 own,
+                                             bool own_mod, int gl, int grp, RowSum* slot) {
+  constexpr int P = 1 << B;
+  constexpr int G = P / 16;
+  const uint4 a = got ? bmax(acc, own) : own;
+  const bool diff = got && differs(a, own);
+  const uint64_t bal = __ballot(diff);
+  const uint32_t msk = (uint32_t)((bal >> (grp * G)) & ((1ull << G) - 1ull));
+  if (msk != 0u || own_mod) st_stream(reinterpret_cast<uint4*>(A.nxt + (size_t)row * P + (size_t)gl * 16), a);
+  RowSum out{0.0, 0.0, 0, msk};
+  if (msk != 0u) {  // uniform over the group
+    const Parts pr = reg_parts(a);
+    double big = pr.big, small = pr.small;
+    int V = pr.zeros;
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+      big += __shfl_xor(big, o);
+      small += __shfl_xor(small, o);
+      V += __shfl_xor(V, o);
+    }
+    out.big = big;
+    out.small = small;
+    out.zeros = V;
+  }
+  if (gl == 0) *slot = out;
+}
+
+// The row's own lane, after the rounds: `done` if its group finished the row
+// (e0, s0, h0 = its E, S, H as before the pass).  Must be called by the whole
+// wavefront (the change bits are combined per bitmap word).
+template <int B>
+__device__ __forceinline__ void finish_lane(const PassArgs& A, int64_t row, bool done, bool own_mod,
+                                            const RowSum* sums, int lane, double e0, double s0, double h0,
+                                            Counts& c) {
+  constexpr int P = 1 << B;
+  bool chg = false;
+  if (done) {
+    const RowSum rs = sums[lane];
+    chg = rs.msk != 0u;
+    c.load += 1u;
+    c.write += (chg || own_mod) ? 1u : 0u;
+    if (chg) {
+      c.chg += 1u;
+      c.sch += (uint32_t)__popc(rs.msk);
+      if (A.roff) c.pairs += (uint32_t)(A.roff[row + 1] - A.roff[row]);
+      const double En = estimate(rs.big, rs.small, rs.zeros, A.alpha_pp, (double)P, A.lc);
+      const double delta = En - e0;
+      const double d = A.d;
+      st_stream(A.S + row, s0 + d * delta);
+      st_stream(A.H + row, h0 + delta / d);
+      st_stream(A.E + row, En);
+      if (A.dmask_cur) A.dmask_cur[row] = (uint16_t)rs.msk;
+    }
+  }
+  set_change_bits(A.mod_cur, row, chg, lane);
+}
+
 // Light rows of a single-graph pass that gathers only changed successors,
 // scanned wave-wide before any gather: the wavefront's lanes take the
 // successor ids of all its 64 rows as one run of consecutive arcs (lane j of
@@ -687,7 +765,7 @@ __device__ __forceinline__ void set_change_bits(uint64_t* mod_cur, int64_t row, 
 // nothing but the queue, when the queue cannot hold all changed successors;
 // the caller then runs the rows one by one.
 template <int B>
-__device__ __forceinline__ bool light_wave_scanned(const PassArgs& A, QEnt* qw, int64_t lw, int lane) {
+__device__ __forceinline__ bool light_wave_scanned(const PassArgs& A, QEnt* qw, RowSum* sums, int64_t lw, int lane) {
   constexpr int P = 1 << B;
   constexpr int G = P / 16;
   constexpr int W = 64 / G;
@@ -764,6 +842,14 @@ __device__ __forceinline__ bool light_wave_scanned(const PassArgs& A, QEnt* qw, 
   }
   int qe = __shfl_down(qs, 1);
   if (lane == 63) qe = nq;
+  // the lane's own row: finished by its group unless it keeps its counter
+  const bool done = need && (qe > qs || own_mod);
+  double e0 = 0.0, s0 = 0.0, h0 = 0.0;
+  if (done) {
+    e0 = ld_stream(A.E + row);
+    s0 = ld_stream(A.S + row);
+    h0 = ld_stream(A.H + row);
+  }
   Counts c{};
   for (int r = 0; r < G; ++r) {
     const int rl = r * W + grp;
@@ -783,11 +869,13 @@ __device__ __forceinline__ bool light_wave_scanned(const PassArgs& A, QEnt* qw, 
     // A row without a changed successor that did not change before keeps
     // its counter (lazy_row): nothing to read or write.
     if (!got && !rmod) continue;
-    const RowPre pre = preload<B>(A, rrow, gl);
+    const uint4 own = ld_stream(reinterpret_cast<const uint4*>(A.cur + (size_t)rrow * P + (size_t)gl * 16));
     SplitAcc acc{zero4(), zero4()};
     drain<B>(A, qw, rqs, rqe, 1, gl, (uint32_t)rrow, acc, c);
-    (void)finish_row<B, false>(A, rrow, unsplit(acc), got, pre, rmod, gl, grp, c);
+    finish_group<B>(A, rrow, unsplit(acc), got, own, rmod, gl, grp, sums + rl);
   }
+  wave_sync();
+  finish_lane<B>(A, row, done, own_mod, sums, lane, e0, s0, h0, c);
   flush_counts(A, c, lw, lane);
   return true;
 }
@@ -851,8 +939,10 @@ constexpr int ID_CAP = 2 * QCAP;
 // written nothing but LDS, when the rows have more arcs than the buffer
 // holds; the caller then runs the rows one by one.
 template <int B>
-__device__ __forceinline__ bool light_wave_staged(const PassArgs& A, int32_t* ids, int64_t lw, int lane) {
-  constexpr int G = (1 << B) / 16;
+__device__ __forceinline__ bool light_wave_staged(const PassArgs& A, int32_t* ids, RowSum* sums, int64_t lw,
+                                                  int lane) {
+  constexpr int P = 1 << B;
+  constexpr int G = P / 16;
   constexpr int W = 64 / G;
   const int gl = lane % G;
   const int grp = lane / G;
@@ -878,6 +968,12 @@ __device__ __forceinline__ bool light_wave_staged(const PassArgs& A, int32_t* id
   const int32_t base = incl - dn;
   const int32_t total = __shfl(incl, 63);
   if (total > ID_CAP) return false;  // uniform over the wavefront
+  double e0 = 0.0, s0 = 0.0, h0 = 0.0;
+  if (need) {
+    e0 = ld_stream(A.E + row);
+    s0 = ld_stream(A.S + row);
+    h0 = ld_stream(A.H + row);
+  }
   for (int32_t k0 = 0; k0 < total; k0 += 64 * U) {
     int32_t w[U];
 #pragma unroll
@@ -903,13 +999,15 @@ __device__ __forceinline__ bool light_wave_staged(const PassArgs& A, int32_t* id
     const int32_t rd = __shfl(deg, rl);
     if (((needs >> rl) & 1ull) != 0ull) {  // uniform over the group
       const bool rmod = ((mods >> rl) & 1ull) != 0ull;
-      const RowPre pre = preload<B>(A, rrow, gl);
+      const uint4 own = ld_stream(reinterpret_cast<const uint4*>(A.cur + (size_t)rrow * P + (size_t)gl * 16));
       bool got = false;
       const uint4 acc = gather_staged<B>(A, ids, rb, rb + rd, gl, (uint32_t)rrow, got, c);
       if (gl == 0) c.arcs += (uint32_t)rd;
-      (void)finish_row<B, false>(A, rrow, acc, got, pre, rmod, gl, grp, c);
+      finish_group<B>(A, rrow, acc, got, own, rmod, gl, grp, sums + rl);
     }
   }
+  wave_sync();
+  finish_lane<B>(A, row, need, own_mod, sums, lane, e0, s0, h0, c);
   flush_counts(A, c, lw, lane);
   return true;
 }
@@ -917,7 +1015,7 @@ __device__ __forceinline__ bool light_wave_staged(const PassArgs& A, int32_t* id
 // 64 consecutive entries of the light-row list per wavefront; entry
 // q*W + grp goes to lane group grp in round q.
 template <int B, bool Q, bool MG, int FL = FL_PLAIN>
-__device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, int64_t lw, int lane) {
+__device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, RowSum* sums, int64_t lw, int lane) {
   constexpr int P = 1 << B;
   constexpr int G = P / 16;
   constexpr int W = 64 / G;
@@ -930,11 +1028,11 @@ __device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, int64_t 
     }
   }
   if constexpr (Q && !MG && FL == FL_PLAIN) {
-    if (A.mode != MODE_FIRST && A.mode != MODE_DENSE && light_wave_scanned<B>(A, qw, lw, lane)) return;
+    if (A.mode != MODE_FIRST && A.mode != MODE_DENSE && light_wave_scanned<B>(A, qw, sums, lw, lane)) return;
     __builtin_amdgcn_wave_barrier();
   }
   if constexpr (!Q && !MG && FL == FL_PLAIN && B >= 6) {
-    if (qw && light_wave_staged<B>(A, reinterpret_cast<int32_t*>(qw), lw, lane)) return;
+    if (qw && light_wave_staged<B>(A, reinterpret_cast<int32_t*>(qw), sums, lw, lane)) return;
     __builtin_amdgcn_wave_barrier();
   }
   const int64_t i = lw * 64 + lane;
@@ -1067,7 +1165,7 @@ __device__ __forceinline__ void heavy_chunk(const PassArgs& A, QEnt* qw, int64_t
 // gather (slice, edge and sparse passes, or dense passes on request) over
 // the direct one.
 template <int B, bool Q, bool MG, int FL = FL_PLAIN>
-__device__ __forceinline__ void expand_item(const PassArgs& A, QEnt* qw, int64_t b) {
+__device__ __forceinline__ void expand_item(const PassArgs& A, QEnt* qw, RowSum* sums, int64_t b) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   if (b == 0)
@@ -1085,7 +1183,7 @@ __device__ __forceinline__ void expand_item(const PassArgs& A, QEnt* qw, int64_t
   }
   b -= med_wgs;
   const int64_t lw = b * 4 + wave;
-  if (lw * 64 < A.n_light) light_wave<B, Q, MG, FL>(A, qw, lw, lane);
+  if (lw * 64 < A.n_light) light_wave<B, Q, MG, FL>(A, qw, sums, lw, lane);
 }
 
 __device__ __forceinline__ int64_t pass_items(const PassArgs& A) {
@@ -1166,16 +1264,22 @@ template <int B, int FL = FL_PLAIN>
 __global__ HB_EXPAND_ATTR void k_expand(PassArgs A) {
   if constexpr (B >= 6 && FL == FL_PLAIN) {
     __shared__ QEnt qbuf[4][QCAP];  // successor ids of light rows (light_wave_staged)
-    expand_item<B, false, false, FL>(A, qbuf[threadIdx.x >> 6], blockIdx.x);
+    __shared__ RowSum sums[4][64];
+    expand_item<B, false, false, FL>(A, qbuf[threadIdx.x >> 6], sums[threadIdx.x >> 6], blockIdx.x);
   } else {
-    expand_item<B, false, false, FL>(A, nullptr, blockIdx.x);
+    expand_item<B, false, false, FL>(A, nullptr, nullptr, blockIdx.x);
   }
 }
 
 template <int B, int FL = FL_PLAIN>
 __global__ HB_EXPAND_ATTR void k_expand_q(PassArgs A) {
   __shared__ QEnt qbuf[4][QCAP];
-  expand_item<B, true, false, FL>(A, qbuf[threadIdx.x >> 6], blockIdx.x);
+  if constexpr (FL == FL_PLAIN) {
+    __shared__ RowSum sums[4][64];  // light_wave_scanned
+    expand_item<B, true, false, FL>(A, qbuf[threadIdx.x >> 6], sums[threadIdx.x >> 6], blockIdx.x);
+  } else {
+    expand_item<B, true, false, FL>(A, qbuf[threadIdx.x >> 6], nullptr, blockIdx.x);
+  }
 }
 
 // Persistent form for device-driven passes: a fixed grid whose workgroups
@@ -1199,7 +1303,7 @@ __global__ HB_PERSIST_ATTR void k_expand_p(PassArgs A0) {
     if (k >= tk.count) break;
     int64_t b0, b1;
     ticket_items(tk, K, k, &b0, &b1);
-    for (int64_t b = b0; b < b1; ++b) expand_item<B, Q, true>(A, Q ? qbuf[threadIdx.x >> 6] : nullptr, b);
+    for (int64_t b = b0; b < b1; ++b) expand_item<B, Q, true>(A, Q ? qbuf[threadIdx.x >> 6] : nullptr, nullptr, b);
   }
 }
 
@@ -1250,11 +1354,6 @@ __global__ __launch_bounds__(256) void k_merge(PassArgs A0) {
 // counters writes.
 
 constexpr int CODE_WORDS = 1024;  // LDS words per wavefront: (64 / G) rows x p registers
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
 
 // Code of node v's singleton counter: register index j (the hash's top B
 // bits) and value rho+ of the remaining bits, as the counters are initialised.
@@ -1397,23 +1496,9 @@ __device__ __forceinline__ void light_codes(const PassArgs& A, uint32_t* lds, in
   flush_counts(A, c, lw, lane);
 }
 
-// What a round leaves for a row's own lane to finish: the row's register
-// sum in two exact parts, its empty registers and its mask of changed slices
-// (0: the row did not change).
-struct RowSum {
-  double big, small;
-  int32_t zeros;
-  uint32_t msk;
-};
-
-// Light rows of a single-graph first pass: as light_codes, with the work that
-// is per row rather than per register done once per wavefront instead of
-// once per round.  Each lane hashes its own row's node and loads the row's
-// estimate and accumulators up front (consecutive list entries); each round's
-// lane groups fold, pack, compare and sum their row's registers and leave a
-// RowSum in LDS; then every lane finishes its own row at once (estimator,
-// accumulators, slice mask, change bit).  Same values, in the same order, as
-// finish_row.
+// Light rows of a single-graph first pass: as light_codes, finished in two
+// steps (finish_group, finish_lane); each lane also hashes its own row's node
+// once, and loads the row's estimate and accumulators, up front.
 template <int B>
 __device__ __forceinline__ void light_codes_1(const PassArgs& A, uint32_t* lds, RowSum* sums, int64_t lw, int lane) {
   constexpr int P = 1 << B;
@@ -1449,57 +1534,16 @@ __device__ __forceinline__ void light_codes_1(const PassArgs& A, uint32_t* lds, 
     if (on) fold_codes<B>(A, regs, rs + gl, rs + rd, G, key);
     wave_sync();
     if (on) {
-      const uint4 own = code_slice(rcode, gl);
       const uint4 acc = take_slice(regs, gl);
-      const bool got = rd > 0;
-      const uint4 a = got ? bmax(acc, own) : own;
-      const bool diff = got && differs(a, own);
-      const uint64_t bal = __ballot(diff);
-      const uint32_t msk = (uint32_t)((bal >> (grp * G)) & ((1ull << G) - 1ull));
-      RowSum out{0.0, 0.0, 0, msk};
-      if (msk != 0u) {  // uniform over the group
-        st_stream(reinterpret_cast<uint4*>(A.nxt + (size_t)rrow * P + (size_t)gl * 16), a);
-        const Parts pr = reg_parts(a);
-        double big = pr.big, small = pr.small;
-        int V = pr.zeros;
-#pragma unroll
-        for (int o = 1; o < G; o <<= 1) {
-          big += __shfl_xor(big, o);
-          small += __shfl_xor(small, o);
-          V += __shfl_xor(V, o);
-        }
-        out.big = big;
-        out.small = small;
-        out.zeros = V;
-      }
+      finish_group<B>(A, rrow, acc, rd > 0, code_slice(rcode, gl), false, gl, grp, sums + rl);
       if (gl == 0) {
-        sums[rl] = out;
         c.gath += (uint32_t)rd;
         c.arcs += (uint32_t)rd;
       }
     }
     wave_sync();
   }
-  bool chg = false;
-  if (valid) {
-    const RowSum rs = sums[lane];
-    c.load += 1u;
-    chg = rs.msk != 0u;
-    if (chg) {
-      c.write += 1u;
-      c.chg += 1u;
-      c.sch += (uint32_t)__popc(rs.msk);
-      if (A.roff) c.pairs += (uint32_t)(A.roff[row + 1] - A.roff[row]);
-      const double En = estimate(rs.big, rs.small, rs.zeros, A.alpha_pp, (double)P, A.lc);
-      const double delta = En - e0;
-      const double d = A.d;
-      st_stream(A.S + row, s0 + d * delta);
-      st_stream(A.H + row, h0 + delta / d);
-      st_stream(A.E + row, En);
-      if (A.dmask_cur) A.dmask_cur[row] = (uint16_t)rs.msk;
-    }
-  }
-  set_change_bits(A.mod_cur, row, chg, lane);
+  finish_lane<B>(A, row, valid, false, sums, lane, e0, s0, h0, c);
   flush_counts(A, c, lw, lane);
 }
 
