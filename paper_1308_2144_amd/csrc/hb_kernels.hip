@@ -725,7 +725,7 @@ __device__ __forceinline__ void finish_group(const PassArgs& A, int64_t row, uin
 // The row's own lane, after the rounds: `done` if its group finished the row
 // (e0, s0, h0 = its E, S, H as before the pass).  Must be called by the whole
 // wavefront (the change bits are combined per bitmap word).
-template <int B>
+template <int B, bool MG = false>
 __device__ __forceinline__ void finish_lane(const PassArgs& A, int64_t row, bool done, bool own_mod,
                                             const RowSum* sums, int lane, double e0, double s0, double h0,
                                             Counts& c) {
@@ -742,7 +742,7 @@ __device__ __forceinline__ void finish_lane(const PassArgs& A, int64_t row, bool
       if (A.roff) c.pairs += (uint32_t)(A.roff[row + 1] - A.roff[row]);
       const double En = estimate(rs.big, rs.small, rs.zeros, A.alpha_pp, (double)P, A.lc);
       const double delta = En - e0;
-      const double d = A.d;
+      const double d = row_d<MG>(A, row);
       st_stream(A.S + row, s0 + d * delta);
       st_stream(A.H + row, h0 + delta / d);
       st_stream(A.E + row, En);
@@ -1012,6 +1012,55 @@ __device__ __forceinline__ bool light_wave_staged(const PassArgs& A, int32_t* id
   return true;
 }
 
+// Light rows of a pass that gathers every successor (dense and first passes
+// that read counters), single- or multi-graph: rows as in light_wave, the
+// successor ids read by the groups, finished in two steps (finish_group,
+// finish_lane) with each row's E, S, H loaded up front by its own lane.
+template <int B, bool MG>
+__device__ __forceinline__ void light_wave_direct(const PassArgs& A, RowSum* sums, int64_t lw, int lane) {
+  constexpr int P = 1 << B;
+  constexpr int G = P / 16;
+  constexpr int W = 64 / G;
+  const int gl = lane % G;
+  const int grp = lane / G;
+  const int64_t i = lw * 64 + lane;
+  int64_t row = 0, s = 0, deg = 0;
+  bool own_mod = false, need = false;
+  double e0 = 0.0, s0 = 0.0, h0 = 0.0;
+  if (i < A.n_light) {
+    row = A.light[i];
+    s = A.off[row];
+    deg = A.off[row + 1] - s;
+    row_flags<MG>(A, row, own_mod, need);
+    if (need) {
+      e0 = ld_stream(A.E + row);
+      s0 = ld_stream(A.S + row);
+      h0 = ld_stream(A.H + row);
+    }
+  }
+  const uint64_t needs = __ballot(need);
+  const uint64_t mods = __ballot(own_mod);
+  Counts c{};
+  if (!needs) return;  // uniform: nothing to count either
+  for (int r = 0; r < G; ++r) {
+    const int rl = r * W + grp;
+    const int64_t rrow = __shfl(row, rl);
+    const int64_t rs = __shfl(s, rl);
+    const int64_t rd = __shfl(deg, rl);
+    if ((needs >> rl) & 1ull) {  // uniform over the group
+      const bool rmod = ((mods >> rl) & 1ull) != 0ull;
+      const uint4 own = ld_stream(reinterpret_cast<const uint4*>(A.cur + (size_t)rrow * P + (size_t)gl * 16));
+      bool got = false;
+      const uint4 acc = gather<B>(A, rs, rs + rd, 1, gl, rrow, got, c);
+      if (gl == 0) c.arcs += (uint32_t)rd;
+      finish_group<B>(A, rrow, acc, got, own, rmod, gl, grp, sums + rl);
+    }
+  }
+  wave_sync();
+  finish_lane<B, MG>(A, row, need, own_mod, sums, lane, e0, s0, h0, c);
+  flush_counts(A, c, lw, lane);
+}
+
 // 64 consecutive entries of the light-row list per wavefront; entry
 // q*W + grp goes to lane group grp in round q.
 template <int B, bool Q, bool MG, int FL = FL_PLAIN>
@@ -1034,6 +1083,12 @@ __device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, RowSum* 
   if constexpr (!Q && !MG && FL == FL_PLAIN && B >= 6) {
     if (qw && light_wave_staged<B>(A, reinterpret_cast<int32_t*>(qw), sums, lw, lane)) return;
     __builtin_amdgcn_wave_barrier();
+  }
+  if constexpr (!Q && FL == FL_PLAIN) {
+    if (sums) {
+      light_wave_direct<B, MG>(A, sums, lw, lane);
+      return;
+    }
   }
   const int64_t i = lw * 64 + lane;
   int64_t row = 0, s = 0, deg = 0;
@@ -1262,10 +1317,14 @@ __device__ __forceinline__ bool queued_mode(const PassArgs& A) {
 
 template <int B, int FL = FL_PLAIN>
 __global__ HB_EXPAND_ATTR void k_expand(PassArgs A) {
-  if constexpr (B >= 6 && FL == FL_PLAIN) {
-    __shared__ QEnt qbuf[4][QCAP];  // successor ids of light rows (light_wave_staged)
+  if constexpr (FL == FL_PLAIN) {
     __shared__ RowSum sums[4][64];
-    expand_item<B, false, false, FL>(A, qbuf[threadIdx.x >> 6], sums[threadIdx.x >> 6], blockIdx.x);
+    if constexpr (B >= 6) {
+      __shared__ QEnt qbuf[4][QCAP];  // successor ids of light rows (light_wave_staged)
+      expand_item<B, false, false, FL>(A, qbuf[threadIdx.x >> 6], sums[threadIdx.x >> 6], blockIdx.x);
+    } else {
+      expand_item<B, false, false, FL>(A, nullptr, sums[threadIdx.x >> 6], blockIdx.x);
+    }
   } else {
     expand_item<B, false, false, FL>(A, nullptr, nullptr, blockIdx.x);
   }
@@ -1292,6 +1351,7 @@ __global__ HB_PERSIST_ATTR void k_expand_p(PassArgs A0) {
   if (queued_mode(A) != Q) return;
   if (!Q && A.mode == MODE_FIRST && A0.singletons) return;  // k_expand_codes_p runs it
   __shared__ QEnt qbuf[Q ? 4 : 1][Q ? QCAP : 1];
+  __shared__ RowSum sums[Q ? 1 : 4][64];  // light_wave_direct
   __shared__ int64_t ticket;
   const int K = ticket_batch(A0, Q);
   const Tickets tk = pass_tickets(A, K);
@@ -1303,7 +1363,8 @@ __global__ HB_PERSIST_ATTR void k_expand_p(PassArgs A0) {
     if (k >= tk.count) break;
     int64_t b0, b1;
     ticket_items(tk, K, k, &b0, &b1);
-    for (int64_t b = b0; b < b1; ++b) expand_item<B, Q, true>(A, Q ? qbuf[threadIdx.x >> 6] : nullptr, nullptr, b);
+    for (int64_t b = b0; b < b1; ++b)
+      expand_item<B, Q, true>(A, Q ? qbuf[threadIdx.x >> 6] : nullptr, Q ? nullptr : sums[threadIdx.x >> 6], b);
   }
 }
 
