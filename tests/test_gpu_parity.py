@@ -95,6 +95,32 @@ def test_parity_every_row_path(opts):
             check(off, idx, b, 31, f"{name}/b{b}/{opts}", **opts)
 
 
+def test_registers_before_the_first_pass_and_after_a_reset():
+    """Registers read after a reset, before any pass, are every node's
+    singleton counter; runs from a fresh context, after such a read and after
+    a second reset all equal the oracle, heavy rows (merged from partial
+    counters) and rows without successors included."""
+    import paper_1308_2144_amd as hb
+
+    off, idx = gg.rmat(9, 6, seed=3, transpose=True, relabel=True)
+    n = len(off) - 1
+    assert (np.diff(off) == 0).any() and np.diff(off).max() > 6
+    for b in (5, 7):
+        ref = run_oracle(off, idx, b, 17)
+        init = np.stack([oracle.counter_of([v], b, 17) for v in range(n)])
+        with hb.HyperBall(off, idx, b, 17, light_max=2, heavy_min=6, chunk=3) as g:
+            g.run()
+            assert np.array_equal(g.registers(), ref["regs"]), b
+            g.reset(17)
+            assert np.array_equal(g.registers(), init), b
+            g.run()
+            assert np.array_equal(g.registers(), ref["regs"]), b
+            g.reset(17)
+            g.run()
+            assert np.array_equal(g.registers(), ref["regs"]), b
+            assert np.array_equal(g.centralities()["harmonic"], ref["H"]), b
+
+
 @pytest.mark.parametrize("b,n,m", [(9, 300, 2000), (10, 200, 1500), (12, 90, 600)])
 def test_wide_counters(b, n, m):
     off, idx = gg.random_digraph(n, m, seed=b)
