@@ -1506,11 +1506,14 @@ __device__ __forceinline__ RowPre preload_code(const PassArgs& A, int64_t row, i
   return r;
 }
 
-// 64 light-row list entries per wavefront, W rows at a time (one per lane
-// group).  Multi-graph passes combine a round's change bits into one atomic
-// per bitmap word, as light_wave does.
+// Light rows of a first pass, 64 list entries per wavefront, W rows at a
+// time (one per lane group): the group folds its row's successor codes into
+// an LDS register array, packs it and finishes the row in two steps
+// (finish_group, finish_lane).  Each lane looks up its own row's hash key,
+// hashes the row's node and loads the row's estimate and accumulators once,
+// up front.
 template <int B, bool MG>
-__device__ __forceinline__ void light_codes(const PassArgs& A, uint32_t* lds, int64_t lw, int lane) {
+__device__ __forceinline__ void light_codes_1(const PassArgs& A, uint32_t* lds, RowSum* sums, int64_t lw, int lane) {
   constexpr int P = 1 << B;
   constexpr int G = P / 16;
   constexpr int W = 64 / G;
@@ -1518,13 +1521,22 @@ __device__ __forceinline__ void light_codes(const PassArgs& A, uint32_t* lds, in
   const int grp = lane / G;
   const int64_t i = lw * 64 + lane;
   int64_t row = 0, s = 0, deg = 0;
-  bool need = false;
+  bool own_mod = false, need = false;
+  uint32_t code = 0u;
+  GraphKey key{0, A.seed};
+  double e0 = 0.0, s0 = 0.0, h0 = 0.0;
   if (i < A.n_light) {
     row = A.light[i];
     s = A.off[row];
     deg = A.off[row + 1] - s;
-    bool own_mod;
     row_flags<MG>(A, row, own_mod, need);
+    if (need) {
+      key = key_of<MG>(A, row);
+      e0 = ld_stream(A.E + row);
+      s0 = ld_stream(A.S + row);
+      h0 = ld_stream(A.H + row);
+      code = singleton_code<B>((uint64_t)(row - key.base), key.seed);
+    }
   }
   const uint64_t live = __ballot(need);
   uint32_t* regs = lds + grp * P;
@@ -1534,65 +1546,14 @@ __device__ __forceinline__ void light_codes(const PassArgs& A, uint32_t* lds, in
     const int64_t rrow = __shfl(row, rl);
     const int64_t rs = __shfl(s, rl);
     const int64_t rd = __shfl(deg, rl);
-    const bool on = ((live >> rl) & 1ull) != 0ull;
-    RowPre pre;
-    if (on) {
-      const GraphKey key = key_of<MG>(A, rrow);
-      pre = preload_code<B>(A, rrow, gl, key);
-      fold_codes<B>(A, regs, rs + gl, rs + rd, G, key);
-    }
-    wave_sync();
-    bool chg = false;
-    if (on) {
-      const uint4 acc = take_slice(regs, gl);
-      if (gl == 0) {
-        c.gath += (uint32_t)rd;
-        c.arcs += (uint32_t)rd;
-      }
-      chg = finish_row<B, MG, FL_PLAIN, MG>(A, rrow, acc, rd > 0, pre, false, gl, grp, c);
-    }
-    if constexpr (MG) set_change_bits(A.mod_cur, rrow, chg && gl == 0, lane);
-    wave_sync();
-  }
-  flush_counts(A, c, lw, lane);
-}
-
-// Light rows of a single-graph first pass: as light_codes, finished in two
-// steps (finish_group, finish_lane); each lane also hashes its own row's node
-// once, and loads the row's estimate and accumulators, up front.
-template <int B>
-__device__ __forceinline__ void light_codes_1(const PassArgs& A, uint32_t* lds, RowSum* sums, int64_t lw, int lane) {
-  constexpr int P = 1 << B;
-  constexpr int G = P / 16;
-  constexpr int W = 64 / G;
-  const int gl = lane % G;
-  const int grp = lane / G;
-  const int64_t i = lw * 64 + lane;
-  const bool valid = i < A.n_light;
-  int64_t row = 0, s = 0, deg = 0;
-  uint32_t code = 0u;
-  double e0 = 0.0, s0 = 0.0, h0 = 0.0;
-  if (valid) {
-    row = A.light[i];
-    s = A.off[row];
-    deg = A.off[row + 1] - s;
-    e0 = ld_stream(A.E + row);
-    s0 = ld_stream(A.S + row);
-    h0 = ld_stream(A.H + row);
-    code = singleton_code<B>((uint64_t)row, A.seed);
-  }
-  const uint64_t live = __ballot(valid);
-  uint32_t* regs = lds + grp * P;
-  const GraphKey key{0, A.seed};
-  Counts c{};
-  for (int r = 0; r < G; ++r) {
-    const int rl = r * W + grp;
-    const int64_t rrow = __shfl(row, rl);
-    const int64_t rs = __shfl(s, rl);
-    const int64_t rd = __shfl(deg, rl);
     const uint32_t rcode = __shfl(code, rl);
+    GraphKey rkey{0, A.seed};
+    if constexpr (MG) {
+      rkey.base = __shfl(key.base, rl);
+      rkey.seed = __shfl(key.seed, rl);
+    }
     const bool on = ((live >> rl) & 1ull) != 0ull;
-    if (on) fold_codes<B>(A, regs, rs + gl, rs + rd, G, key);
+    if (on) fold_codes<B>(A, regs, rs + gl, rs + rd, G, rkey);
     wave_sync();
     if (on) {
       const uint4 acc = take_slice(regs, gl);
@@ -1604,7 +1565,7 @@ __device__ __forceinline__ void light_codes_1(const PassArgs& A, uint32_t* lds, 
     }
     wave_sync();
   }
-  finish_lane<B>(A, row, valid, false, sums, lane, e0, s0, h0, c);
+  finish_lane<B, MG>(A, row, need, false, sums, lane, e0, s0, h0, c);
   flush_counts(A, c, lw, lane);
 }
 
@@ -1682,12 +1643,7 @@ __device__ __forceinline__ void codes_item(const PassArgs& A, uint32_t (*regs)[C
   }
   b -= med_wgs;
   const int64_t lw = b * 4 + wave;
-  if (lw * 64 < A.n_light) {
-    if constexpr (MG)
-      light_codes<B, MG>(A, regs[wave], lw, lane);
-    else
-      light_codes_1<B>(A, regs[wave], sums[wave], lw, lane);
-  }
+  if (lw * 64 < A.n_light) light_codes_1<B, MG>(A, regs[wave], sums[wave], lw, lane);
 }
 
 template <int B>
@@ -1708,6 +1664,7 @@ __global__ HB_PERSIST_ATTR void k_expand_codes_p(PassArgs A0) {
   const PassArgs A = resolve(A0);
   if (A.mode != MODE_FIRST || !A0.singletons) return;
   __shared__ uint32_t regs[4][CODE_WORDS];
+  __shared__ RowSum sums[4][64];
   __shared__ int64_t ticket;
   uint4* z = reinterpret_cast<uint4*>(&regs[0][0]);
   for (int i = threadIdx.x; i < CODE_WORDS; i += 256) z[i] = zero4();
@@ -1722,7 +1679,7 @@ __global__ HB_PERSIST_ATTR void k_expand_codes_p(PassArgs A0) {
     if (k >= tk.count) break;
     int64_t b0, b1;
     ticket_items(tk, K, k, &b0, &b1);
-    for (int64_t b = b0; b < b1; ++b) codes_item<B, true>(A, regs, nullptr, b, threadIdx.x & 63, threadIdx.x >> 6);
+    for (int64_t b = b0; b < b1; ++b) codes_item<B, true>(A, regs, sums, b, threadIdx.x & 63, threadIdx.x >> 6);
   }
 }
 
