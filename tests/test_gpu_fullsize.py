@@ -108,3 +108,32 @@ def test_rmat_s24_against_oracle_run(s24):
     empty = np.flatnonzero(deg == 0)[:1000]
     assert np.all((regs[empty] > 0).sum(axis=1) == 1)
     assert np.all(S[empty] == 0.0) and np.all(cen["lin"][empty] == 1.0)
+
+
+@pytest.mark.timeout(900)
+def test_rmat_s24_streamed_against_oracle_run(s24):
+    """The benchmark workload with the CSR kept in pinned host memory and
+    streamed to the device in row chunks every pass (graph budget 512 MiB:
+    five chunks), as is and compressed: the oracle run's pass count, changed
+    counters per pass and digests of the registers, S, H and the four outputs."""
+    import paper_1308_2144_amd as hb
+
+    off, idx = s24
+    b, seed = 7, 42
+    gold = load_golden_single("fullsize_rmat-s24.txt")
+    for compress in (0, 1):
+        with hb.HyperBall(off, idx, b, seed, stream_graph=1, graph_budget=512 << 20,
+                          stream_compress=compress) as g:
+            st = g.stats()
+            assert st["streamed"] == 1 and st["compressed"] == compress and st["chunks"] >= 4
+            passes = g.run()
+            nmod = [g.pass_stats(t)["rows_changed"] for t in range(passes)]
+            regs = g.registers()
+            S, H = g.accumulators()
+            got = dict(S=S, H=H, **g.centralities())
+        _log("s24 streamed compress", compress, "chunks", st["chunks"], "host bytes", st["host_graph_bytes"],
+             "passes", passes)
+        assert passes == gold["passes"] and nmod == gold["nmod"], (compress, passes, nmod)
+        assert sha256_of(regs) == gold["sha256"]["registers"], compress
+        for key in ("S", "H") + CENTRALITIES:
+            assert sha256_of(got[key]) == gold["sha256"][key], (compress, key)
