@@ -124,9 +124,10 @@ typedef struct {
  *   stream_compress  streamed graphs: 1 keeps the arcs in host memory
  *              compressed (each row's successors sorted, then blocks of 32
  *              arcs coded as the first id and the differences between
- *              consecutive ids in 7-bit variable-length bytes) and decodes
- *              each uploaded chunk on the device: fewer bytes over the host
- *              link for the same results.  Each staging buffer then has a
+ *              consecutive ids, as 7-bit variable-length bytes or bit-packed
+ *              at the block's widest difference, whichever is shorter) and
+ *              decodes each uploaded chunk on the device: fewer bytes over
+ *              the host link for the same results.  Each staging buffer then has a
  *              second buffer beside it for the chunk's coded form.  Ignored
  *              when the graph is not streamed. */
 typedef struct {

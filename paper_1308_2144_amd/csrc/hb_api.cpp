@@ -428,13 +428,62 @@ void put_varint(std::vector<uint8_t>& out, uint32_t v) {
   out.push_back((uint8_t)v);
 }
 
+int varint_len(uint32_t v) {
+  int k = 1;
+  while (v >= 0x80u) {
+    v >>= 7;
+    ++k;
+  }
+  return k;
+}
+
+int bit_width(uint32_t v) { return v == 0u ? 0 : 32 - __builtin_clz(v); }
+
+// One block of a compressed chunk: ids x[0..L), L <= STREAM_BLOCK_ARCS.  A
+// header byte, the first id as a variable-length integer, then the zigzag
+// differences of consecutive ids either as variable-length integers (header
+// 0) or bit-packed at the block's widest difference W, low bits first
+// (header W + 1), whichever is shorter: gaps inside sorted rows are alike in
+// size, so packing them saves the 7-bit granularity; blocks crossing many
+// row starts keep the variable lengths.
+void put_block(std::vector<uint8_t>& out, const int32_t* x, int64_t L) {
+  uint32_t z[hb::STREAM_BLOCK_ARCS];
+  int64_t vlen = 0;
+  int W = 0;
+  for (int64_t a = 1; a < L; ++a) {
+    const int32_t d = (int32_t)((uint32_t)x[a] - (uint32_t)x[a - 1]);
+    z[a] = ((uint32_t)d << 1) ^ (uint32_t)(d >> 31);
+    vlen += varint_len(z[a]);
+    W = std::max(W, bit_width(z[a]));
+  }
+  const int64_t plen = ((L - 1) * W + 7) / 8;
+  const bool packed = plen < vlen;
+  out.push_back(packed ? (uint8_t)(W + 1) : (uint8_t)0);
+  put_varint(out, (uint32_t)x[0]);
+  if (!packed) {
+    for (int64_t a = 1; a < L; ++a) put_varint(out, z[a]);
+    return;
+  }
+  uint64_t acc = 0;
+  int nbits = 0;
+  for (int64_t a = 1; a < L; ++a) {
+    acc |= (uint64_t)z[a] << nbits;
+    nbits += W;
+    while (nbits >= 8) {
+      out.push_back((uint8_t)acc);
+      acc >>= 8;
+      nbits -= 8;
+    }
+  }
+  if (nbits > 0) out.push_back((uint8_t)acc);
+}
+
 // Compressed streamed arcs: every row's successors sorted (the union is
 // order-free, so results do not change), then each chunk's arcs coded in
-// blocks of STREAM_BLOCK_ARCS consecutive arcs: the first id, then the
-// zigzag-coded differences to the previous id, all as variable-length
-// integers of 7 bits per byte (small differences inside a sorted row take one
-// or two bytes).  Chunks are coded in parallel; the bytes and block offsets
-// go to pinned memory, the ids stay only as the pinned copy's sorted order.
+// blocks of STREAM_BLOCK_ARCS consecutive arcs (put_block).  Chunks are coded
+// in parallel; the bytes (each chunk followed by 8 zero bytes, so the decoder
+// may read a few bytes past a block) and block offsets go to pinned memory,
+// and the raw arcs are freed.
 hb_status compress_chunks(hb_ctx* c) {
   const int64_t nch = (int64_t)c->chunks.size();
   std::vector<std::vector<uint8_t>> bytes((size_t)nch);
@@ -452,15 +501,7 @@ hb_status compress_chunks(hb_ctx* c) {
         out.reserve((size_t)(ch.e1 - ch.e0) * 3);
         for (int64_t e = ch.e0; e < ch.e1; e += hb::STREAM_BLOCK_ARCS) {
           bo.push_back((uint32_t)out.size());
-          const int64_t end = std::min<int64_t>(e + hb::STREAM_BLOCK_ARCS, ch.e1);
-          uint32_t prev = (uint32_t)c->host_idx[e];
-          put_varint(out, prev);
-          for (int64_t a = e + 1; a < end; ++a) {
-            const uint32_t x = (uint32_t)c->host_idx[a];
-            const int32_t d = (int32_t)(x - prev);
-            put_varint(out, ((uint32_t)d << 1) ^ (uint32_t)(d >> 31));
-            prev = x;
-          }
+          put_block(out, c->host_idx + e, std::min<int64_t>(hb::STREAM_BLOCK_ARCS, ch.e1 - e));
         }
         bo.push_back((uint32_t)out.size());
         if (out.size() > 0xfffff000u) too_big = true;
@@ -476,8 +517,8 @@ hb_status compress_chunks(hb_ctx* c) {
     ch.cb_at = cb;
     ch.cb_len = (int64_t)bytes[(size_t)ci].size();
     bo += ch.nb + 1;
-    cb += (ch.cb_len + 3) / 4 * 4;
-    cap = std::max<int64_t>(cap, (int64_t)align256(sizeof(uint32_t) * (size_t)(ch.nb + 1)) + (ch.cb_len + 3) / 4 * 4);
+    cb += (ch.cb_len + 8 + 3) / 4 * 4;
+    cap = std::max<int64_t>(cap, (int64_t)align256(sizeof(uint32_t) * (size_t)(ch.nb + 1)) + (ch.cb_len + 8 + 3) / 4 * 4);
   }
   HB_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->host_cbytes), (size_t)std::max<int64_t>(cb, 4), hipHostMallocDefault));
   HB_HIP(hipHostMalloc(reinterpret_cast<void**>(&c->host_boff), sizeof(uint32_t) * (size_t)std::max<int64_t>(bo, 1),
@@ -485,7 +526,7 @@ hb_status compress_chunks(hb_ctx* c) {
   for (int64_t ci = 0; ci < nch; ++ci) {
     const StreamChunk& ch = c->chunks[(size_t)ci];
     std::memcpy(c->host_cbytes + ch.cb_at, bytes[(size_t)ci].data(), (size_t)ch.cb_len);
-    std::memset(c->host_cbytes + ch.cb_at + ch.cb_len, 0, (size_t)((ch.cb_len + 3) / 4 * 4 - ch.cb_len));
+    std::memset(c->host_cbytes + ch.cb_at + ch.cb_len, 0, (size_t)((ch.cb_len + 8 + 3) / 4 * 4 - ch.cb_len));
     std::memcpy(c->host_boff + ch.bo_at, boff[(size_t)ci].data(), sizeof(uint32_t) * (size_t)(ch.nb + 1));
   }
   c->cstage_bytes = std::max<int64_t>(cap, 256);
@@ -662,7 +703,7 @@ hipError_t streamed_pass(hb_ctx* c, const hb::PassArgs& a, bool timing, hb_pass_
       cboff = reinterpret_cast<uint32_t*>(c->cstage[s]);
       cbytes = c->cstage[s] + align256(sizeof(uint32_t) * (size_t)(ch.nb + 1));
       const size_t bbytes = sizeof(uint32_t) * (size_t)(ch.nb + 1);
-      const size_t cb = (size_t)((ch.cb_len + 3) / 4 * 4);
+      const size_t cb = (size_t)((ch.cb_len + 8 + 3) / 4 * 4);  // with the zero padding
       if (e == hipSuccess) e = hipMemcpyAsync(cboff, c->host_boff + ch.bo_at, bbytes, hipMemcpyHostToDevice, c->copy_stream);
       if (e == hipSuccess && cb)
         e = hipMemcpyAsync(cbytes, c->host_cbytes + ch.cb_at, cb, hipMemcpyHostToDevice, c->copy_stream);

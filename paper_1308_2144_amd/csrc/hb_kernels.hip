@@ -1835,14 +1835,16 @@ __global__ void k_chunk_activity(const uint64_t* __restrict__ mod_prev, int64_t 
 }
 
 // Compressed streamed chunks: a chunk's arcs are cut into blocks of
-// STREAM_BLOCK_ARCS consecutive arcs (across row boundaries); a block is its first
-// successor id as a variable-length integer (7 bits per byte, low bits first,
-// high bit set on every byte but the last) followed by the zigzag-coded
-// differences between consecutive ids, coded the same way.  boff[b] is the
-// byte offset of block b in the chunk's bytes.  Each workgroup first copies
-// the bytes of its 256 blocks into LDS (one coalesced copy), then each thread
-// decodes one block into ids.
-constexpr int DECODE_LDS = 256 * STREAM_BLOCK_ARCS * 5;  // bytes of 256 blocks at worst (5 per id)
+// STREAM_BLOCK_ARCS consecutive arcs (across row boundaries).  A block is a
+// header byte, its first successor id as a variable-length integer (7 bits
+// per byte, low bits first, high bit set on every byte but the last), then
+// the zigzag-coded differences between consecutive ids: as variable-length
+// integers too (header 0), or bit-packed, each W = header - 1 bits wide, low
+// bits first.  boff[b] is the byte offset of block b in the chunk's bytes,
+// which are followed by at least 8 readable bytes.  Each workgroup first
+// copies the bytes of its 256 blocks into LDS (one coalesced copy), then each
+// thread decodes one block into ids.
+constexpr int DECODE_LDS = 256 * (1 + STREAM_BLOCK_ARCS * 5);  // bytes of 256 blocks at worst
 
 // At most 5 bytes (a 32-bit value), so a damaged stream cannot run on.
 __device__ __forceinline__ uint32_t read_varint(const uint8_t* p, int& at) {
@@ -1856,14 +1858,23 @@ __device__ __forceinline__ uint32_t read_varint(const uint8_t* p, int& at) {
   return v;
 }
 
+// W <= 32 bits at bit position `bit` of p (reads 5 bytes from bit / 8 on).
+__device__ __forceinline__ uint32_t read_bits(const uint8_t* p, uint32_t bit, uint32_t W) {
+  const uint8_t* q = p + (bit >> 3);
+  const uint64_t x = (uint64_t)q[0] | ((uint64_t)q[1] << 8) | ((uint64_t)q[2] << 16) | ((uint64_t)q[3] << 24) |
+                     ((uint64_t)q[4] << 32);
+  return (uint32_t)((x >> (bit & 7u)) & ((1ull << W) - 1ull));
+}
+
 __global__ __launch_bounds__(256) void k_decode_chunk(const uint32_t* __restrict__ boff, const uint8_t* __restrict__ bytes,
                                                       int64_t n_arcs, int64_t n_blocks, int32_t* __restrict__ ids) {
-  __shared__ uint32_t buf[DECODE_LDS / 4 + 2];  // + the partial words at both ends
+  __shared__ uint32_t buf[DECODE_LDS / 4 + 4];  // + the partial words at both ends and the read-ahead
   const int64_t b0 = (int64_t)blockIdx.x * 256;
   const int64_t b1 = b0 + 256 < n_blocks ? b0 + 256 : n_blocks;
   const uint32_t lo = boff[b0], hi = boff[b1];
-  // the workgroup's bytes [lo, hi) into LDS, in 4-byte words from lo rounded down
-  const uint32_t w0 = lo >> 2, w1 = (hi + 3) >> 2;
+  // the workgroup's bytes [lo, hi) and the 8 after them into LDS, in 4-byte
+  // words from lo rounded down
+  const uint32_t w0 = lo >> 2, w1 = ((hi + 3) >> 2) + 2;
   const uint32_t* src = reinterpret_cast<const uint32_t*>(bytes);
   for (uint32_t w = w0 + threadIdx.x; w < w1; w += 256) buf[w - w0] = src[w];
   __syncthreads();
@@ -1873,12 +1884,24 @@ __global__ __launch_bounds__(256) void k_decode_chunk(const uint32_t* __restrict
   int at = (int)(boff[b] - (w0 << 2));
   const int64_t a0 = b * STREAM_BLOCK_ARCS;
   const int64_t a1 = a0 + STREAM_BLOCK_ARCS < n_arcs ? a0 + STREAM_BLOCK_ARCS : n_arcs;
+  const uint32_t head = lds[at++];
   uint32_t cur = read_varint(lds, at);
   ids[a0] = (int32_t)cur;
-  for (int64_t a = a0 + 1; a < a1; ++a) {
-    const uint32_t z = read_varint(lds, at);
-    cur += (z >> 1) ^ (0u - (z & 1u));  // zigzag: 2d for d >= 0, -2d-1 for d < 0
-    ids[a] = (int32_t)cur;
+  if (head == 0u) {
+    for (int64_t a = a0 + 1; a < a1; ++a) {
+      const uint32_t z = read_varint(lds, at);
+      cur += (z >> 1) ^ (0u - (z & 1u));  // zigzag: 2d for d >= 0, -2d-1 for d < 0
+      ids[a] = (int32_t)cur;
+    }
+  } else {
+    const uint32_t W = head - 1u < 32u ? head - 1u : 32u;
+    uint32_t bit = (uint32_t)at * 8u;
+    for (int64_t a = a0 + 1; a < a1; ++a) {
+      const uint32_t z = read_bits(lds, bit, W);
+      bit += W;
+      cur += (z >> 1) ^ (0u - (z & 1u));
+      ids[a] = (int32_t)cur;
+    }
   }
 }
 
