@@ -680,8 +680,9 @@ __device__ __forceinline__ void set_change_bits(uint64_t* mod_cur, int64_t row, 
   }
 }
 
-// Light rows of single-graph passes finish in two steps.  Per round, the
-// row's lane group does what is per register: the write-back rule, change
+// Light rows taken 64 to a wavefront (first and dense passes of every context,
+// edge passes of single graphs) finish in two steps.  Per round, the row's
+// lane group does what is per register: the write-back rule, change
 // detection and the register sum (finish_group), and leaves a RowSum in LDS;
 // after the rounds every lane finishes its own row, all 64 at once: the
 // estimator, the accumulators, the slice mask, the change bit and the counts
