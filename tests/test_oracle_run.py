@@ -353,3 +353,28 @@ def test_discount_tables_exact_values(orc):
         assert f[0] == 1.0 and np.all(np.diff(f) <= 0.0)
     with pytest.raises(KeyError):
         orc.discount_table("exponential", 4)
+
+
+def test_first_pass_rows_is_pass_zero_and_openmp_build_agrees(orc, gg):
+    """The bounded pass behind the CPU baseline: over every row it is pass 0 of
+    the oracle run (counters at radius 1, S, H and the change count), over a
+    sub-range it is that range of the same pass, and the OpenMP build of the
+    same loop (several threads) gives identical counters, sums and count."""
+    off, idx = gg.rmat(12, 8, seed=7, transpose=True, relabel=True)
+    n = len(off) - 1
+    b, seed = 6, 9
+    one = orc.run(off, idx, b, seed, max_passes=1)
+    full = orc.first_pass_rows(off, idx, b, seed, 0, n)
+    assert np.array_equal(full["next"], one["regs"])
+    assert np.array_equal(full["S"], one["S"]) and np.array_equal(full["H"], one["H"])
+    assert full["changed"] == one["nmod"][0] and full["threads"] == 1
+    v0, v1 = 100, 3000
+    part = orc.first_pass_rows(off, idx, b, seed, v0, v1)
+    par = orc.first_pass_rows(off, idx, b, seed, v0, v1, all_cores=True)
+    assert np.array_equal(part["next"], full["next"][v0:v1])
+    assert np.array_equal(part["S"], full["S"][v0:v1]) and np.array_equal(part["H"], full["H"][v0:v1])
+    for key in ("next", "S", "H"):
+        assert np.array_equal(par[key], part[key]), key
+    assert par["changed"] == part["changed"]
+    with pytest.raises(ValueError):
+        orc.first_pass_rows(off, idx, b, seed, 5, n + 1)
