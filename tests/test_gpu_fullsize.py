@@ -1,7 +1,8 @@
 """GPU parity at the full benchmark sizes.
 
 * R-MAT scale 20, edge factor 16, transposed, int32 CSR, log2m = 6: the whole
-  oracle run (about 30 s of CPU) against the GPU, element by element.
+  oracle run (about 30 s of CPU) against the GPU, element by element, with
+  the default planning and with every pass mode forced.
 * R-MAT scale 24, edge factor 16, transposed, int64 offsets, log2m = 7 (the
   benchmark workload, same launch configuration as bench.py), against the
   whole oracle run stored in tests/golden/fullsize_rmat-s24.txt (written by
@@ -17,7 +18,7 @@ import pytest
 
 import graphgen as gg
 import oracle
-from hbcheck import CENTRALITIES, assert_fp, check, load_golden_single, sha256_of
+from hbcheck import CENTRALITIES, assert_fp, compare, load_golden_single, run_hb, run_oracle, sha256_of
 
 pytestmark = pytest.mark.gpu
 
@@ -26,12 +27,36 @@ def _log(*a):
     print(*a, flush=True)
 
 
-@pytest.mark.timeout(600)
-def test_rmat_s20_full_oracle():
+@pytest.fixture(scope="module")
+def s20():
     off, idx = gg.rmat(20, 16, seed=2, transpose=True, relabel=True)
     _log("s20: n", len(off) - 1, "m", len(idx))
-    got, ref = check(off.astype(np.int32), idx, 6, 42, "s20")
+    return off, idx, run_oracle(off, idx, 6, 42)
+
+
+@pytest.mark.timeout(600)
+def test_rmat_s20_full_oracle(s20):
+    off, idx, ref = s20
+    got = run_hb(off.astype(np.int32), idx, 6, 42)
+    compare(got, ref, "s20")
     _log("s20 passes", got["passes"])
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("opts", [
+    dict(frontier=0),                              # every pass dense
+    dict(dense_pct=101, sparse_pct=0),             # every pass after the first an edge pass
+    dict(dense_pct=101, sparse_pct=0, slice=1),    # edge passes reading changed slices only
+    dict(dense_pct=0, qdense=1),                   # dense passes through the queued gather
+    dict(pairs=0),                                 # sparse passes from activation stamps
+    dict(light_max=16, heavy_min=1024, chunk=512),
+])
+def test_rmat_s20_every_pass_mode_against_the_same_oracle_run(s20, opts):
+    """The scale-20 configuration with each pass mode and row split forced:
+    the same registers, pass count, S, H and outputs as the oracle run."""
+    off, idx, ref = s20
+    got = run_hb(off.astype(np.int32), idx, 6, 42, **opts)
+    compare(got, ref, f"s20 {opts}")
 
 
 @pytest.fixture(scope="module")
