@@ -165,3 +165,35 @@ def test_rmat_s24_streamed_against_oracle_run(s24):
         assert sha256_of(regs) == gold["sha256"]["registers"], compress
         for key in ("S", "H") + CENTRALITIES:
             assert sha256_of(got[key]) == gold["sha256"][key], (compress, key)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("opts", [
+    dict(frontier=0),                              # every pass dense
+    dict(dense_pct=101, sparse_pct=0),             # every pass after the first an edge pass
+    dict(pairs=0),                                 # sparse passes from activation stamps
+])
+def test_rmat_s24_pass_modes_against_oracle_run(s24, opts):
+    """The benchmark workload with other pass modes forced: the stored oracle
+    run's pass count, changed counters per pass and digests of the registers,
+    S, H and the four outputs."""
+    import torch
+
+    import paper_1308_2144_amd as hb
+
+    off, idx = s24
+    gold = load_golden_single("fullsize_rmat-s24.txt")
+    o = torch.from_numpy(off).cuda()
+    i = torch.from_numpy(idx).cuda()
+    with hb.HyperBall(o, i, 7, 42, stream=torch.cuda.current_stream().cuda_stream, **opts) as g:
+        passes = g.run()
+        nmod = [g.pass_stats(t)["rows_changed"] for t in range(passes)]
+        modes = [g.pass_stats(t)["mode"] for t in range(passes)]
+        regs = g.registers()
+        S, H = g.accumulators()
+        got = dict(S=S, H=H, **g.centralities())
+    _log("s24", opts, "modes", modes)
+    assert passes == gold["passes"] and nmod == gold["nmod"], (opts, passes, nmod)
+    assert sha256_of(regs) == gold["sha256"]["registers"], opts
+    for key in ("S", "H") + CENTRALITIES:
+        assert sha256_of(got[key]) == gold["sha256"][key], (opts, key)
