@@ -7,7 +7,8 @@ plus properties that hold at any size.
   hash seeds 42+i, options from the committed autotuner cache: every graph's
   pass count and the digests of its registers, S and H against the whole
   oracle run of that graph (tests/golden/fullsize_batch-4096.txt, written by
-  tests/golden/make_fullsize.py from the oracle alone);
+  tests/golden/make_fullsize.py from the oracle alone); the same with the
+  library's default options and with other forced configurations;
 * serving: the largest, smallest and a middle request of the served R-MAT
   pool (scale 10..20, edge factor 4..32, log2m 4/6/8) in a mix: pass counts,
   and digests of registers, S, H and the finalized outputs against the whole
@@ -115,6 +116,38 @@ def test_batch_bench_config():
             assert np.array_equal(regs[base:base + n].cpu().numpy(), ref["regs"]), what
             assert_fp(S[base:base + n].cpu().numpy(), ref["S"], what + " S")
         _log("batch ok:", what, "passes", int(passes[g]))
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("opts", [
+    dict(),                                          # library defaults, not the tuned ones
+    dict(frontier=0),                                # every device pass dense
+    dict(push=1, graph_passes=2, light_max=32),      # reverse CSR for sparse passes, other split
+])
+def test_batch_all_graphs_in_other_configurations(opts):
+    """The 4096-graph batch with untuned and forced options: every graph's
+    pass count and register, S and H digests equal its stored oracle run."""
+    import paper_1308_2144_amd as hb
+
+    graphs = gg.batch_workload()
+    k = len(graphs)
+    seeds = np.arange(k, dtype=np.uint64) + 42
+    opt = hb.default_options(**opts)
+    with hb.Batch(graphs, 5, seeds, options=opt) as bt:
+        bt.run()
+        passes = bt.passes()
+        regs, S, H = bt.registers(), *bt.accumulators()
+        bounds = bt.bounds
+    gold = load_golden_batch("fullsize_batch-4096.txt")
+    bad = []
+    for g in range(k):
+        base, n = int(bounds[g]), len(graphs[g][0]) - 1
+        ref = gold[g]
+        if (int(passes[g]) != ref["passes"] or sha256_of(regs[base:base + n])[:16] != ref["regs"]
+                or sha256_of(S[base:base + n])[:16] != ref["S"] or sha256_of(H[base:base + n])[:16] != ref["H"]):
+            bad.append(g)
+    assert not bad, (opts, bad[:10])
+    _log("batch", opts, ": all", k, "graphs equal the oracle runs")
 
 
 @pytest.mark.timeout(900)
