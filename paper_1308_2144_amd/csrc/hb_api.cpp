@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "hb_ctx.h"
+#include "hb_stream_codes.h"
 
 namespace hbh {
 thread_local std::string g_err;
@@ -420,70 +421,12 @@ int host_csr_check(const T* off, const int32_t* idx, int64_t n, int64_t m) {
   return 0;
 }
 
-void put_varint(std::vector<uint8_t>& out, uint32_t v) {
-  while (v >= 0x80u) {
-    out.push_back((uint8_t)(v | 0x80u));
-    v >>= 7;
-  }
-  out.push_back((uint8_t)v);
-}
-
-int varint_len(uint32_t v) {
-  int k = 1;
-  while (v >= 0x80u) {
-    v >>= 7;
-    ++k;
-  }
-  return k;
-}
-
-int bit_width(uint32_t v) { return v == 0u ? 0 : 32 - __builtin_clz(v); }
-
-// One block of a compressed chunk: ids x[0..L), L <= STREAM_BLOCK_ARCS.  A
-// header byte, the first id as a variable-length integer, then the zigzag
-// differences of consecutive ids either as variable-length integers (header
-// 0) or bit-packed at the block's widest difference W, low bits first
-// (header W + 1), whichever is shorter: gaps inside sorted rows are alike in
-// size, so packing them saves the 7-bit granularity; blocks crossing many
-// row starts keep the variable lengths.
-void put_block(std::vector<uint8_t>& out, const int32_t* x, int64_t L) {
-  uint32_t z[hb::STREAM_BLOCK_ARCS];
-  int64_t vlen = 0;
-  int W = 0;
-  for (int64_t a = 1; a < L; ++a) {
-    const int32_t d = (int32_t)((uint32_t)x[a] - (uint32_t)x[a - 1]);
-    z[a] = ((uint32_t)d << 1) ^ (uint32_t)(d >> 31);
-    vlen += varint_len(z[a]);
-    W = std::max(W, bit_width(z[a]));
-  }
-  const int64_t plen = ((L - 1) * W + 7) / 8;
-  const bool packed = plen < vlen;
-  out.push_back(packed ? (uint8_t)(W + 1) : (uint8_t)0);
-  put_varint(out, (uint32_t)x[0]);
-  if (!packed) {
-    for (int64_t a = 1; a < L; ++a) put_varint(out, z[a]);
-    return;
-  }
-  uint64_t acc = 0;
-  int nbits = 0;
-  for (int64_t a = 1; a < L; ++a) {
-    acc |= (uint64_t)z[a] << nbits;
-    nbits += W;
-    while (nbits >= 8) {
-      out.push_back((uint8_t)acc);
-      acc >>= 8;
-      nbits -= 8;
-    }
-  }
-  if (nbits > 0) out.push_back((uint8_t)acc);
-}
-
 // Compressed streamed arcs: every row's successors sorted (the union is
 // order-free, so results do not change), then each chunk's arcs coded in
-// blocks of STREAM_BLOCK_ARCS consecutive arcs (put_block).  Chunks are coded
-// in parallel; the bytes (each chunk followed by 8 zero bytes, so the decoder
-// may read a few bytes past a block) and block offsets go to pinned memory,
-// and the raw arcs are freed.
+// blocks of STREAM_BLOCK_ARCS consecutive arcs (hb_stream_codes.h).  Chunks
+// are coded in parallel; the bytes (each chunk followed by 8 zero bytes, so
+// the decoder may read a few bytes past a block) and block offsets go to
+// pinned memory, and the raw arcs are freed.
 hb_status compress_chunks(hb_ctx* c) {
   const int64_t nch = (int64_t)c->chunks.size();
   std::vector<std::vector<uint8_t>> bytes((size_t)nch);
@@ -501,7 +444,8 @@ hb_status compress_chunks(hb_ctx* c) {
         out.reserve((size_t)(ch.e1 - ch.e0) * 3);
         for (int64_t e = ch.e0; e < ch.e1; e += hb::STREAM_BLOCK_ARCS) {
           bo.push_back((uint32_t)out.size());
-          put_block(out, c->host_idx + e, std::min<int64_t>(hb::STREAM_BLOCK_ARCS, ch.e1 - e));
+          hb::codes::put_block<hb::STREAM_BLOCK_ARCS>(out, c->host_idx + e,
+                                                      std::min<int64_t>(hb::STREAM_BLOCK_ARCS, ch.e1 - e));
         }
         bo.push_back((uint32_t)out.size());
         if (out.size() > 0xfffff000u) too_big = true;
