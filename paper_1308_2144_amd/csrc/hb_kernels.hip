@@ -1275,12 +1275,17 @@ struct Tickets {
 
 __device__ __forceinline__ int64_t next_ticket(PassCtl* ctl) { return (int64_t)atomicAdd(&ctl->work, 1ull); }
 
-__device__ __forceinline__ Tickets pass_tickets(const PassArgs& A, int K) {
+// `single` items taken one per ticket, then the rest K per ticket.
+__device__ __forceinline__ Tickets tickets_of(int64_t single, int64_t total, int K) {
   Tickets t;
-  t.single = A.n_items + (A.n_medium + 3) / 4;
-  t.total = pass_items(A);
+  t.single = single;
+  t.total = total;
   t.count = t.single + (t.total - t.single + K - 1) / K;
   return t;
+}
+
+__device__ __forceinline__ Tickets pass_tickets(const PassArgs& A, int K) {
+  return tickets_of(A.n_items + (A.n_medium + 3) / 4, pass_items(A), K);
 }
 
 // Items [*b0, *b1) of ticket k.
@@ -1493,20 +1498,6 @@ __device__ __forceinline__ void fold_codes(const PassArgs& A, uint32_t* regs, in
   }
 }
 
-// As preload, with the own counter taken from its code.
-template <int B>
-__device__ __forceinline__ RowPre preload_code(const PassArgs& A, int64_t row, int gl, GraphKey key) {
-  RowPre r;
-  r.own = code_slice(singleton_code<B>((uint64_t)(row - key.base), key.seed), gl);
-  r.e = r.s = r.h = r.dd = 0.0;
-  if (gl == 0) {
-    r.e = ld_stream(A.E + row);
-    r.s = ld_stream(A.S + row);
-    r.h = ld_stream(A.H + row);
-  }
-  return r;
-}
-
 // Light rows of a first pass, 64 list entries per wavefront, W rows at a
 // time (one per lane group): the group folds its row's successor codes into
 // an LDS register array, packs it and finishes the row in two steps
@@ -1570,34 +1561,76 @@ __device__ __forceinline__ void light_codes_1(const PassArgs& A, uint32_t* lds, 
   flush_counts(A, c, lw, lane);
 }
 
-// One medium row per wavefront: all 64 lanes fold its arcs.
+// Medium rows of a first pass, R to a wavefront (R = 8, or 4 for p = 256):
+// all 64 lanes fold each row's successor codes in turn into that row's own
+// LDS register array, then the rows' lane groups pack and finish them
+// together in two steps (finish_group, finish_lane), so that the per-row work
+// runs once per R rows instead of once per row.
+template <int B>
+__host__ __device__ constexpr int codes_med_rows() {
+  return (1024 >> B) < 8 ? (1024 >> B) : 8;
+}
+
 template <int B, bool MG>
-__device__ __forceinline__ void medium_codes(const PassArgs& A, uint32_t* lds, int64_t mi, int lane) {
-  constexpr int G = (1 << B) / 16;
+__device__ __forceinline__ void medium_codes(const PassArgs& A, uint32_t* lds, RowSum* sums, int64_t mw, int lane) {
+  constexpr int P = 1 << B;
+  constexpr int G = P / 16;
+  constexpr int R = codes_med_rows<B>();
   const int gl = lane % G;
   const int grp = lane / G;
-  const int64_t row = A.medium[mi];
-  bool own_mod, need;
-  row_flags<MG>(A, row, own_mod, need);
-  Counts c{};
-  if (need) {  // uniform over the wavefront
-    const int64_t s = A.off[row];
-    const int64_t deg = A.off[row + 1] - s;
-    const GraphKey key = key_of<MG>(A, row);
-    RowPre pre;
-    if (grp == 0) pre = preload_code<B>(A, row, gl, key);
-    fold_codes<B>(A, lds, s + lane, s + deg, 64, key);
-    wave_sync();
-    if (grp == 0) {
-      const uint4 acc = take_slice(lds, gl);
-      if (gl == 0) {
-        c.gath += (uint32_t)deg;
-        c.arcs += (uint32_t)deg;
-      }
-      (void)finish_row<B, MG>(A, row, acc, deg > 0, pre, false, gl, 0, c);
+  const int64_t i = mw * R + lane;
+  int64_t row = 0, s = 0, deg = 0;
+  bool own_mod = false, need = false;
+  uint32_t code = 0u;
+  GraphKey key{0, A.seed};
+  double e0 = 0.0, s0 = 0.0, h0 = 0.0;
+  if (lane < R && i < A.n_medium) {
+    row = A.medium[i];
+    s = A.off[row];
+    deg = A.off[row + 1] - s;
+    row_flags<MG>(A, row, own_mod, need);
+    if (need) {
+      key = key_of<MG>(A, row);
+      e0 = ld_stream(A.E + row);
+      s0 = ld_stream(A.S + row);
+      h0 = ld_stream(A.H + row);
+      code = singleton_code<B>((uint64_t)(row - key.base), key.seed);
     }
   }
-  flush_counts(A, c, mi, lane);
+  const uint64_t live = __ballot(need);
+  Counts c{};
+  for (int r = 0; r < R; ++r) {
+    const int64_t rs = __shfl(s, r);
+    const int64_t rd = __shfl(deg, r);
+    GraphKey rkey{0, A.seed};
+    if constexpr (MG) {
+      rkey.base = __shfl(key.base, r);
+      rkey.seed = __shfl(key.seed, r);
+    }
+    if (((live >> r) & 1ull) == 0ull) continue;  // uniform
+    fold_codes<B>(A, lds + r * P, rs + lane, rs + rd, 64, rkey);
+    if (lane == 0) {
+      c.gath += (uint32_t)rd;
+      c.arcs += (uint32_t)rd;
+    }
+  }
+  wave_sync();
+  const int64_t grow = __shfl(row, grp);
+  const int64_t gdeg = __shfl(deg, grp);
+  const uint32_t gcode = __shfl(code, grp);
+  if (grp < R && ((live >> grp) & 1ull) != 0ull) {
+    const uint4 acc = take_slice(lds + grp * P, gl);
+    finish_group<B>(A, grow, acc, gdeg > 0, code_slice(gcode, gl), false, gl, grp, sums + grp);
+  }
+  wave_sync();
+  finish_lane<B, MG>(A, row, need, false, sums, lane, e0, s0, h0, c);
+  flush_counts(A, c, mw, lane);
+}
+
+// Work items of a first pass: [heavy chunks][medium: 4 R rows each][light: 256 rows each].
+template <int B>
+__host__ __device__ constexpr int64_t codes_items(int64_t n_items, int64_t n_medium, int64_t n_light) {
+  return n_items + (n_medium + 4 * codes_med_rows<B>() - 1) / (4 * codes_med_rows<B>()) + (n_light + 255) / 256;
 }
 
 // One chunk of a heavy row per workgroup: its four wavefronts fold into one
@@ -1625,7 +1658,7 @@ __device__ __forceinline__ void heavy_codes(const PassArgs& A, uint32_t* lds, in
     *reinterpret_cast<uint4*>(A.partial + (size_t)item * P + (size_t)gl * 16) = take_slice(lds, gl);
 }
 
-// One work item, numbered as in expand_item: [heavy chunks][medium rows][light rows].
+// One work item, numbered as codes_items counts them.
 template <int B, bool MG>
 __device__ __forceinline__ void codes_item(const PassArgs& A, uint32_t (*regs)[CODE_WORDS], RowSum (*sums)[64],
                                            int64_t b, int lane, int wave) {
@@ -1636,10 +1669,11 @@ __device__ __forceinline__ void codes_item(const PassArgs& A, uint32_t (*regs)[C
     return;
   }
   b -= A.n_items;
-  const int64_t med_wgs = (A.n_medium + 3) / 4;
+  constexpr int R = codes_med_rows<B>();
+  const int64_t med_wgs = (A.n_medium + 4 * R - 1) / (4 * R);
   if (b < med_wgs) {
-    const int64_t mi = b * 4 + wave;
-    if (mi < A.n_medium) medium_codes<B, MG>(A, regs[wave], mi, lane);
+    const int64_t mw = b * 4 + wave;
+    if (mw * R < A.n_medium) medium_codes<B, MG>(A, regs[wave], sums[wave], mw, lane);
     return;
   }
   b -= med_wgs;
@@ -1671,7 +1705,8 @@ __global__ HB_PERSIST_ATTR void k_expand_codes_p(PassArgs A0) {
   for (int i = threadIdx.x; i < CODE_WORDS; i += 256) z[i] = zero4();
   // no counter gathers, so no L2 window to keep narrow: batch when there are enough items
   const int K = (A.n_light + 255) / 256 >= 64 * (int64_t)gridDim.x ? 8 : 1;
-  const Tickets tk = pass_tickets(A, K);
+  const int64_t total = codes_items<B>(A.n_items, A.n_medium, A.n_light);
+  const Tickets tk = tickets_of(total - (A.n_light + 255) / 256, total, K);
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) ticket = next_ticket(A0.ctl);
@@ -2860,18 +2895,20 @@ hipError_t launch_lanes(int log2m, const PassArgs& a, hipStream_t s, hipEvent_t 
 
 // First pass from node hashes: the codes kernel, then the plain merge of heavy
 // rows.
+template <int B>
+void launch_codes_b(const PassArgs& a, hipStream_t s) {
+  const int64_t grid = codes_items<B>(a.n_items, a.n_medium, a.n_light);
+  if (grid > 0) hipLaunchKernelGGL(k_expand_codes<B>, dim3((unsigned)grid), dim3(256), 0, s, a);
+}
+
 hipError_t launch_codes(int log2m, const PassArgs& a, hipStream_t s, hipEvent_t ev_mid) {
-  const int64_t grid = a.n_items + (a.n_medium + 3) / 4 + (a.n_light + 255) / 256;
-  if (grid > 0) {
-    const dim3 g((unsigned)grid), t(256);
-    switch (log2m) {
-      case 4: hipLaunchKernelGGL(k_expand_codes<4>, g, t, 0, s, a); break;
-      case 5: hipLaunchKernelGGL(k_expand_codes<5>, g, t, 0, s, a); break;
-      case 6: hipLaunchKernelGGL(k_expand_codes<6>, g, t, 0, s, a); break;
-      case 7: hipLaunchKernelGGL(k_expand_codes<7>, g, t, 0, s, a); break;
-      case 8: hipLaunchKernelGGL(k_expand_codes<8>, g, t, 0, s, a); break;
-      default: return hipErrorInvalidValue;
-    }
+  switch (log2m) {
+    case 4: launch_codes_b<4>(a, s); break;
+    case 5: launch_codes_b<5>(a, s); break;
+    case 6: launch_codes_b<6>(a, s); break;
+    case 7: launch_codes_b<7>(a, s); break;
+    case 8: launch_codes_b<8>(a, s); break;
+    default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
