@@ -1141,6 +1141,81 @@ __device__ __forceinline__ void light_wave(const PassArgs& A, QEnt* qw, RowSum* 
   flush_counts<FL>(A, c, lw, lane);
 }
 
+// Medium rows per wavefront where their finish is batched (first passes, and
+// the queued passes of plain single-graph contexts): one per lane group, at
+// most 8.
+__host__ __device__ constexpr int batched_med_rows(int B) { return (1024 >> B) < 8 ? (1024 >> B) : 8; }
+
+template <int B, bool Q, bool MG, int FL>
+__host__ __device__ constexpr int med_rows_per_wave() {
+  return Q && !MG && FL == FL_PLAIN ? batched_med_rows(B) : 1;
+}
+
+// Medium rows of a plain single-graph queued pass, R to a wavefront: the
+// whole wavefront gathers each row's changed successors in turn (as
+// medium_wave does), lane group r keeps row r's maximum, and the R rows are
+// finished together in two steps (finish_group, finish_lane).  The rows' list
+// entries and offsets are loaded once for all R rows, and their own counters
+// and accumulators after all the gathers, in one round trip.
+template <int B>
+__device__ __forceinline__ void medium_rows_q(const PassArgs& A, QEnt* qw, RowSum* sums, int64_t mw, int lane) {
+  constexpr int P = 1 << B;
+  constexpr int G = P / 16;
+  constexpr int R = batched_med_rows(B);
+  const int gl = lane % G;
+  const int grp = lane / G;
+  const int64_t i = mw * R + lane;
+  int64_t row = 0, s = 0, deg = 0;
+  bool own_mod = false, need = false;
+  if (lane < R && i < A.n_medium) {
+    row = A.medium[i];
+    s = A.off[row];
+    deg = A.off[row + 1] - s;
+    row_flags<false>(A, row, own_mod, need);
+  }
+  const uint64_t live = __ballot(need);
+  Counts c{};
+  uint4 mine = zero4();
+  bool mine_got = false;
+#pragma unroll 1
+  for (int r = 0; r < R; ++r) {
+    if (((live >> r) & 1ull) == 0ull) continue;  // uniform
+    const int64_t rrow = __shfl(row, r);
+    const int64_t rs = __shfl(s, r);
+    const int64_t rd = __shfl(deg, r);
+    bool got = false;
+    uint4 acc = gather_wave_q<B>(A, qw, rs, rs + rd, lane, gl, grp, lanes_below(lane), rrow, got, c);
+    if (lane == 0) c.arcs += (uint32_t)rd;
+#pragma unroll
+    for (int o = G; o < 64; o <<= 1) acc = bmax(acc, shfl_xor4(acc, o));
+    got = __ballot(got) != 0ull;
+    if (grp == r) {
+      mine = acc;
+      mine_got = got;
+    }
+  }
+  // As in medium_wave, a lazy row (see light_wave) that found no changed
+  // successor is left as it is.
+  const bool got_r = __shfl((int)mine_got, (lane % R) * G) != 0;
+  const bool done = need && (!lazy_row<true>(A, own_mod) || got_r);
+  double e0 = 0.0, s0 = 0.0, h0 = 0.0;
+  if (done) {
+    e0 = ld_stream(A.E + row);
+    s0 = ld_stream(A.S + row);
+    h0 = ld_stream(A.H + row);
+  }
+  const int64_t grow = __shfl(row, grp % R);
+  const bool gmod = __shfl((int)own_mod, grp % R) != 0;
+  const bool gdone = __shfl((int)done, grp % R) != 0 && grp < R;
+  if (gdone) {
+    const uint4 own = ld_stream(reinterpret_cast<const uint4*>(A.cur + (size_t)grow * P + (size_t)gl * 16));
+    finish_group<B>(A, grow, mine, mine_got, own, gmod, gl, grp, sums + grp);
+  }
+  wave_sync();
+  finish_lane<B, false>(A, row, done, own_mod, sums, lane, e0, s0, h0, c);
+  flush_counts(A, c, mw, lane);
+}
+
 // One medium row per wavefront: the groups share its arcs and reduce their
 // partial maxima by shuffles.
 template <int B, bool Q, bool MG, int FL = FL_PLAIN>
@@ -1216,10 +1291,10 @@ __device__ __forceinline__ void heavy_chunk(const PassArgs& A, QEnt* qw, int64_t
   }
 }
 
-// Work items of a pass, one per workgroup: [heavy chunks][medium rows, 4
-// per workgroup][light rows, 256 per workgroup].  Q selects the queued
-// gather (slice, edge and sparse passes, or dense passes on request) over
-// the direct one.
+// Work items of a pass, one per workgroup: [heavy chunks][medium rows, 4 R
+// per workgroup (R = med_rows_per_wave)][light rows, 256 per workgroup].  Q
+// selects the queued gather (slice, edge and sparse passes, or dense passes
+// on request) over the direct one.
 template <int B, bool Q, bool MG, int FL = FL_PLAIN>
 __device__ __forceinline__ void expand_item(const PassArgs& A, QEnt* qw, RowSum* sums, int64_t b) {
   const int lane = threadIdx.x & 63;
@@ -1231,10 +1306,15 @@ __device__ __forceinline__ void expand_item(const PassArgs& A, QEnt* qw, RowSum*
     return;
   }
   b -= A.n_items;
-  const int64_t med_wgs = (A.n_medium + 3) / 4;
+  constexpr int R = med_rows_per_wave<B, Q, MG, FL>();
+  const int64_t med_wgs = (A.n_medium + 4 * R - 1) / (4 * R);
   if (b < med_wgs) {
-    const int64_t mi = b * 4 + wave;
-    if (mi < A.n_medium) medium_wave<B, Q, MG, FL>(A, qw, mi, lane);
+    const int64_t mw = b * 4 + wave;
+    if constexpr (R > 1) {
+      if (mw * R < A.n_medium) medium_rows_q<B>(A, qw, sums, mw, lane);
+    } else {
+      if (mw < A.n_medium) medium_wave<B, Q, MG, FL>(A, qw, mw, lane);
+    }
     return;
   }
   b -= med_wgs;
@@ -1242,6 +1322,7 @@ __device__ __forceinline__ void expand_item(const PassArgs& A, QEnt* qw, RowSum*
   if (lw * 64 < A.n_light) light_wave<B, Q, MG, FL>(A, qw, sums, lw, lane);
 }
 
+// Items of a multi-graph pass (R = 1).
 __device__ __forceinline__ int64_t pass_items(const PassArgs& A) {
   return A.n_items + (A.n_medium + 3) / 4 + (A.n_light + 255) / 256;
 }
@@ -1561,21 +1642,17 @@ __device__ __forceinline__ void light_codes_1(const PassArgs& A, uint32_t* lds, 
   flush_counts(A, c, lw, lane);
 }
 
-// Medium rows of a first pass, R to a wavefront (R = 8, or 4 for p = 256):
+// Medium rows of a first pass, R to a wavefront (R = batched_med_rows(B)):
 // all 64 lanes fold each row's successor codes in turn into that row's own
 // LDS register array, then the rows' lane groups pack and finish them
 // together in two steps (finish_group, finish_lane), so that the per-row work
 // runs once per R rows instead of once per row.
-template <int B>
-__host__ __device__ constexpr int codes_med_rows() {
-  return (1024 >> B) < 8 ? (1024 >> B) : 8;
-}
 
 template <int B, bool MG>
 __device__ __forceinline__ void medium_codes(const PassArgs& A, uint32_t* lds, RowSum* sums, int64_t mw, int lane) {
   constexpr int P = 1 << B;
   constexpr int G = P / 16;
-  constexpr int R = codes_med_rows<B>();
+  constexpr int R = batched_med_rows(B);
   const int gl = lane % G;
   const int grp = lane / G;
   const int64_t i = mw * R + lane;
@@ -1599,6 +1676,7 @@ __device__ __forceinline__ void medium_codes(const PassArgs& A, uint32_t* lds, R
   }
   const uint64_t live = __ballot(need);
   Counts c{};
+#pragma unroll 1
   for (int r = 0; r < R; ++r) {
     const int64_t rs = __shfl(s, r);
     const int64_t rd = __shfl(deg, r);
@@ -1630,7 +1708,7 @@ __device__ __forceinline__ void medium_codes(const PassArgs& A, uint32_t* lds, R
 // Work items of a first pass: [heavy chunks][medium: 4 R rows each][light: 256 rows each].
 template <int B>
 __host__ __device__ constexpr int64_t codes_items(int64_t n_items, int64_t n_medium, int64_t n_light) {
-  return n_items + (n_medium + 4 * codes_med_rows<B>() - 1) / (4 * codes_med_rows<B>()) + (n_light + 255) / 256;
+  return n_items + (n_medium + 4 * batched_med_rows(B) - 1) / (4 * batched_med_rows(B)) + (n_light + 255) / 256;
 }
 
 // One chunk of a heavy row per workgroup: its four wavefronts fold into one
@@ -1669,7 +1747,7 @@ __device__ __forceinline__ void codes_item(const PassArgs& A, uint32_t (*regs)[C
     return;
   }
   b -= A.n_items;
-  constexpr int R = codes_med_rows<B>();
+  constexpr int R = batched_med_rows(B);
   const int64_t med_wgs = (A.n_medium + 4 * R - 1) / (4 * R);
   if (b < med_wgs) {
     const int64_t mw = b * 4 + wave;
@@ -2856,8 +2934,9 @@ hipError_t launch_ensemble_summary(int64_t n, int k, int which, const double* S,
 // Expand and merge kernels of one lane-group pass for flavour FL.
 template <int FL>
 hipError_t launch_lanes(int log2m, const PassArgs& a, hipStream_t s, hipEvent_t ev_mid) {
-  const int64_t grid = a.n_items + (a.n_medium + 3) / 4 + (a.n_light + 255) / 256;
   const bool q = !(a.mode == MODE_FIRST || a.mode == MODE_DENSE) || a.qdense;
+  const int64_t R = q && FL == FL_PLAIN ? batched_med_rows(log2m) : 1;  // med_rows_per_wave
+  const int64_t grid = a.n_items + (a.n_medium + 4 * R - 1) / (4 * R) + (a.n_light + 255) / 256;
   if (grid > 0) {
     const dim3 g((unsigned)grid), t(256);
     switch (log2m * 2 + (q ? 1 : 0)) {
