@@ -237,6 +237,35 @@ def test_pass_counters():
     assert sparse["pass_stats"][-1]["rows_loaded"] < nonempty
 
 
+def _k_medium_graph(n, k, seed):
+    """n nodes; k rows of 2-40 successors (the medium rows when light_max is
+    1), every other row 0 or 1 successor, all successors uniform."""
+    rng = np.random.default_rng(seed)
+    deg = rng.integers(0, 2, size=n)
+    deg[rng.choice(n, size=k, replace=False)] = rng.integers(2, 41, size=k)
+    off = np.zeros(n + 1, dtype=np.int64)
+    off[1:] = np.cumsum(deg)
+    idx = rng.integers(0, n, size=int(off[-1])).astype(np.int32)
+    return off, idx
+
+
+@pytest.mark.parametrize("k", [1, 3, 8, 9, 33])
+def test_medium_rows_finished_together(k):
+    """Medium rows are taken several to a wavefront (8, or 4 at p = 256) in
+    first passes and in the queued passes of plain single-graph contexts, and
+    finished together.  Ragged counts of medium rows, rows that skip a pass
+    (sparse passes) and rows that keep their counter (lazy rows of edge
+    passes), for every register count, in every pass mode: equal to the
+    oracle."""
+    off, idx = _k_medium_graph(400, k, 60 + k)
+    for b in (4, 5, 6, 7, 8):
+        for opts in (dict(), dict(dense_pct=0), dict(dense_pct=101, sparse_pct=0),
+                     dict(dense_pct=101, sparse_pct=0, slice=1), dict(dense_pct=101, sparse_pct=101, pairs=0)):
+            _log("k", k, "b", b, opts)
+            got, _ = check(off, idx, b, 40 + b, f"k{k}/b{b}/{opts}", light_max=1, heavy_min=100000, **opts)
+            assert got["pass_stats"][0]["mode"] == 0
+
+
 @pytest.mark.parametrize("b", [4, 5, 6, 7, 8])
 @pytest.mark.parametrize("opts", [dict(), dict(light_max=2, heavy_min=6, chunk=3),
                                   dict(light_max=1, heavy_min=100000), dict(light_max=4, heavy_min=40, chunk=17)])
