@@ -818,10 +818,12 @@ def main():
     scanned = 0
     per_kernel = {}  # kernel name -> [ms, algorithmic bytes, launches]
     first = None
+    step_pass_ms = []  # per timed step: device time of each pass (push + expand + merge), ms
     for k in range(args.steps):
         passes = step()
         step_passes.append(passes)
         infos = [g.pass_stats(t) for t in range(passes)]
+        step_pass_ms.append([ps["push_ms"] + ps["expand_ms"] + ps["merge_ms"] for ps in infos])
         scanned += sum(ps["arcs_scanned"] for ps in infos)
         for ps in infos:
             kname = kernel_of(ps, w["log2m"])
@@ -874,6 +876,12 @@ def main():
         "first_pass": {"ms": p0["expand_ms"] + p0["merge_ms"],
                        "edge_visits_per_s": m / ((p0["expand_ms"] + p0["merge_ms"]) * 1e-3),
                        "GBps": pass_bytes(p0, listed, p) / (p0["expand_ms"] * 1e6)},
+        # Timing protocol: each pass's device time and the sum over a run's
+        # passes, medians over the timed steps (every step runs the same passes).
+        "pass_ms_median": [round(float(np.median([sp[t] for sp in step_pass_ms])), 4)
+                           for t in range(min(len(sp) for sp in step_pass_ms))] if step_pass_ms else [],
+        "passes_ms_median_of_run": round(float(np.median([sum(sp) for sp in step_pass_ms])), 4)
+                                   if step_pass_ms else None,
         "nominal_edge_visits_per_s": nominal / dt,
         "arcs_scanned_per_step": scanned // args.steps,
         "roofline": roof,
