@@ -1541,7 +1541,7 @@ __device__ __forceinline__ uint4 take_slice(uint32_t* regs, int gl) {
 // ids in flight.  The hash is the costly part (two 64-bit products), so a
 // slot no lane of the wavefront has is branched over, not computed and
 // discarded (light rows have only a few arcs per lane).
-constexpr int UC = 4;
+constexpr int UC = 8;
 
 // Hash key of a row's graph: arena base and hash seed (multi-graph contexts
 // number nodes within their graph; every arc stays inside it, so a row's
