@@ -78,6 +78,17 @@ def test_batch_row_paths_and_modes(opts):
     compare_batch(graphs, 5, seeds, **opts)
 
 
+@pytest.mark.parametrize("b", [4, 6, 8])
+def test_batch_medium_rows_of_many_graphs(b):
+    """Every row with 2+ arcs a medium row: first passes take several medium
+    rows to a wavefront (8, or 4 at p = 256), rows of different graphs among
+    them, each hashed with its own graph's seed and node numbering."""
+    graphs = mixed_graphs(13, count=12)
+    seeds = np.arange(len(graphs), dtype=np.uint64) * 3 + 11
+    _log("medium rows, b", b)
+    compare_batch(graphs, b, seeds, light_max=1, heavy_min=100000)
+
+
 def test_batch_partial_runs_and_reset():
     import paper_1308_2144_amd as hb
 
